@@ -1,0 +1,220 @@
+"""Plain CPU FP64 oracle of the MacCormack-TVD compressible-convection step.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package; the product path
+never does.  It shares no code with the GPU library: the C source here
+(``mtvd_oracle.c``) is compiled with gcc, ``-O2 -ffp-contract=off``, no
+fast-math, and loaded through ctypes.
+
+Paper: Tiwari, Sharma & Verma, arXiv:2411.10372, Sec. 2 (nondimensional
+equations, Nusselt numbers) and Sec. 3.1 (MacCormack-TVD scheme).
+
+Parity status of each function (what pins it is in ``tests/test_oracle_*``):
+  init, splitmix64  -- pinned (closed forms, published SplitMix64 outputs)
+  sweep x/y/z, step -- pinned (linear acoustics/viscous/thermal amplification
+                       in closed form, conservation, symmetries, hydrostatic
+                       convergence, second-order self-convergence)
+  TVD limiter form  -- parity unpinned beyond its properties (conservative,
+                       zero on linear data, no new extrema at a contact)
+  diag              -- pinned (conduction Nu = 1, closed-form sums)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field, fields
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mtvd_oracle.c")
+_LIB = os.path.join(_HERE, "libmtvd_oracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (OpenMP on, contraction off)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math",
+               "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wno-unused-function",
+               "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.run(cmd, check=True, cwd=_HERE)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("nz", ctypes.c_int32), ("aspect", ctypes.c_double),
+        ("gamma", ctypes.c_double), ("Pr", ctypes.c_double), ("Ra", ctypes.c_double),
+        ("eps", ctypes.c_double), ("D", ctypes.c_double), ("cfl", ctypes.c_double),
+        ("seed", ctypes.c_uint64), ("noise_amp", ctypes.c_double),
+        ("dt_mode", ctypes.c_int32), ("bulk_coef", ctypes.c_double),
+        ("limiter_form", ctypes.c_int32), ("sweep_order", ctypes.c_int32),
+        ("tvd_on", ctypes.c_int32), ("gravity_scale", ctypes.c_double),
+        ("wall_order", ctypes.c_int32), ("pred_dir", ctypes.c_int32), ("diffusion_scale", ctypes.c_double),
+        ("nthreads", ctypes.c_int32),
+    ]
+
+
+class _Diag(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in (
+        "mass", "kinetic", "total_energy", "nu_bottom", "nu_top", "nu_mean",
+        "nu_bulk", "nu_conv", "nu_kin")] + [("tmean", ctypes.c_double * 6)]
+
+
+@dataclass
+class Params:
+    """Problem parameters (defaults: the 256x64 2D case)."""
+    ndim: int = 2
+    nx: int = 256
+    ny: int = 1
+    nz: int = 64
+    aspect: float = 4.0
+    gamma: float = 1.4
+    Pr: float = 1.0
+    Ra: float = 1e6
+    eps: float = 0.1
+    D: float = 0.4
+    cfl: float = 0.5
+    seed: int = 0
+    noise_amp: float = 1e-3
+    dt_mode: int = 0
+    bulk_coef: float = -2.0 / 3.0
+    limiter_form: int = 0
+    sweep_order: int = 0
+    tvd_on: int = 1
+    gravity_scale: float = 1.0
+    wall_order: int = 2
+    pred_dir: int = 0
+    diffusion_scale: float = 1.0
+    nthreads: int = 0
+
+    def _c(self) -> _Params:
+        return _Params(**{f.name: getattr(self, f.name) for f in fields(self)})
+
+    @property
+    def nf(self) -> int:
+        return self.ndim + 2
+
+    @property
+    def shape(self):
+        ny = self.ny if self.ndim == 3 else 1
+        if self.ndim == 3:
+            return (self.nf, self.nz, ny, self.nx)
+        return (self.nf, self.nz, self.nx)
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER(_Params)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.ora_state_len.argtypes = [P]
+        L.ora_state_len.restype = ctypes.c_size_t
+        L.ora_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.ora_splitmix64.restype = ctypes.c_uint64
+        L.ora_init.argtypes = [P, dp]
+        L.ora_init_box.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_int, dp]
+        L.ora_dt.argtypes = [P, dp]
+        L.ora_dt.restype = ctypes.c_double
+        L.ora_sweep.argtypes = [P, ctypes.c_int, ctypes.c_double, dp, dp]
+        L.ora_sweep_box.argtypes = [P, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                    ctypes.c_int, dp, dp]
+        L.ora_step.argtypes = [P, dp, ctypes.c_int, dp, dp]
+        L.ora_diag.argtypes = [P, dp, ctypes.POINTER(_Diag)]
+        for fn in ("ora_init", "ora_init_box", "ora_sweep", "ora_sweep_box",
+                   "ora_step", "ora_diag"):
+            getattr(L, fn).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ok(rc: int, what: str):
+    if rc != 0:
+        raise ValueError(f"oracle {what} rejected its arguments (rc={rc})")
+
+
+def splitmix64(seed: int, n: int) -> int:
+    return int(lib().ora_splitmix64(seed, n))
+
+
+def init(p: Params) -> np.ndarray:
+    X = np.empty(p.shape, dtype=np.float64)
+    pc = p._c()
+    _ok(lib().ora_init(ctypes.byref(pc), _ptr(X)), "init")
+    return X
+
+
+def init_box(p: Params, i0: int, j0: int, bx: int, by: int = 1) -> np.ndarray:
+    if p.ndim == 2:
+        by = 1
+        B = np.empty((p.nf, p.nz, bx), dtype=np.float64)
+    else:
+        B = np.empty((p.nf, p.nz, by, bx), dtype=np.float64)
+    pc = p._c()
+    _ok(lib().ora_init_box(ctypes.byref(pc), i0, j0, bx, by, _ptr(B)), "init_box")
+    return B
+
+
+def dt(p: Params, X: np.ndarray) -> float:
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    pc = p._c()
+    return float(lib().ora_dt(ctypes.byref(pc), _ptr(X)))
+
+
+def sweep(p: Params, axis: int, tau: float, X: np.ndarray) -> np.ndarray:
+    """One directional operator L_axis(tau); axis 0 = x, 1 = y, 2 = z."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    Y = np.empty_like(X)
+    pc = p._c()
+    _ok(lib().ora_sweep(ctypes.byref(pc), axis, tau, _ptr(X), _ptr(Y)), "sweep")
+    return Y
+
+
+def sweep_box(p: Params, axis: int, tau: float, B: np.ndarray) -> np.ndarray:
+    """L_axis(tau) on a box with a two-column halo in x (and y in 3D).
+    Only the non-halo columns of the result are meaningful."""
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    out = np.zeros_like(B)
+    bx = B.shape[-1]
+    by = B.shape[-2] if p.ndim == 3 else 1
+    pc = p._c()
+    _ok(lib().ora_sweep_box(ctypes.byref(pc), axis, tau, bx, by, _ptr(B), _ptr(out)),
+        "sweep_box")
+    return out
+
+
+def step(p: Params, X: np.ndarray, nsteps: int, time: float = 0.0,
+         dt_frozen: float = 0.0):
+    """Advance X by nsteps full steps.  Returns (X, time, last_dt)."""
+    X = np.array(X, dtype=np.float64, order="C", copy=True)
+    t = ctypes.c_double(time)
+    d = ctypes.c_double(dt_frozen)
+    pc = p._c()
+    _ok(lib().ora_step(ctypes.byref(pc), _ptr(X), nsteps, ctypes.byref(t),
+                       ctypes.byref(d)), "step")
+    return X, t.value, d.value
+
+
+def diag(p: Params, X: np.ndarray) -> dict:
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    d = _Diag()
+    pc = p._c()
+    _ok(lib().ora_diag(ctypes.byref(pc), _ptr(X), ctypes.byref(d)), "diag")
+    out = {n: getattr(d, n) for n, _ in _Diag._fields_ if n != "tmean"}
+    out["tmean"] = list(d.tmean)
+    return out

@@ -1,0 +1,615 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these compare the oracle with itself through a retyped formula: each
+checks a closed form, an exact invariant, a symmetry or a convergence rate
+that a plausible mistake in the oracle (a dropped term, a wrong sign, a wrong
+index or derivative direction, a transposed operand) would break.
+
+Paper: Tiwari, Sharma & Verma, arXiv:2411.10372; Sec. 2 (equations, Nu),
+Sec. 3.1 (scheme).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import Params
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------
+# helpers
+
+
+def cv_of(p):
+    """c_v in E = rho(u^2/2 + cv T + z/eps) (Sec. 2, definition of E)."""
+    return 1.0 / (p.gamma * p.eps * p.D)
+
+
+def uniform_state(p, rho0, u0, T0):
+    """A state with uniform rho, velocity u0 = (ux, [uy], uz) and T, gravity
+    off (E carries no potential energy)."""
+    assert p.gravity_scale == 0.0
+    X = np.empty(p.shape)
+    q2 = float(np.dot(u0, u0))
+    X[0] = rho0
+    for a, ua in enumerate(u0):
+        X[1 + a] = rho0 * ua
+    X[-1] = rho0 * (cv_of(p) * T0 + 0.5 * q2)
+    return X
+
+
+def euler_jacobian(nd, gamma, u, H, al):
+    """Flux Jacobian dF_al/dX of the inviscid flux for X = (rho, m_1..m_nd, E)
+    at velocity u (length nd) and total enthalpy H, from p = (gamma-1)(E -
+    |m|^2/(2 rho)); the textbook form (e.g. Toro, Riemann Solvers, ch. 3)."""
+    nf = nd + 2
+    A = np.zeros((nf, nf))
+    q2 = float(np.dot(u, u))
+    g1 = gamma - 1.0
+    A[0, 1 + al] = 1.0
+    for g in range(nd):
+        r = 1 + g
+        A[r, 0] = -u[g] * u[al] + (0.5 * g1 * q2 if g == al else 0.0)
+        for b in range(nd):
+            A[r, 1 + b] = (u[al] if g == b else 0.0) + (u[g] if b == al else 0.0) \
+                - (g1 * u[b] if g == al else 0.0)
+        A[r, nf - 1] = g1 if g == al else 0.0
+    A[nf - 1, 0] = u[al] * (0.5 * g1 * q2 - H)
+    for b in range(nd):
+        A[nf - 1, 1 + b] = (H if b == al else 0.0) - g1 * u[al] * u[b]
+    A[nf - 1, nf - 1] = gamma * u[al]
+    return A
+
+
+def viscous_symbol(nd, p, rho0, u0, E0, al, dsym):
+    """Linearised viscous + conductive part of F_al about a uniform state, as
+    a matrix acting on the Fourier amplitude of dX.  dsym[b] is the symbol of
+    the difference operator used for d/dx_b (inner one along al, central
+    across).  Derived by hand from tau_ij = mu(d_j u_i + d_i u_j + lam d_m u_m
+    delta_ij) and the energy flux -K dT/dx_al - u_b tau_{b al} (Sec. 2)."""
+    nf = nd + 2
+    mu = np.sqrt(p.Pr / p.Ra) * p.diffusion_scale
+    K = 1.0 / (p.eps * p.D * np.sqrt(p.Ra * p.Pr)) * p.diffusion_scale
+    lam = p.bulk_coef
+    cv = cv_of(p)
+    # d(u_g)/dX and dT/dX about the uniform state
+    du = np.zeros((nd, nf))
+    for g in range(nd):
+        du[g, 0] = -u0[g] / rho0
+        du[g, 1 + g] = 1.0 / rho0
+    dT = np.zeros(nf)
+    dT[0] = -E0 / rho0**2
+    dT[nf - 1] = 1.0 / rho0
+    for g in range(nd):
+        dT -= u0[g] * du[g]
+    dT = dT / cv
+    # tau_{g al} as a matrix on dX
+    div = sum(dsym[m] * du[m] for m in range(nd))
+    tau = np.zeros((nd, nf), dtype=complex)
+    for g in range(nd):
+        tau[g] = mu * (dsym[al] * du[g] + dsym[g] * du[al])
+        if g == al:
+            tau[g] = tau[g] + mu * lam * div
+    Fv = np.zeros((nf, nf), dtype=complex)
+    for g in range(nd):
+        Fv[1 + g] = -tau[g]
+    Fv[nf - 1] = -K * dsym[al] * dT - sum(u0[g] * tau[g] for g in range(nd))
+    return Fv
+
+
+def maccormack_symbol(p, nd, rho0, u0, T0, al, theta, h, tau):
+    """Amplification matrix of one L_al(tau) for the linearised equations and
+    the Fourier mode exp(i sum_b theta_b n_b): predictor with backward flux
+    differences and forward inner derivatives, corrector with forward flux
+    differences and backward inner derivatives, then the average (the
+    MacCormack structure of Sec. 3.1; TVD off)."""
+    nf = nd + 2
+    cv = cv_of(p)
+    q2 = float(np.dot(u0, u0))
+    E0 = rho0 * (cv * T0 + 0.5 * q2)
+    pr = (p.gamma - 1.0) * (E0 - 0.5 * rho0 * q2)
+    H = (E0 + pr) / rho0
+    A = euler_jacobian(nd, p.gamma, np.asarray(u0, float), H, al)
+    cen = [1j * np.sin(theta[b]) / h[b] for b in range(nd)]
+    fwd = list(cen)
+    bwd = list(cen)
+    fwd[al] = (np.exp(1j * theta[al]) - 1.0) / h[al]
+    bwd[al] = (1.0 - np.exp(-1j * theta[al])) / h[al]
+    Fp = A + viscous_symbol(nd, p, rho0, u0, E0, al, fwd)
+    Fc = A + viscous_symbol(nd, p, rho0, u0, E0, al, bwd)
+    I = np.eye(nf)
+    lam = tau / h[al]
+    P = I - lam * (1.0 - np.exp(-1j * theta[al])) * Fp
+    Q = lam * (np.exp(1j * theta[al]) - 1.0) * Fc
+    return 0.5 * (P + I - Q @ P)
+
+
+def _mode_field(p, theta, v):
+    """Re(v_f exp(i(theta_x i + theta_y j + theta_z k))) on the grid."""
+    k = np.arange(p.nz)[:, None, None]
+    j = np.arange(p.ny if p.ndim == 3 else 1)[None, :, None]
+    i = np.arange(p.nx)[None, None, :]
+    if p.ndim == 3:
+        ph = theta[0] * i + theta[1] * j + theta[2] * k
+    else:
+        ph = theta[0] * i + theta[1] * k + 0 * j
+    e = np.exp(1j * ph)
+    out = np.stack([np.real(vf * e) for vf in v])
+    return out if p.ndim == 3 else out[:, :, 0, :]
+
+
+# --------------------------------------------------------------------------
+# SplitMix64 and the initial state
+
+
+def test_splitmix64_published_outputs(ora):
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "splitmix64_seed0.txt"))
+            if l.strip() and not l.startswith("#")]
+    for n, hexv in rows:
+        assert ora.splitmix64(0, int(n)) == int(hexv, 16)
+
+
+def test_initial_profiles_closed_form(ora):
+    """T = 1-(eps+D)z, rho = T^(m-1), u = 0, noise bounded and zero-mean on
+    interior T, plates exact (Sec. 2: plate temperatures 1 and 1-eps-D)."""
+    p = Params(nx=64, nz=33, noise_amp=1e-3, seed=7)
+    X = ora.init(p)
+    cv = cv_of(p)
+    z = np.arange(p.nz) / (p.nz - 1)
+    Delta = p.eps + p.D
+    m = p.gamma * p.D / ((p.gamma - 1.0) * Delta)
+    rho_ref = (1.0 - Delta * z) ** (m - 1.0)
+    assert np.allclose(X[0], rho_ref[:, None], rtol=1e-15, atol=0)
+    assert np.all(X[1] == 0) and np.all(X[2] == 0)
+    T = (X[3] / X[0] - z[:, None] / p.eps) / cv
+    T0 = 1.0 - Delta * z
+    noise = T - T0[:, None]
+    assert np.max(np.abs(noise[[0, -1]])) < 1e-14          # plates untouched
+    assert abs(T0[-1] - (1.0 - p.eps - p.D)) < 1e-15
+    inner = noise[1:-1]
+    assert np.max(np.abs(inner)) <= 1e-3 * (1 + 1e-9)
+    assert np.min(np.abs(inner)) < 1e-5 and np.max(np.abs(inner)) > 0.99e-3
+    assert abs(np.mean(inner)) < 1e-3 * 4 / np.sqrt(inner.size)  # uniform, zero mean
+    # the noise is the published generator, draw n+1 for canonical index n
+    lin = 5 + p.nx * 3
+    U = (ora.splitmix64(p.seed, lin + 1) >> 11) * 2.0**-53
+    assert abs(noise[3, 5] - 1e-3 * (2 * U - 1)) < 1e-14
+
+
+def test_initial_state_is_hydrostatic_to_second_order(ora):
+    """p = a rho T with dp/dz = -rho/eps (Sec. 2 momentum equation at rest):
+    the centred residual of the sampled profile falls as dz^2."""
+    res = []
+    for nz in (17, 33, 65):
+        p = Params(nx=4, nz=nz, noise_amp=0.0)
+        X = ora.init(p)
+        z = np.arange(nz) / (nz - 1)
+        cv = cv_of(p)
+        T = (X[3, :, 0] / X[0, :, 0] - z / p.eps) / cv
+        pr = (p.gamma - 1) / (p.gamma * p.eps * p.D) * X[0, :, 0] * T
+        dz = 1.0 / (nz - 1)
+        r = (pr[2:] - pr[:-2]) / (2 * dz) + X[0, 1:-1, 0] / p.eps
+        res.append(np.max(np.abs(r)))
+    assert 3.6 < res[0] / res[1] < 4.4 and 3.6 < res[1] / res[2] < 4.4
+
+
+# --------------------------------------------------------------------------
+# diagnostics
+
+
+def test_conduction_gives_nu_one(ora):
+    """A conductive state has Nu_{z=0,1} = 1 and bulk Nu = 1 (Sec. 2,
+    volume_Nu and mean_Nu: T_sa = -eps z is linear)."""
+    for ndim in (2, 3):
+        p = Params(ndim=ndim, nx=16, ny=8 if ndim == 3 else 1, nz=17, noise_amp=0.0)
+        d = ora.diag(p, ora.init(p))
+        for k in ("nu_bottom", "nu_top", "nu_mean", "nu_bulk"):
+            assert abs(d[k] - 1.0) < 1e-12, (k, d[k])
+        assert d["nu_conv"] == 0.0 and d["nu_kin"] == 0.0 and d["kinetic"] == 0.0
+
+
+def test_diag_sums_closed_form(ora):
+    """Mass and energy integrals of a state whose integrals are known exactly
+    under the trapezoid rule in z (rho linear in z, uniform E)."""
+    p = Params(nx=8, nz=9, gravity_scale=0.0, noise_amp=0.0)
+    X = np.zeros(p.shape)
+    z = np.arange(p.nz) / (p.nz - 1)
+    X[0] = (1.0 + 0.5 * z)[:, None]          # integral over [0,1] = 1.25
+    X[1] = 0.3 * X[0]
+    X[3] = 20.0
+    d = ora.diag(p, X)
+    assert abs(d["mass"] - 1.25 * p.aspect) < 1e-13
+    assert abs(d["total_energy"] - 20.0 * p.aspect) < 1e-12
+    assert abs(d["kinetic"] - 0.5 * 0.09 * 1.25 * p.aspect) < 1e-14
+
+
+def test_nu_conv_and_nu_kin_closed_form(ora):
+    """Nu_conv = sqrt(Ra Pr)/eps <rho u_z T_sa>_V and Nu_K = D sqrt(Ra Pr)/2
+    <rho u_z u^2>_V (Sec. 2, volume_Nu) on a state where the integrands are
+    constant: rho = 1, u = (0, U), T = T_A(z) + c = 1 - D z + c."""
+    p = Params(nx=8, nz=9, noise_amp=0.0, Ra=1e6, Pr=0.7)
+    z = np.arange(p.nz) / (p.nz - 1)
+    U, cshift = 0.03, 0.02
+    X = np.zeros(p.shape)
+    X[0] = 1.0
+    X[2] = U
+    T = 1.0 - p.D * z + cshift
+    X[3] = (0.5 * U * U + cv_of(p) * T + z / p.eps)[:, None]
+    d = ora.diag(p, X)
+    s = np.sqrt(p.Ra * p.Pr)
+    assert abs(d["nu_conv"] - s / p.eps * U * cshift) < 1e-10 * s
+    assert abs(d["nu_kin"] - p.D * s / 2 * U**3) < 1e-12 * s
+    assert abs(d["nu_bulk"] - (1 + s / p.eps * U * cshift + p.D * s / 2 * U**3)) < 1e-9 * s
+
+
+@pytest.mark.parametrize("wall_order", [1, 2])
+def test_heating_rate_next_to_the_plates(ora, wall_order):
+    """Conduction only (u = 0, uniform p, gravity off) with a quadratic
+    T = 1 + b z + g z^2: the exact heating rate is dE/dt = K T'' = 2 K g.
+    As tau -> 0 one L_z(tau) changes E_k by tau times the average of the
+    predictor and corrector flux divergences.  The interior compact
+    differences give 2Kg exactly.  On the first node off each plate the
+    plate flux is evaluated at the plate itself when wall_order = 2 (exact
+    for a quadratic: -K T'(0)), while its partner flux sits half a cell
+    away, so that node heats at (5/4) 2Kg; wall_order = 1 gives 2Kg there
+    too."""
+    p = Params(nx=4, nz=17, noise_amp=0.0, gravity_scale=0.0, tvd_on=0, Ra=1e4,
+               wall_order=wall_order)
+    z = np.arange(p.nz) / (p.nz - 1)
+    g = 0.3
+    b = -0.5 - g                      # T(1) = 1 - eps - D = 0.5
+    T = 1 + b * z + g * z * z
+    a = (p.gamma - 1) / (p.gamma * p.eps * p.D)
+    p0 = 1.0
+    X = np.zeros(p.shape)
+    X[0] = (p0 / (a * T))[:, None]
+    X[3] = (p0 / (a * T) * cv_of(p) * T)[:, None]
+    tau = 1e-6
+    Y = ora.sweep(p, 2, tau, X)
+    rate = (Y[3, :, 0] - X[3, :, 0]) / tau
+    K = 1.0 / (p.eps * p.D * np.sqrt(p.Ra * p.Pr))
+    exact = 2 * K * g
+    assert np.max(np.abs(rate[2:-2] / exact - 1)) < 1e-3
+    edge = 1.25 if wall_order == 2 else 1.0
+    assert abs(rate[1] / exact - edge) < 1e-3 and abs(rate[-2] / exact - edge) < 1e-3
+
+
+# --------------------------------------------------------------------------
+# linearised scheme in closed form (all three directions, oblique modes)
+
+
+@pytest.mark.parametrize("ndim,al", [(2, 0), (2, 2), (3, 0), (3, 1), (3, 2)])
+@pytest.mark.parametrize("visc", [0.0, 1.0])
+def test_linear_amplification_matches_closed_form(ora, ndim, al, visc):
+    """One L_al(tau) on a small Fourier mode about a uniform moving state
+    equals the closed-form MacCormack amplification of the linearised
+    Navier-Stokes-Fourier equations.  With visc = 0 this is the Lax-Wendroff
+    symbol of the Euler equations (wave speeds u +- c, c = sqrt(gamma p/rho));
+    with visc = 1 it also fixes mu, lambda, K and the one-sided inner /
+    central cross derivative rule."""
+    rng = np.random.default_rng(100 + 10 * ndim + al + int(visc))
+    nzz = 24 if al == 2 else 9
+    p = Params(ndim=ndim, nx=32 if ndim == 2 else 16, ny=16 if ndim == 3 else 1,
+               nz=nzz, aspect=2.0, gravity_scale=0.0, tvd_on=0, noise_amp=0.0,
+               Ra=1e3, Pr=0.7, diffusion_scale=visc)
+    nd = 3 if ndim == 3 else 2
+    rho0, T0 = 1.2, 0.8
+    u0 = [0.3, -0.15, 0.2][:nd] if nd == 3 else [0.3, 0.2]
+    X0 = uniform_state(p, rho0, np.array(u0), T0)
+    h = [p.aspect / p.nx, p.aspect / p.ny, 1.0 / (p.nz - 1)] if nd == 3 else \
+        [p.aspect / p.nx, 1.0 / (p.nz - 1)]
+    th = [2 * np.pi * 3 / p.nx, 2 * np.pi * 2 / p.ny, 0.7] if nd == 3 else \
+        [2 * np.pi * 3 / p.nx, 0.7]
+    v = rng.normal(size=nd + 2) + 1j * rng.normal(size=nd + 2)
+    amp = 1e-7
+    X = X0 + amp * _mode_field(p, th, v)
+    c = np.sqrt(p.gamma * (p.gamma - 1) / (p.gamma * p.eps * p.D) * T0)
+    axis_slot = al if nd == 3 else (0 if al == 0 else 1)
+    tau = 0.2 * h[axis_slot] / (abs(u0[axis_slot]) + c)
+    Y = ora.sweep(p, al, tau, X)
+    G = maccormack_symbol(p, nd, rho0, u0, T0, axis_slot, th, h, tau)
+    expect = amp * _mode_field(p, th, G @ v)
+    got = Y - X0
+    # rows whose stencil meets a plate row (reset by L_z, copied through
+    # unpredicted by L_x and L_y) are not pure-mode nodes
+    rows = slice(3, p.nz - 3) if al == 2 else slice(2, p.nz - 2)
+    err = np.max(np.abs(got[:, rows] - expect[:, rows])) / (amp * np.max(np.abs(v)))
+    assert err < 2e-5, err
+    # the update is not trivially small: the mode really moved
+    assert np.max(np.abs(got - amp * _mode_field(p, th, v))) > 1e-3 * amp
+
+
+def test_acoustic_wave_speed_lax_wendroff(ora):
+    """A right-going acoustic eigenmode (gravity, viscosity, TVD off) is
+    multiplied per L_x(tau) by g = 1 - i nu sin(th) - nu^2 (1 - cos th) with
+    nu = c tau/dx, c = sqrt(gamma p/rho): its phase speed is the Lax-Wendroff
+    one, which tends to c."""
+    p = Params(nx=64, nz=3, gravity_scale=0.0, tvd_on=0, noise_amp=0.0,
+               diffusion_scale=0.0)
+    rho0, T0 = 1.0, 0.75
+    X0 = uniform_state(p, rho0, np.array([0.0, 0.0]), T0)
+    cv = cv_of(p)
+    pr = (p.gamma - 1) * cv * rho0 * T0
+    c = np.sqrt(p.gamma * pr / rho0)
+    H = (X0[3, 0, 0] + pr) / rho0
+    r = np.array([1.0, c, 0.0, H])              # right eigenvector, speed +c
+    th = 2 * np.pi * 4 / p.nx
+    i = np.arange(p.nx)
+    amp = 1e-8
+    X = X0.copy()
+    X[:, 1, :] += amp * r[:, None] * np.cos(th * i)[None, :]
+    dx = p.aspect / p.nx
+    tau = 0.4 * dx / c
+    Y = ora.sweep(p, 0, tau, X)
+    nu = c * tau / dx
+    g = 1 - 1j * nu * np.sin(th) - nu**2 * (1 - np.cos(th))
+    coef = 2.0 / p.nx * np.sum((Y[0, 1] - rho0) * np.exp(-1j * th * i))
+    assert abs(coef / amp - g) < 1e-6
+    # measured shift per application, in cells, against c tau/dx: the
+    # Lax-Wendroff dispersion error is (1 - nu^2) th^2 / 6 to leading order
+    shift = -np.angle(coef / amp) / th
+    assert abs(shift / nu - 1.0) < 1.5 * (1 - nu**2) * th**2 / 6
+
+
+# --------------------------------------------------------------------------
+# conservation, symmetry and invariants
+
+
+def test_mass_conserved_to_roundoff(ora):
+    """Conservative form (Sec. 3.1, vector_eqn) with no-flux plates: total
+    mass (trapezoid in z) is constant to roundoff over 200 steps."""
+    p = Params(nx=64, nz=17, noise_amp=1e-2, seed=3, Ra=1e5)
+    X = ora.init(p)
+    m0 = ora.diag(p, X)["mass"]
+    Y, t, dt = ora.step(p, X, 200)
+    m1 = ora.diag(p, Y)["mass"]
+    assert abs(m1 - m0) / m0 < 1e-13
+    assert np.max(np.abs(Y[2])) > 1e-6          # the flow did move
+
+
+def test_x_sweep_conserves_every_field(ora):
+    """The x operator is in flux form with periodic ends: each conserved
+    field's row sum is unchanged to roundoff, TVD on."""
+    p = Params(nx=48, nz=9, noise_amp=0.0, Ra=1e4)
+    rng = np.random.default_rng(1)
+    X = ora.init(p)
+    X[:, 1:-1] *= 1 + 0.05 * rng.random(X[:, 1:-1].shape)
+    X[1:3, 1:-1] += 0.1 * rng.standard_normal(X[1:3, 1:-1].shape)
+    Y = ora.sweep(p, 0, 0.3 * ora.dt(p, X), X)
+    s0, s1 = X[:, 1:-1].sum(axis=2), Y[:, 1:-1].sum(axis=2)
+    assert np.max(np.abs(s1 - s0) / np.abs(X[:, 1:-1]).sum(axis=2)) < 1e-14
+
+
+def test_x_uniform_state_stays_x_uniform(ora):
+    p = Params(nx=32, nz=17, noise_amp=0.0, Ra=1e5)
+    X = ora.init(p)
+    Y, _, _ = ora.step(p, X, 20)
+    assert np.all(Y == Y[:, :, :1])
+
+
+def test_translation_equivariance(ora):
+    """Periodic x: shifting the initial state by s columns shifts the result,
+    bit for bit."""
+    p = Params(nx=48, nz=13, noise_amp=1e-2, seed=11, Ra=1e5)
+    X = ora.init(p)
+    Ya, _, _ = ora.step(p, X, 5)
+    Yb, _, _ = ora.step(p, np.roll(X, 37, axis=2), 5)
+    assert np.array_equal(np.roll(Ya, 37, axis=2), Yb)
+
+
+def test_mirror_equivariance_exact(ora):
+    """x -> -x, m_x -> -m_x maps the scheme with backward predictor
+    differences onto the one with forward predictor differences, exactly."""
+    p = Params(nx=40, nz=11, noise_amp=1e-2, seed=5, Ra=1e5)
+    X = ora.init(p)
+    X[1, 1:-1] = 0.05 * np.sin(2 * np.pi * np.arange(p.nx) / p.nx)[None, :] * X[0, 1:-1]
+
+    def mirror(A):
+        B = A[:, :, (-np.arange(p.nx)) % p.nx].copy()
+        B[1] = -B[1]
+        return B
+
+    tau = 0.5 * ora.dt(p, X)
+    Ya = ora.sweep(p, 0, tau, X)
+    pf = Params(**{**p.__dict__, "pred_dir": 1})
+    Yb = ora.sweep(pf, 0, tau, mirror(X))
+    assert np.array_equal(mirror(Ya), Yb)
+
+
+def test_mirror_symmetry_defect_converges(ora):
+    """With the printed (one-sided) predictor a mirror-symmetric state picks
+    up an asymmetry of O(dx^2) per unit time: the defect falls by about 4x
+    per grid doubling."""
+    defects = []
+    for nx in (32, 64, 128):
+        p = Params(nx=nx, nz=3, gravity_scale=0.0, tvd_on=0, noise_amp=0.0,
+                   Ra=1e4)
+        X = uniform_state(p, 1.0, np.array([0.0, 0.0]), 0.75)
+        x = (np.arange(nx) + 0.0) * p.aspect / nx
+        bump = 1e-2 * np.cos(2 * np.pi * x / p.aspect)   # even about x = 0
+        X[0, 1] *= 1 + bump
+        tau = 0.1 * (p.aspect / nx)
+        n = int(round(0.05 / tau))
+        for _ in range(n):
+            X = ora.sweep(p, 0, tau, X)
+        rho = X[0, 1]
+        defects.append(np.max(np.abs(rho - rho[(-np.arange(nx)) % nx])))
+    assert defects[0] / defects[1] > 3.3 and defects[1] / defects[2] > 3.3
+
+
+def test_2d_equals_y_uniform_3d(ora):
+    """A y-uniform 3D state (m_y = 0) evolves exactly like the 2D one: L_y is
+    the identity and the z,y,x,z,y,x order collapses to z,x,z,x."""
+    p2 = Params(nx=24, nz=11, noise_amp=1e-2, seed=9, Ra=1e5)
+    p3 = Params(**{**p2.__dict__, "ndim": 3, "ny": 4})
+    X2 = ora.init(p2)
+    X3 = np.zeros(p3.shape)
+    X3[0] = X2[0][:, None, :]
+    X3[1] = X2[1][:, None, :]
+    X3[3] = X2[2][:, None, :]
+    X3[4] = X2[3][:, None, :]
+    Y2, t2, d2 = ora.step(p2, X2, 5)
+    Y3, t3, d3 = ora.step(p3, X3, 5)
+    assert d2 == d3 and t2 == t3
+    assert np.all(Y3[2] == 0)
+    for f2, f3 in ((0, 0), (1, 1), (2, 3), (3, 4)):
+        assert np.array_equal(Y3[f3], np.repeat(Y2[f2][:, None, :], 4, axis=1))
+
+
+def test_x_and_y_operators_are_rotations_of_each_other(ora):
+    """Swapping x <-> y (and m_x <-> m_y) on a square-columned 3D grid maps
+    L_x onto L_y."""
+    p = Params(ndim=3, nx=12, ny=12, nz=7, noise_amp=2e-2, seed=4, Ra=1e4)
+    X = ora.init(p)
+    rng = np.random.default_rng(2)
+    X[1, 1:-1] = 0.05 * rng.standard_normal(X[1, 1:-1].shape)
+    X[2, 1:-1] = 0.05 * rng.standard_normal(X[2, 1:-1].shape)
+
+    def swap(A):
+        B = np.swapaxes(A, 2, 3).copy()
+        B[[1, 2]] = B[[2, 1]]
+        return B
+
+    tau = 0.5 * ora.dt(p, X)
+    Ya = ora.sweep(p, 0, tau, X)
+    Yb = ora.sweep(p, 1, tau, swap(X))
+    assert np.max(np.abs(swap(Ya) - Yb)) <= 1e-14 * np.max(np.abs(Ya))
+
+
+# --------------------------------------------------------------------------
+# the TVD stage
+
+
+def _contact(p, ratio=2.0, u=0.8):
+    X = uniform_state(p, 1.0, np.array([u, 0.0]), 0.75)
+    cv = cv_of(p)
+    pr = (p.gamma - 1) * cv * 1.0 * 0.75
+    rho = np.where((np.arange(p.nx) >= p.nx // 4) & (np.arange(p.nx) < p.nx // 2),
+                   ratio, 1.0)
+    T = pr / ((p.gamma - 1) * cv * rho)
+    X[0, 1] = rho
+    X[1, 1] = rho * u
+    X[2, 1] = 0.0
+    X[3, 1] = rho * (cv * T + 0.5 * u * u)
+    return X
+
+
+def test_tvd_stage_prevents_new_extrema_at_a_contact(ora):
+    """Sec. 3.1 says the TVD term keeps solutions free of spurious
+    oscillations.  Advecting a density step: MacCormack alone over- and
+    undershoots; with the limiter in the form G(r+) + G(r-) (Davis; Yee) no
+    new extremum appears.  The argument as printed, G(r+_k + r-_{k+1}), only
+    damps the overshoot: at the foot of a jump one ratio is 0 and the other
+    large, their sum exceeds 1/2 and that face gets no dissipation.  Both
+    forms are kept (limiter_form 0 = as printed, the default; 1 = Davis)."""
+    out = {}
+    for tvd, lf in ((0, 0), (1, 0), (1, 1)):
+        p = Params(nx=128, nz=3, gravity_scale=0.0, diffusion_scale=0.0,
+                   tvd_on=tvd, limiter_form=lf, noise_amp=0.0)
+        X = _contact(p)
+        tau = 0.5 * ora.dt(p, X)
+        for _ in range(60):
+            X = ora.sweep(p, 0, tau, X)
+        rho = X[0, 1]
+        out[(tvd, lf)] = max(rho.max() - 2.0, 1.0 - rho.min())
+    assert out[(0, 0)] > 0.2
+    assert out[(1, 1)] < 1e-6
+    assert 0.05 < out[(1, 0)] < 0.6 * out[(0, 0)]
+
+
+def test_tvd_term_at_an_isolated_spike(ora):
+    """At an isolated extremum both ratios are negative, phi = 0 and each
+    face gets the full coefficient G = C/2 with C = Co(1 - Co): the TVD term
+    is C/2 times the discrete second difference of the spike, and it is zero
+    where the data are flat."""
+    p = Params(nx=32, nz=3, gravity_scale=0.0, diffusion_scale=0.0, noise_amp=0.0)
+    X = uniform_state(p, 1.0, np.array([0.0, 0.0]), 0.75)
+    s = 0.2
+    X[3, 1, 16] += s
+    tau = 0.5 * ora.dt(p, X)
+    Y1 = ora.sweep(p, 0, tau, X)
+    Y0 = ora.sweep(Params(**{**p.__dict__, "tvd_on": 0}), 0, tau, X)
+    d = (Y1 - Y0)[3, 1]
+    cv = cv_of(p)
+    a = (p.gamma - 1) / (p.gamma * p.eps * p.D)
+    T = (X[3, 1] / X[0, 1]) / cv
+    c = np.sqrt(p.gamma * a * T)
+    dx = p.aspect / p.nx
+    Co_l = tau / dx * max(c[15], c[16])
+    Co_r = tau / dx * max(c[16], c[17])
+    Gl, Gr = 0.5 * Co_l * (1 - Co_l), 0.5 * Co_r * (1 - Co_r)
+    assert abs(d[15] - Gl * s) < 1e-14
+    assert abs(d[16] + (Gl + Gr) * s) < 1e-14
+    assert abs(d[17] - Gr * s) < 1e-14
+    assert np.all(d[:14] == 0) and np.all(d[19:] == 0)
+    assert np.all((Y1 - Y0)[:3] == 0)
+
+
+def test_tvd_term_vanishes_on_linear_data(ora):
+    """Linear data: every ratio is 1, r+ + r- = 2, phi = 1, G = 0."""
+    p = Params(nx=12, nz=5, gravity_scale=0.0, Ra=1e4, noise_amp=0.0)
+    B = uniform_state(Params(**{**p.__dict__, "nx": 12}), 1.0, np.array([0.1, 0.0]), 0.75)
+    ramp = 1 + 0.01 * np.arange(12)
+    B = B * ramp[None, None, :]
+    Y1 = ora.sweep_box(p, 0, 1e-3, B)
+    Y0 = ora.sweep_box(Params(**{**p.__dict__, "tvd_on": 0}), 0, 1e-3, B)
+    assert np.array_equal(Y1[:, 1:-1, 2:-2], Y0[:, 1:-1, 2:-2])
+
+
+# --------------------------------------------------------------------------
+# accuracy
+
+
+def _smooth_wave(p, nx):
+    X = uniform_state(p, 1.0, np.array([0.2, 0.1]), 0.75)
+    x = np.arange(nx) * p.aspect / nx
+    k = 2 * np.pi / p.aspect
+    X[0, 1] *= 1 + 0.05 * np.sin(k * x)
+    X[1, 1] += 0.03 * np.cos(k * x)
+    X[2, 1] += 0.02 * np.sin(2 * k * x)
+    X[3, 1] *= 1 + 0.04 * np.cos(k * x + 0.3)
+    return X
+
+
+@pytest.mark.parametrize("tvd,lf", [(0, 0), (1, 0), (1, 1)])
+def test_second_order_self_convergence_in_x(ora, tvd, lf):
+    """Sec. 3.1 claims second order in space and time.  Smooth periodic
+    nonlinear flow with viscosity and conduction, run to a fixed time with
+    dt proportional to dx: differences between successive grids fall 4x.
+    The printed limiter never acts on smooth data (r+ + r- stays near 2 even
+    at an extremum); the Davis form clips extrema on coarse grids and lets go
+    as the grid resolves them, so its observed order is at least 2."""
+    sols = {}
+    for nx in (32, 64, 128, 256):
+        p = Params(nx=nx, nz=3, gravity_scale=0.0, tvd_on=tvd, limiter_form=lf,
+                   noise_amp=0.0, Ra=1e4, aspect=1.0)
+        X = _smooth_wave(p, nx)
+        tau = 0.05 / nx
+        for _ in range(int(round(0.1 / tau))):
+            X = ora.sweep(p, 0, tau, X)
+        sols[nx] = X[:, 1]
+    e = [np.max(np.abs(sols[n][:, :] - sols[2 * n][:, ::2])) for n in (32, 64, 128)]
+    order = np.log2(e[1] / e[2])
+    if lf == 0:
+        assert 1.9 < order < 2.1, e
+    else:
+        assert order > 1.9, e
+
+
+def test_hydrostatic_state_error_is_second_order_in_z(ora):
+    """The conductive-hydrostatic profile is an exact steady solution of the
+    equations (Sec. 2) but not of the discrete scheme: its spurious velocity
+    at a fixed time (t = 0.1, after the start-up acoustic transient) falls
+    about 4x per doubling of nz.  This fixes the gravity source (-rho/eps in
+    the z momentum), p in the z flux and the plate closure."""
+    umax = []
+    for nz in (33, 65, 129):
+        p = Params(nx=4, nz=nz, noise_amp=0.0, Ra=1e5)
+        X = ora.init(p)
+        n = int(round(0.1 / ora.dt(p, X)))
+        Y, t, _ = ora.step(p, X, n)
+        umax.append(np.max(np.abs(Y[2] / Y[0])))
+    assert umax[0] / umax[1] > 3.3 and umax[1] / umax[2] > 3.3, umax
+    assert umax[2] < 1e-4
