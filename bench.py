@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Benchmark of the MacCormack-TVD step on one MI355X.
+
+Workload (default): the 2D 4096 x 1024 box, FP64, gamma 1.4, Pr 1, Ra 1e10,
+plates at T = 1 and 0.5, seeded +-1e-3 T noise, 1000 steps with the
+diagnostics (Nu, mass, ...) every 100 steps.  The state is synthetic
+(generated on the GPU by mtvd_init_state) and resident in HBM before the
+timed region.
+
+Prints ONE JSON line: cell-updates/s over the timed steps (diagnostics
+included), the per-kernel roofline of the dominant sweep kernel (bytes of
+the per-sweep model: read and write every field once per node, measured
+with HIP events recorded on the library's stream), and the CPU oracle timed
+on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FP64 MacCormack-TVD cell-updates/s, % HBM roofline; adjoint cost/forward"
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+AXES = {0: "sweep_x", 1: "sweep_y", 2: "sweep_z"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2411_10372_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str, kernel: str, shash: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("source_hash") != shash:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(kw: dict, budget_s: float):
+    """The CPU oracle, as it stands, on a bounded sample of the workload:
+    as many full steps from its initial state as fit in about budget_s."""
+    import oracle
+    p = oracle.Params(**kw)
+    X = oracle.init(p)
+    nodes = p.nx * (p.ny if p.ndim == 3 else 1) * p.nz
+    t0 = time.perf_counter()
+    X, _, _ = oracle.step(p, X, 1)
+    one = time.perf_counter() - t0
+    extra = max(0, int(budget_s / max(one, 1e-9)) - 1)
+    t1 = time.perf_counter()
+    if extra:
+        X, _, _ = oracle.step(p, X, extra)
+    tot = one + (time.perf_counter() - t1)
+    steps = 1 + extra
+    return {"value": nodes * steps / tot, "unit": "cell-updates/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{steps} full steps of the same workload from its initial state "
+                      f"({tot:.1f} s, OpenMP threads {oracle.threads()})"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="2d_4096x1024_ra1e10")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rows", type=int, nargs=2, default=None,
+                    help="rows per wave for the x and z sweeps (default: library choice)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2411_10372_amd as mtvd
+    from paper_2411_10372_amd.workloads import WORKLOADS, params_dict
+
+    wl = WORKLOADS[args.workload]
+    kw = params_dict(args.workload)
+    p = mtvd.Params(**kw)
+    diag_every = wl.get("diag_every", 0)
+    K, W = args.steps, args.warmup
+    nodes = p.nodes
+
+    torch.cuda.set_device(0)
+    s = mtvd.Solver(p, device="cuda:0")
+    if args.rows:
+        s.set_tiling(*args.rows)
+    s.init_state()
+    s.step(W)
+    s.sync()
+    torch.cuda.synchronize()
+
+    # timed region: K steps, diagnostics every diag_every steps (they
+    # synchronise with the host, as a production run would)
+    log(f"timing {K} steps of {args.workload} ({nodes} nodes)")
+    t0 = time.perf_counter()
+    done = 0
+    diags = []
+    while done < K:
+        n = K - done
+        if diag_every:
+            n = min(n, diag_every - done % diag_every)
+        s.step(n)
+        done += n
+        if diag_every and done % diag_every == 0:
+            diags.append(s.diagnostics())
+    s.sync()
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t0
+
+    # the same K steps without diagnostics, with HIP events around every
+    # sweep launch on the library's stream
+    s.set_timing(True)
+    t0 = time.perf_counter()
+    s.step(K)
+    s.sync()
+    torch.cuda.synchronize()
+    t_nodiag = time.perf_counter() - t0
+    s.set_timing(False)
+    ms, cnt = s.kernel_times()
+    dfin = s.diagnostics()
+
+    kern = {AXES[a]: {"avg_us": 1e3 * ms[a] / cnt[a], "launches": cnt[a]}
+            for a in range(3) if cnt[a]}
+    dom = max(range(3), key=lambda a: ms[a])
+    per_launch_bytes = nodes * 2 * p.nf * 8      # read + write every field once
+    avg_s = 1e-3 * ms[dom] / cnt[dom]
+    achieved = per_launch_bytes / avg_s / 1e9
+    shash = source_hash()
+    traffic = load_traffic(args.workload, AXES[dom], shash)
+
+    value = nodes * K / t_all
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": 1e3 * t_all / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded initial state generated on the GPU)",
+        "config": {"workload": args.workload, "ndim": p.ndim, "nx": p.nx, "ny": p.ny,
+                   "nz": p.nz, "Ra": p.Ra, "Pr": p.Pr, "gamma": p.gamma, "eps": p.eps,
+                   "D": p.D, "cfl": p.cfl, "diag_every": diag_every},
+        "roofline": {"bound": "hbm", "kernel": AXES[dom], "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "bytes_per_launch": per_launch_bytes},
+        "value_no_diag": nodes * K / t_nodiag,
+        "kernels": kern,
+        "final": {"step": dfin["step"], "time": dfin["time"], "mass": dfin["mass"],
+                  "nu_mean": dfin["nu_mean"], "nu_bulk": dfin["nu_bulk"]},
+        "source_hash": shash,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(kw, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,175 @@
+/*
+ * mtvd.h -- C ABI of the MI355X (gfx950) MacCormack-TVD library.
+ *
+ * One explicit time step of the nondimensional, fully compressible
+ * Navier-Stokes equations of an ideal gas under gravity (density, momentum,
+ * total energy) in a box with periodic side walls and no-slip isothermal
+ * plates, as defined by Tiwari, Sharma & Verma, arXiv:2411.10372:
+ *   - equations, p, E and tau_ij:       Sec. 2 (nondimensional equations);
+ *   - conservative vector form, fluxes: Sec. 3.1 (vector_eqn, F_alpha, S_alpha);
+ *   - split step:                       Sec. 3.1 (time_step);
+ *   - predictor / corrector / TVD:      Sec. 3.1 (the three update formulas
+ *                                        and the definitions of T, r, G, phi, C);
+ *   - Nusselt numbers:                  Sec. 2 (volume_Nu, mean_Nu).
+ * Every step runs in HIP kernels on the caller's stream; the host only
+ * launches.  FP64 throughout.
+ *
+ * State layout ("canonical"): one array of nf * nz * ny * nx doubles,
+ * X[f][k][j][i], i fastest, no padding, with fields
+ *   2D (nf = 4): rho, rho u_x, rho u_z, E
+ *   3D (nf = 5): rho, rho u_x, rho u_y, rho u_z, E.
+ * x and y are periodic (dx = aspect/nx, dy = aspect/ny, no repeated end
+ * point); z has nz nodes with the bottom plate at k = 0 and the top plate
+ * at k = nz-1 (dz = 1/(nz-1)).
+ *
+ * Ownership: the caller allocates and owns the two state buffers and the
+ * workspace (device memory, 256-byte aligned, at least the sizes that
+ * mtvd_state_bytes reports) and the stream.  The library owns only the
+ * context.  A context is bound to one stream, is not thread-safe, and
+ * keeps no pointer to host memory after a call returns.
+ *
+ * Errors: every function returns MTVD_OK (0) or a negative MTVD_E* code and
+ * never aborts.  Asynchronous device errors (non-finite values, rho <= 0,
+ * T <= 0) are latched in the workspace and reported by the next
+ * synchronising call (mtvd_diagnostics, mtvd_get_state, mtvd_sync).
+ */
+#ifndef MTVD_H
+#define MTVD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MTVD_OK = 0,
+  MTVD_EINVAL = -1,      /* bad parameters or argument */
+  MTVD_ESIZE = -2,       /* buffer too small or misaligned, count mismatch */
+  MTVD_ESTABILITY = -3,  /* cfl outside (0, 1] or diffusion number > 1/2 */
+  MTVD_ESTATE = -4,      /* call out of order (no buffers / no state yet) */
+  MTVD_ENONFINITE = -5,  /* device flag: NaN/Inf, rho <= 0 or T <= 0 seen */
+  MTVD_EHIP = -6         /* HIP runtime error; text in mtvd_last_error */
+};
+
+/* Problem parameters.  Defaults (mtvd_default_params): the 2D 256x64 box,
+ * gamma 1.4, Pr 1, Ra 1e6, eps 0.1, D 0.4, cfl 0.5, noise 1e-3, and the
+ * readings listed with each knob. */
+typedef struct mtvd_params {
+  int32_t ndim;          /* 2 or 3 */
+  int32_t nx, ny, nz;    /* ny = 1 in 2D; nz >= 5 (plates included) */
+  double aspect;         /* Gamma = L/d */
+  double gamma, Pr, Ra, eps, D;   /* Sec. 2 parameters; plates T = 1, 1-eps-D */
+  double cfl;            /* dt = cfl * min_nodes,a h_a/(|u_a| + c) */
+  uint64_t seed;         /* SplitMix64 seed of the initial T noise */
+  double noise_amp;      /* uniform +-noise_amp on interior T at init */
+  int32_t dt_mode;       /* 0: dt from the state at every step;
+                            1: dt frozen at its value for the state given by
+                            mtvd_init_state / mtvd_set_state */
+  double bulk_coef;      /* lambda in tau_ij = mu(d_j u_i + d_i u_j +
+                            lambda d_m u_m delta_ij); -2/3 (Stokes) by
+                            default, +2/3 is the sign as printed */
+  int32_t limiter_form;  /* 0: G(r+_k + r-_{k+1}) as printed (default);
+                            1: G(r+_k) + G(r-_{k+1}) (Davis) */
+  int32_t sweep_order;   /* 0: L_x L_y L_z L_x L_y L_z as printed (default);
+                            1: L_z L_y L_x L_x L_y L_z (symmetric) */
+  int32_t tvd_on;        /* 1 (default); 0 drops the TVD term */
+  double gravity_scale;  /* 1 (default); 0 switches gravity off */
+  int32_t wall_order;    /* 2 (default): z-derivatives inside the plate
+                            fluxes are second-order one-sided; 1: interior
+                            first differences */
+} mtvd_params;
+
+/* Diagnostics of the current state (Sec. 2: mass, kinetic energy, total
+ * energy; Nu_{z=0}, Nu_{z=1} and their mean from <T>_A on the three rows next
+ * to each plate with second-order one-sided differences; bulk Nu = 1 +
+ * Nu_conv + Nu_K as volume averages; trapezoid weights in z). */
+typedef struct mtvd_diag {
+  int64_t step;          /* steps taken since init/set_state (+ given base) */
+  double time;           /* simulated time */
+  double dt;             /* dt of the next step */
+  double mass, kinetic, total_energy;
+  double nu_bottom, nu_top, nu_mean, nu_bulk, nu_conv, nu_kin;
+  double tmean[6];       /* <T>_A on rows 0, 1, 2, nz-3, nz-2, nz-1 */
+  int32_t flags;         /* latched device flags (bit 0: non-finite or
+                            non-positive rho/T seen) */
+} mtvd_diag;
+
+typedef struct mtvd_ctx mtvd_ctx;
+
+void mtvd_default_params(mtvd_params* p);
+
+/* Bytes of one state buffer and of the workspace for these parameters. */
+int mtvd_state_bytes(const mtvd_params* p, size_t* state_bytes,
+                     size_t* workspace_bytes);
+
+/* Validate parameters and create a context on `hip_stream` (a hipStream_t,
+ * NULL = default stream) of the current device.  No device work.
+ * Returns MTVD_EINVAL / MTVD_ESTABILITY on bad parameters. */
+int mtvd_create(const mtvd_params* p, void* hip_stream, mtvd_ctx** out);
+
+/* Attach caller-owned device memory: two state buffers (ping-pong) and the
+ * workspace.  The pointers must be distinct, 256-byte aligned and at least
+ * the sizes of mtvd_state_bytes (MTVD_ESIZE otherwise).  Buffer contents
+ * are not read. */
+int mtvd_bind(mtvd_ctx* c, double* buf_a, double* buf_b, void* workspace);
+
+/* Write the initial state (conductive T = 1 - (eps+D) z, hydrostatic
+ * rho = T^(m-1) with m = gamma D/((gamma-1)(eps+D)), u = 0, SplitMix64 noise
+ * on interior T) into buffer a and compute its dt.  Time and step are reset
+ * to 0.  Asynchronous. */
+int mtvd_init_state(mtvd_ctx* c);
+
+/* Advance nsteps >= 0 time steps of the split scheme (Sec. 3.1, time_step):
+ * 2D L_x L_z L_x L_z, 3D L_x L_y L_z L_x L_y L_z (rightmost first), each
+ * L_a(dt/2) a fused predictor/corrector/TVD kernel.  Asynchronous: no host
+ * synchronisation, dt never leaves the device. */
+int mtvd_step(mtvd_ctx* c, int32_t nsteps);
+
+/* Apply one directional operator L_axis(dt/2) (axis 0 = x, 1 = y, 2 = z)
+ * with dt computed from the current state; time and step are unchanged.
+ * For per-operator checks.  Asynchronous. */
+int mtvd_sweep(mtvd_ctx* c, int32_t axis);
+
+/* Compute the diagnostics of the current state; synchronises the stream.
+ * Returns MTVD_ENONFINITE (and still fills *out) if a device flag is set. */
+int mtvd_diagnostics(mtvd_ctx* c, mtvd_diag* out);
+
+/* Copy the current state to host memory in the canonical layout; count
+ * must equal nf*nz*ny*nx.  Synchronises. */
+int mtvd_get_state(mtvd_ctx* c, double* host, size_t count);
+
+/* Replace the current state by a host array in the canonical layout, set
+ * time and step, recompute dt (and the frozen dt when dt_mode = 1), clear
+ * the device flags.  Synchronises. */
+int mtvd_set_state(mtvd_ctx* c, const double* host, size_t count, double time,
+                   int64_t step);
+
+/* Which bound buffer (0 = a, 1 = b) holds the current state. */
+int mtvd_current(const mtvd_ctx* c, int32_t* which);
+
+/* Wait for the context's stream and report latched device flags. */
+int mtvd_sync(mtvd_ctx* c);
+
+/* Rows per wave along z for the sweep kernels (0 = library default).  Any
+ * value >= 1 gives identical results; it only changes the launch shape. */
+int mtvd_set_tiling(mtvd_ctx* c, int32_t rows_x, int32_t rows_z);
+
+/* Per-launch timing of the sweep kernels with HIP events recorded on the
+ * context's stream around each launch (for benchmarks).  enable != 0 starts
+ * recording, 0 stops it.  mtvd_kernel_times synchronises, adds the elapsed
+ * milliseconds and launch counts of the recorded launches to ms[axis] and
+ * counts[axis] (axis 0 = L_x, 1 = L_y, 2 = L_z) and forgets them. */
+int mtvd_set_timing(mtvd_ctx* c, int32_t enable);
+int mtvd_kernel_times(mtvd_ctx* c, double ms[3], int64_t counts[3]);
+
+int mtvd_destroy(mtvd_ctx* c);
+
+const char* mtvd_strerror(int status);
+const char* mtvd_last_error(const mtvd_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -117,6 +117,8 @@ def lib():
         L = ctypes.CDLL(_LIB)
         P = ctypes.POINTER(_Params)
         dp = ctypes.POINTER(ctypes.c_double)
+        L.ora_threads.argtypes = []
+        L.ora_threads.restype = ctypes.c_int
         L.ora_state_len.argtypes = [P]
         L.ora_state_len.restype = ctypes.c_size_t
         L.ora_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
@@ -146,6 +148,11 @@ def _ptr(a: np.ndarray):
 def _ok(rc: int, what: str):
     if rc != 0:
         raise ValueError(f"oracle {what} rejected its arguments (rc={rc})")
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().ora_threads())
 
 
 def splitmix64(seed: int, n: int) -> int:

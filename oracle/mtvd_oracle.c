@@ -126,6 +126,14 @@ static void set_threads(const ora_params* p) {
 /* height of row k: z_k = k / M, so the plates sit exactly at 0 and 1 */
 static double zrow(const coefs* c, int k) { return (double)k / (double)c->M; }
 
+int ora_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 size_t ora_state_len(const ora_params* p) {
   size_t ny = (p->ndim == 3) ? (size_t)p->ny : 1;
   return (size_t)(p->ndim + 2) * (size_t)p->nz * ny * (size_t)p->nx;

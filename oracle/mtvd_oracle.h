@@ -56,6 +56,9 @@ typedef struct ora_diag {
   double tmean[6];       /* <T>_A on rows 0, 1, 2, M-2, M-1, M */
 } ora_diag_t;
 
+/* OpenMP threads the oracle's parallel loops use */
+int ora_threads(void);
+
 /* number of doubles in one state array */
 size_t ora_state_len(const ora_params* p);
 

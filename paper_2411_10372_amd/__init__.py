@@ -1,0 +1,264 @@
+"""MI355X (gfx950) MacCormack-TVD step of compressible convection.
+
+A thin ctypes binding of ``libmtvd.so`` (C ABI in ``include/mtvd.h``): every
+step of the method runs in the library's HIP kernels; this module only
+marshals arguments.  PyTorch supplies device memory (the two state buffers
+and the workspace) and the stream.  There is no CPU fallback: importing works
+without a GPU, but creating a :class:`Solver` needs the built library and a
+GPU, and raises otherwise.
+
+Paper: Tiwari, Sharma & Verma, arXiv:2411.10372 (Sec. 2 equations and
+Nusselt numbers, Sec. 3.1 MacCormack-TVD scheme).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, fields
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmtvd.so")
+
+MTVD_OK = 0
+MTVD_EINVAL = -1
+MTVD_ESIZE = -2
+MTVD_ESTABILITY = -3
+MTVD_ESTATE = -4
+MTVD_ENONFINITE = -5
+MTVD_EHIP = -6
+
+
+class MtvdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mtvd error {code}: {msg}")
+        self.code = code
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("nz", ctypes.c_int32), ("aspect", ctypes.c_double),
+        ("gamma", ctypes.c_double), ("Pr", ctypes.c_double), ("Ra", ctypes.c_double),
+        ("eps", ctypes.c_double), ("D", ctypes.c_double), ("cfl", ctypes.c_double),
+        ("seed", ctypes.c_uint64), ("noise_amp", ctypes.c_double),
+        ("dt_mode", ctypes.c_int32), ("bulk_coef", ctypes.c_double),
+        ("limiter_form", ctypes.c_int32), ("sweep_order", ctypes.c_int32),
+        ("tvd_on", ctypes.c_int32), ("gravity_scale", ctypes.c_double),
+        ("wall_order", ctypes.c_int32),
+    ]
+
+
+class _Diag(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("time", ctypes.c_double), ("dt", ctypes.c_double)] + \
+        [(n, ctypes.c_double) for n in ("mass", "kinetic", "total_energy", "nu_bottom",
+                                        "nu_top", "nu_mean", "nu_bulk", "nu_conv", "nu_kin")] + \
+        [("tmean", ctypes.c_double * 6), ("flags", ctypes.c_int32)]
+
+
+@dataclass
+class Params:
+    """Problem parameters; field names and meaning as in ``mtvd_params``."""
+    ndim: int = 2
+    nx: int = 256
+    ny: int = 1
+    nz: int = 64
+    aspect: float = 4.0
+    gamma: float = 1.4
+    Pr: float = 1.0
+    Ra: float = 1e6
+    eps: float = 0.1
+    D: float = 0.4
+    cfl: float = 0.5
+    seed: int = 0
+    noise_amp: float = 1e-3
+    dt_mode: int = 0
+    bulk_coef: float = -2.0 / 3.0
+    limiter_form: int = 0
+    sweep_order: int = 0
+    tvd_on: int = 1
+    gravity_scale: float = 1.0
+    wall_order: int = 2
+
+    def _c(self) -> _Params:
+        return _Params(**{f.name: getattr(self, f.name) for f in fields(self)})
+
+    @property
+    def nf(self) -> int:
+        return self.ndim + 2
+
+    @property
+    def shape(self):
+        if self.ndim == 3:
+            return (self.nf, self.nz, self.ny, self.nx)
+        return (self.nf, self.nz, self.nx)
+
+    @property
+    def nodes(self) -> int:
+        return self.nx * (self.ny if self.ndim == 3 else 1) * self.nz
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise MtvdError(MTVD_EHIP, f"{LIB_PATH} is missing: run __graft_entry__.build() "
+                                       "(or python paper_2411_10372_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER(_Params)
+        vp = ctypes.c_void_p
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.mtvd_default_params.argtypes = [P]
+        L.mtvd_default_params.restype = None
+        L.mtvd_state_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t),
+                                       ctypes.POINTER(ctypes.c_size_t)]
+        L.mtvd_create.argtypes = [P, vp, ctypes.POINTER(vp)]
+        L.mtvd_bind.argtypes = [vp, vp, vp, vp]
+        L.mtvd_init_state.argtypes = [vp]
+        L.mtvd_step.argtypes = [vp, ctypes.c_int32]
+        L.mtvd_sweep.argtypes = [vp, ctypes.c_int32]
+        L.mtvd_diagnostics.argtypes = [vp, ctypes.POINTER(_Diag)]
+        L.mtvd_get_state.argtypes = [vp, dp, ctypes.c_size_t]
+        L.mtvd_set_state.argtypes = [vp, dp, ctypes.c_size_t, ctypes.c_double, ctypes.c_int64]
+        L.mtvd_current.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+        L.mtvd_sync.argtypes = [vp]
+        L.mtvd_set_tiling.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+        L.mtvd_set_timing.argtypes = [vp, ctypes.c_int32]
+        L.mtvd_kernel_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int64)]
+        L.mtvd_destroy.argtypes = [vp]
+        L.mtvd_strerror.argtypes = [ctypes.c_int]
+        L.mtvd_strerror.restype = ctypes.c_char_p
+        L.mtvd_last_error.argtypes = [vp]
+        L.mtvd_last_error.restype = ctypes.c_char_p
+        for fn in ("mtvd_state_bytes", "mtvd_create", "mtvd_bind", "mtvd_init_state",
+                   "mtvd_step", "mtvd_sweep", "mtvd_diagnostics", "mtvd_get_state",
+                   "mtvd_set_state", "mtvd_current", "mtvd_sync", "mtvd_set_tiling",
+                   "mtvd_set_timing", "mtvd_kernel_times", "mtvd_destroy"):
+            getattr(L, fn).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def state_bytes(p: Params):
+    """(state_bytes, workspace_bytes) for these parameters."""
+    sb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    pc = p._c()
+    rc = lib().mtvd_state_bytes(ctypes.byref(pc), ctypes.byref(sb), ctypes.byref(wb))
+    if rc != MTVD_OK:
+        raise MtvdError(rc, lib().mtvd_strerror(rc).decode())
+    return sb.value, wb.value
+
+
+class Solver:
+    """One box on one GPU.  Buffers are torch tensors on ``device``; calls are
+    stream-ordered on ``stream`` (default: the current torch stream)."""
+
+    def __init__(self, p: Params, device=None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise MtvdError(MTVD_EHIP, "no GPU visible: the HIP library needs one")
+        self.p = p
+        self.device = torch.device(device if device is not None else "cuda")
+        L = lib()
+        sb, wb = state_bytes(p)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            n = sb // 8
+            # 256-byte aligned by the caching allocator; checked by mtvd_bind
+            self.bufs = [torch.empty(n, dtype=torch.float64, device=self.device) for _ in range(2)]
+            self.ws = torch.empty((wb + 7) // 8, dtype=torch.float64, device=self.device)
+            ctx = ctypes.c_void_p()
+            pc = p._c()
+            self._check(L.mtvd_create(ctypes.byref(pc), ctypes.c_void_p(self.stream.cuda_stream),
+                                      ctypes.byref(ctx)), None)
+            self.ctx = ctx
+            self._check(L.mtvd_bind(self.ctx, ctypes.c_void_p(self.bufs[0].data_ptr()),
+                                    ctypes.c_void_p(self.bufs[1].data_ptr()),
+                                    ctypes.c_void_p(self.ws.data_ptr())))
+
+    def _check(self, rc: int, ctx="self"):
+        if rc != MTVD_OK:
+            L = lib()
+            msg = L.mtvd_strerror(rc).decode()
+            c = self.ctx if ctx == "self" else ctx
+            if c:
+                extra = L.mtvd_last_error(c).decode()
+                if extra:
+                    msg += f" ({extra})"
+            raise MtvdError(rc, msg)
+
+    # -- the C ABI, one method per entry point --------------------------------
+    def init_state(self):
+        self._check(lib().mtvd_init_state(self.ctx))
+
+    def step(self, n: int = 1):
+        self._check(lib().mtvd_step(self.ctx, int(n)))
+
+    def sweep(self, axis: int):
+        self._check(lib().mtvd_sweep(self.ctx, int(axis)))
+
+    def diagnostics(self, check: bool = True) -> dict:
+        d = _Diag()
+        rc = lib().mtvd_diagnostics(self.ctx, ctypes.byref(d))
+        if check:
+            self._check(rc)
+        out = {n: getattr(d, n) for n, _ in _Diag._fields_ if n != "tmean"}
+        out["tmean"] = list(d.tmean)
+        return out
+
+    def get_state(self) -> np.ndarray:
+        X = np.empty(self.p.shape, dtype=np.float64)
+        self._check(lib().mtvd_get_state(self.ctx, X.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                         X.size))
+        return X
+
+    def set_state(self, X: np.ndarray, time: float = 0.0, step: int = 0):
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        if X.shape != self.p.shape:
+            raise ValueError(f"state shape {X.shape} != {self.p.shape}")
+        self._check(lib().mtvd_set_state(self.ctx, X.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                         X.size, float(time), int(step)))
+
+    def current(self) -> int:
+        w = ctypes.c_int32()
+        self._check(lib().mtvd_current(self.ctx, ctypes.byref(w)))
+        return w.value
+
+    def state_tensor(self):
+        """The device buffer holding the current state (a view, canonical
+        layout).  Valid until the next step."""
+        return self.bufs[self.current()].view(self.p.shape)
+
+    def sync(self):
+        self._check(lib().mtvd_sync(self.ctx))
+
+    def set_tiling(self, rows_x: int = 0, rows_z: int = 0):
+        self._check(lib().mtvd_set_tiling(self.ctx, int(rows_x), int(rows_z)))
+
+    def set_timing(self, enable: bool):
+        self._check(lib().mtvd_set_timing(self.ctx, 1 if enable else 0))
+
+    def kernel_times(self):
+        """(ms[3], counts[3]) of the launches recorded since the last call,
+        indexed by axis (0 = x, 1 = y, 2 = z)."""
+        ms = (ctypes.c_double * 3)()
+        cnt = (ctypes.c_int64 * 3)()
+        self._check(lib().mtvd_kernel_times(self.ctx, ms, cnt))
+        return list(ms), list(cnt)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().mtvd_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

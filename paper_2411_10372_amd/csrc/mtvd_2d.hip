@@ -1,0 +1,431 @@
+// mtvd_2d.hip -- fused predictor/corrector/TVD kernels of one directional
+// operator L_a(tau) in 2D (Sec. 3.1 of arXiv:2411.10372: predictor with
+// backward flux differences, corrector with forward differences of the
+// predicted fluxes, average plus the TVD term).
+//
+// Launch shape (both directions): one wave of 64 lanes owns a strip of 60
+// output columns plus two halo columns on each side (lane l <-> column
+// i0 - 2 + l, periodic) and marches up a chunk of rows.  Values along z
+// stay in registers in rings of period 4 (the march is unrolled by 4 so
+// every ring index is a compile-time constant); values along x move
+// between lanes with cross-lane shuffles.  Each sweep reads and writes the
+// state once: 4 fields x 8 B in, 4 x 8 B out per node, plus halo re-reads
+// that hit in L2.
+#include "mtvd_device.h"
+#include "mtvd_launch.h"
+
+namespace mtvd {
+
+constexpr int kStrip = 60;   // output columns per wave
+
+struct Cols {
+  int col;        // this lane's (wrapped) column
+  bool out;       // lane writes its column
+};
+
+__device__ __forceinline__ Cols lane_cols(const Coef& c, int strip, int lane) {
+  Cols r;
+  int i0 = strip * kStrip;
+  int i = i0 - 2 + lane;
+  int m = i % c.nx;
+  r.col = (m < 0) ? m + c.nx : m;
+  r.out = lane >= 2 && lane < 62 && (i0 + lane - 2) < c.nx;
+  return r;
+}
+
+__device__ __forceinline__ N2 load2(const Coef& c, const double* __restrict__ X,
+                                    int k, int col) {
+  long long n = (long long)k * c.nx + col;
+  N2 v;
+  v.r = X[n];
+  v.mx = X[n + c.cnt];
+  v.mz = X[n + 2 * c.cnt];
+  v.E = X[n + 3 * c.cnt];
+  return v;
+}
+
+__device__ __forceinline__ void store2(const Coef& c, double* __restrict__ Y, int k,
+                                       int col, const N2& v) {
+  long long n = (long long)k * c.nx + col;
+  Y[n] = v.r;
+  Y[n + c.cnt] = v.mx;
+  Y[n + 2 * c.cnt] = v.mz;
+  Y[n + 3 * c.cnt] = v.E;
+}
+
+__device__ __forceinline__ double sh_dn(double v) { return __shfl_down(v, 1, 64); }
+__device__ __forceinline__ double sh_up(double v) { return __shfl_up(v, 1, 64); }
+__device__ __forceinline__ N2 sh_dn(const N2& v) {
+  return N2{sh_dn(v.r), sh_dn(v.mx), sh_dn(v.mz), sh_dn(v.E)};
+}
+__device__ __forceinline__ N2 sh_up(const N2& v) {
+  return N2{sh_up(v.r), sh_up(v.mx), sh_up(v.mz), sh_up(v.E)};
+}
+
+// Per-wave bookkeeping of the step: the first sweep of a step publishes dt
+// and time and clears the other max slot; the last one folds |u_a| + c of
+// its output into that slot.
+__device__ __forceinline__ void step_head(const Coef& c, Shared* sh, int slot, int first,
+                                          double dt) {
+  if (first && blockIdx.x == 0 && threadIdx.x == 0) {
+    sh->time += dt;
+    sh->dt_last = dt;
+    for (int a = 0; a < 4; ++a) sh->smax[slot ^ 1][a] = 0ull;
+  }
+}
+
+__device__ __forceinline__ void fold_max(Shared* sh, int slot, double mx, double mz,
+                                         bool bad) {
+  mx = wave_max(mx);
+  mz = wave_max(mz);
+  unsigned long long anybad = __ballot(bad);
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(&sh->smax[slot ^ 1][0], d2u(mx));
+    atomicMax(&sh->smax[slot ^ 1][2], d2u(mz));
+    if (anybad) atomicOr(&sh->flags, 1u);
+  }
+}
+
+__device__ __forceinline__ void out_max(const Coef& c, const N2& o, double z, double& mx,
+                                        double& mz, bool& bad, bool lane_out) {
+  P2 q = prim2(c, o, z);
+  double cs = sound(c, q.T);
+  double sx = fabs(q.ux) + cs, sz = fabs(q.uz) + cs;
+  if (lane_out) {
+    mx = fmax(mx, sx);
+    mz = fmax(mz, sz);
+    if (!(o.r > 0.0) || !(q.T > 0.0) || !(sx < INFINITY) || !(sz < INFINITY)) bad = true;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// L_z(tau): flux differences along the march, cross x-derivatives by shuffle.
+
+struct Z2 {
+  N2 x[4];      // X^n rows, slot row & 3
+  P2 pn[4];     // primitives of X^n
+  double s[4];  // |u_z| + c of X^n
+  N2 dl[4];     // dX_{row+1/2} = X[row+1] - X[row]
+  double G[4];  // TVD coefficient of face row+1/2
+  N2 F[2];      // predictor flux (forward inner derivatives), slot row & 1
+  N2 xp[4];     // X^P
+  P2 pp[4];     // primitives of X^P
+  N2 FP[2];     // corrector flux (backward inner derivatives)
+  double mx, mz;
+  bool bad;
+};
+
+template <int S, bool FUSE>
+__device__ __forceinline__ void z2_iter(const Coef& c, Z2& st, int f, int fs, int fe,
+                                        int k0, int k1, const Cols& L,
+                                        const double* __restrict__ zr,
+                                        const double* __restrict__ X,
+                                        double* __restrict__ Y, double tau, double lz) {
+  if (f < fs || f > fe) return;
+  const int M = c.M;
+  constexpr int c0 = S & 3;          // row f
+  constexpr int c1 = (S + 3) & 3;    // row f-1
+  constexpr int c2 = (S + 2) & 3;    // row f-2
+  constexpr int c3 = (S + 1) & 3;    // row f-3
+  constexpr int c4 = S & 3;          // row f-4
+  constexpr int e2 = S & 1;          // row f-2 in period-2 rings
+  constexpr int e3 = (S + 1) & 1;    // row f-3
+
+  // A: load row f and its primitives; dX of face f-1/2
+  if (f <= M) {
+    st.x[c0] = load2(c, X, f, L.col);
+    st.pn[c0] = prim2(c, st.x[c0], zr[f]);
+    st.s[c0] = fabs(st.pn[c0].uz) + sound(c, st.pn[c0].T);
+    if (f - 1 >= fs) st.dl[c1] = st.x[c0] - st.x[c1];
+  }
+  const int r = f - 2;
+  // B: predictor flux F_r (inner z forward; second-order forward at the
+  //    bottom plate when wall_order = 2), central x cross-derivatives
+  if (r >= k0 - 2 && r >= 0 && r <= M - 1) {
+    const P2& q0 = st.pn[c2];
+    const P2& q1 = st.pn[c1];
+    double dzux, dzuz, dzT;
+    if (r == 0 && c.wall_order == 2) {
+      const P2& q2 = st.pn[c0];
+      double h2 = 0.5 * c.ihz;
+      dzux = ((-3.0 * q0.ux + 4.0 * q1.ux) - q2.ux) * h2;
+      dzuz = ((-3.0 * q0.uz + 4.0 * q1.uz) - q2.uz) * h2;
+      dzT = ((-3.0 * q0.T + 4.0 * q1.T) - q2.T) * h2;
+    } else {
+      dzux = (q1.ux - q0.ux) * c.ihz;
+      dzuz = (q1.uz - q0.uz) * c.ihz;
+      dzT = (q1.T - q0.T) * c.ihz;
+    }
+    double dxux = (sh_dn(q0.ux) - sh_up(q0.ux)) * (0.5 * c.ihx);
+    double dxuz = (sh_dn(q0.uz) - sh_up(q0.uz)) * (0.5 * c.ihx);
+    st.F[e2] = flux_z2(c, st.x[c2], q0, dzux, dzuz, dzT, dxux, dxuz);
+  }
+  // C: predictor X^P_r = X_r - (tau/dz)(F_r - F_{r-1}) + tau S(X_r); plates:
+  //    u = 0, T = T_plate, top density from the backward mass-flux difference
+  if (r >= k0 - 1 && r >= 0 && r <= M) {
+    if (r == 0) {
+      double rho = st.x[c2].r;
+      st.xp[c2] = N2{rho, 0.0, 0.0, rho * (c.cv * c.Tb + c.g * zr[0])};
+      st.pp[c2] = P2{0.0, 0.0, c.Tb, c.a * rho * c.Tb};
+    } else if (r == M) {
+      double rho = st.x[c2].r - lz * (st.x[c2].mz - st.x[c3].mz);
+      st.xp[c2] = N2{rho, 0.0, 0.0, rho * (c.cv * c.Tt + c.g * zr[M])};
+      st.pp[c2] = P2{0.0, 0.0, c.Tt, c.a * rho * c.Tt};
+    } else {
+      N2 v = st.x[c2] - N2{lz * (st.F[e2].r - st.F[e3].r), lz * (st.F[e2].mx - st.F[e3].mx),
+                           lz * (st.F[e2].mz - st.F[e3].mz), lz * (st.F[e2].E - st.F[e3].E)};
+      v.mz = v.mz + tau * (-c.g * st.x[c2].r);
+      st.xp[c2] = v;
+      st.pp[c2] = prim2(c, v, zr[r]);
+    }
+  }
+  // D: corrector flux F^P_r (inner z backward; second-order backward at the
+  //    top plate when wall_order = 2), central x cross-derivatives of X^P
+  if (r >= k0 && r >= 1 && r <= M) {
+    const P2& q0 = st.pp[c2];
+    const P2& qm = st.pp[c3];
+    double dzux, dzuz, dzT;
+    if (r == M && c.wall_order == 2) {
+      const P2& qmm = st.pp[c4];
+      double h2 = 0.5 * c.ihz;
+      dzux = ((3.0 * q0.ux - 4.0 * qm.ux) + qmm.ux) * h2;
+      dzuz = ((3.0 * q0.uz - 4.0 * qm.uz) + qmm.uz) * h2;
+      dzT = ((3.0 * q0.T - 4.0 * qm.T) + qmm.T) * h2;
+    } else {
+      dzux = (q0.ux - qm.ux) * c.ihz;
+      dzuz = (q0.uz - qm.uz) * c.ihz;
+      dzT = (q0.T - qm.T) * c.ihz;
+    }
+    double dxux = (sh_dn(q0.ux) - sh_up(q0.ux)) * (0.5 * c.ihx);
+    double dxuz = (sh_dn(q0.uz) - sh_up(q0.uz)) * (0.5 * c.ihx);
+    st.FP[e2] = flux_z2(c, st.xp[c2], q0, dzux, dzuz, dzT, dxux, dxuz);
+  }
+  // E: TVD coefficient of face q+1/2, q = f-2 (zero on the two faces next
+  //    to the plates)
+  {
+    const int q = r;
+    if (q >= k0 - 1 && q >= 0 && q <= M - 1) {
+      double G = 0.0;
+      if (c.tvd_on && q >= 1 && q <= M - 2) {
+        const N2& dm = st.dl[c3];
+        const N2& d0 = st.dl[c2];
+        const N2& dp = st.dl[c1];
+        double Co = lz * fmax(st.s[c2], st.s[c1]);
+        G = tvd_G(c, dot2(dm, d0), dot2(d0, dp), dot2(d0, d0), Co);
+      }
+      st.G[c2] = G;
+    }
+  }
+  // F: corrector, average, TVD term and plate closure of row f-3
+  const int o = f - 3;
+  if (o >= k0 && o < k1) {
+    N2 out;
+    if (o == 0) {
+      double rho = st.x[c3].r - lz * (st.xp[c2].mz - 0.0);
+      out = N2{rho, 0.0, 0.0, rho * (c.cv * c.Tb + c.g * zr[0])};
+    } else if (o == M) {
+      double rho = st.xp[c3].r;
+      out = N2{rho, 0.0, 0.0, rho * (c.cv * c.Tt + c.g * zr[M])};
+    } else {
+      const N2& fp1 = st.FP[e2];
+      const N2& fp0 = st.FP[e3];
+      N2 xc = st.x[c3] - N2{lz * (fp1.r - fp0.r), lz * (fp1.mx - fp0.mx),
+                            lz * (fp1.mz - fp0.mz), lz * (fp1.E - fp0.E)};
+      xc.mz = xc.mz + tau * (-c.g * st.xp[c3].r);
+      const N2& d0 = st.dl[c3];
+      const N2& dm = st.dl[c4];
+      double G0 = st.G[c3], Gm = st.G[c4];
+      const N2& xp = st.xp[c3];
+      out.r = 0.5 * (xp.r + xc.r) + (G0 * d0.r - Gm * dm.r);
+      out.mx = 0.5 * (xp.mx + xc.mx) + (G0 * d0.mx - Gm * dm.mx);
+      out.mz = 0.5 * (xp.mz + xc.mz) + (G0 * d0.mz - Gm * dm.mz);
+      out.E = 0.5 * (xp.E + xc.E) + (G0 * d0.E - Gm * dm.E);
+    }
+    if (FUSE) out_max(c, out, zr[o], st.mx, st.mz, st.bad, L.out);
+    if (L.out) store2(c, Y, o, L.col, out);
+  }
+}
+
+template <bool FUSE>
+__global__ __launch_bounds__(256) void sweep_z2d(Coef c, Shared* sh, const double* zr,
+                                                 int slot, int first,
+                                                 const double* __restrict__ X,
+                                                 double* __restrict__ Y, int kc,
+                                                 int nstrips, int nwaves) {
+  const int lane = threadIdx.x & 63;
+  const int w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const double dt = step_dt(c, sh, slot);
+  step_head(c, sh, slot, first, dt);
+  if (w >= nwaves) return;
+  const int strip = w % nstrips, chunk = w / nstrips;
+  const Cols L = lane_cols(c, strip, lane);
+  const int k0 = chunk * kc;
+  const int k1 = min(k0 + kc, c.nz);
+  const double tau = 0.5 * dt;
+  const double lz = tau * c.ihz;
+  Z2 st;
+  st.mx = 0.0;
+  st.mz = 0.0;
+  st.bad = false;
+  const int fs = max(0, k0 - 2);
+  const int fe = k1 + 2;
+  for (int fb = fs & ~3; fb <= fe; fb += 4) {
+    z2_iter<0, FUSE>(c, st, fb + 0, fs, fe, k0, k1, L, zr, X, Y, tau, lz);
+    z2_iter<1, FUSE>(c, st, fb + 1, fs, fe, k0, k1, L, zr, X, Y, tau, lz);
+    z2_iter<2, FUSE>(c, st, fb + 2, fs, fe, k0, k1, L, zr, X, Y, tau, lz);
+    z2_iter<3, FUSE>(c, st, fb + 3, fs, fe, k0, k1, L, zr, X, Y, tau, lz);
+  }
+  if (FUSE) fold_max(sh, slot, st.mx, st.mz, st.bad);
+}
+
+// ---------------------------------------------------------------------------
+// L_x(tau): flux differences across lanes, cross z-derivatives from the
+// march.  Plate rows are copied through.
+
+struct X2 {
+  N2 x[4];
+  P2 pn[4];
+  double s[4];   // |u_x| + c of X^n
+  N2 xp[4];
+  P2 pp[4];
+  double mx, mz;
+  bool bad;
+};
+
+template <int S, bool FUSE>
+__device__ __forceinline__ void x2_iter(const Coef& c, X2& st, int f, int fs, int fe,
+                                        int k0, int k1, const Cols& L,
+                                        const double* __restrict__ zr,
+                                        const double* __restrict__ X,
+                                        double* __restrict__ Y, double lx) {
+  if (f < fs || f > fe) return;
+  const int M = c.M;
+  constexpr int c0 = S & 3;          // row f
+  constexpr int c1 = (S + 3) & 3;    // row f-1
+  constexpr int c2 = (S + 2) & 3;    // row f-2
+  constexpr int c3 = (S + 1) & 3;    // row f-3
+
+  if (f <= M) {
+    st.x[c0] = load2(c, X, f, L.col);
+    st.pn[c0] = prim2(c, st.x[c0], zr[f]);
+    st.s[c0] = fabs(st.pn[c0].ux) + sound(c, st.pn[c0].T);
+  }
+  // predictor on row f-1: X^P_i = X_i - (tau/dx)(F_i - F_{i-1})
+  const int r1 = f - 1;
+  if (r1 >= k0 - 1 && r1 >= 0 && r1 <= M) {
+    if (r1 == 0 || r1 == M) {
+      st.xp[c1] = st.x[c1];
+      st.pp[c1] = st.pn[c1];
+    } else {
+      const P2& q = st.pn[c1];
+      double dxux = (sh_dn(q.ux) - q.ux) * c.ihx;
+      double dxuz = (sh_dn(q.uz) - q.uz) * c.ihx;
+      double dxT = (sh_dn(q.T) - q.T) * c.ihx;
+      double dzux = (st.pn[c0].ux - st.pn[c2].ux) * (0.5 * c.ihz);
+      double dzuz = (st.pn[c0].uz - st.pn[c2].uz) * (0.5 * c.ihz);
+      N2 Fi = flux_x2(c, st.x[c1], q, dxux, dxuz, dxT, dzux, dzuz);
+      N2 Fm = sh_up(Fi);
+      N2 v = st.x[c1] - N2{lx * (Fi.r - Fm.r), lx * (Fi.mx - Fm.mx), lx * (Fi.mz - Fm.mz),
+                           lx * (Fi.E - Fm.E)};
+      st.xp[c1] = v;
+      st.pp[c1] = prim2(c, v, zr[r1]);
+    }
+  }
+  // corrector, average and TVD term on row f-2
+  const int r = f - 2;
+  if (r >= k0 && r < k1) {
+    N2 out;
+    if (r == 0 || r == M) {
+      out = st.x[c2];
+    } else {
+      const P2& q = st.pp[c2];
+      double dxux = (q.ux - sh_up(q.ux)) * c.ihx;
+      double dxuz = (q.uz - sh_up(q.uz)) * c.ihx;
+      double dxT = (q.T - sh_up(q.T)) * c.ihx;
+      double dzux = (st.pp[c1].ux - st.pp[c3].ux) * (0.5 * c.ihz);
+      double dzuz = (st.pp[c1].uz - st.pp[c3].uz) * (0.5 * c.ihz);
+      N2 Fi = flux_x2(c, st.xp[c2], q, dxux, dxuz, dxT, dzux, dzuz);
+      N2 Fp = sh_dn(Fi);
+      const N2& x0 = st.x[c2];
+      N2 xc = x0 - N2{lx * (Fp.r - Fi.r), lx * (Fp.mx - Fi.mx), lx * (Fp.mz - Fi.mz),
+                      lx * (Fp.E - Fi.E)};
+      // TVD: face i+1/2 belongs to lane i
+      N2 d0 = sh_dn(x0) - x0;
+      double G = 0.0;
+      if (c.tvd_on) {
+        N2 dm = sh_up(d0);
+        N2 dp = sh_dn(d0);
+        double Co = lx * fmax(st.s[c2], sh_dn(st.s[c2]));
+        G = tvd_G(c, dot2(dm, d0), dot2(d0, dp), dot2(d0, d0), Co);
+      }
+      N2 D{G * d0.r, G * d0.mx, G * d0.mz, G * d0.E};
+      N2 Dm = sh_up(D);
+      const N2& xp = st.xp[c2];
+      out.r = 0.5 * (xp.r + xc.r) + (D.r - Dm.r);
+      out.mx = 0.5 * (xp.mx + xc.mx) + (D.mx - Dm.mx);
+      out.mz = 0.5 * (xp.mz + xc.mz) + (D.mz - Dm.mz);
+      out.E = 0.5 * (xp.E + xc.E) + (D.E - Dm.E);
+    }
+    if (FUSE) out_max(c, out, zr[r], st.mx, st.mz, st.bad, L.out);
+    if (L.out) store2(c, Y, r, L.col, out);
+  }
+}
+
+template <bool FUSE>
+__global__ __launch_bounds__(256) void sweep_x2d(Coef c, Shared* sh, const double* zr,
+                                                 int slot, int first,
+                                                 const double* __restrict__ X,
+                                                 double* __restrict__ Y, int kc,
+                                                 int nstrips, int nwaves) {
+  const int lane = threadIdx.x & 63;
+  const int w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const double dt = step_dt(c, sh, slot);
+  step_head(c, sh, slot, first, dt);
+  if (w >= nwaves) return;
+  const int strip = w % nstrips, chunk = w / nstrips;
+  const Cols L = lane_cols(c, strip, lane);
+  const int k0 = chunk * kc;
+  const int k1 = min(k0 + kc, c.nz);
+  const double lx = 0.5 * dt * c.ihx;
+  X2 st;
+  st.mx = 0.0;
+  st.mz = 0.0;
+  st.bad = false;
+  const int fs = max(0, k0 - 2);
+  const int fe = k1 + 1;
+  for (int fb = fs & ~3; fb <= fe; fb += 4) {
+    x2_iter<0, FUSE>(c, st, fb + 0, fs, fe, k0, k1, L, zr, X, Y, lx);
+    x2_iter<1, FUSE>(c, st, fb + 1, fs, fe, k0, k1, L, zr, X, Y, lx);
+    x2_iter<2, FUSE>(c, st, fb + 2, fs, fe, k0, k1, L, zr, X, Y, lx);
+    x2_iter<3, FUSE>(c, st, fb + 3, fs, fe, k0, k1, L, zr, X, Y, lx);
+  }
+  if (FUSE) fold_max(sh, slot, st.mx, st.mz, st.bad);
+}
+
+// ---------------------------------------------------------------------------
+
+int strips_2d(int nx) { return (nx + kStrip - 1) / kStrip; }
+
+hipError_t launch_sweep_2d(int axis, const Coef& c, Shared* sh, const double* zr, int slot,
+                           int first, bool fuse, const double* X, double* Y, int kc,
+                           hipStream_t s) {
+  const int nstrips = strips_2d(c.nx);
+  const int nchunks = (c.nz + kc - 1) / kc;
+  const int nwaves = nstrips * nchunks;
+  const int block = 256;
+  const int grid = (nwaves + 3) / 4;
+  if (axis == 2) {
+    if (fuse)
+      sweep_z2d<true><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nwaves);
+    else
+      sweep_z2d<false><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nwaves);
+  } else {
+    if (fuse)
+      sweep_x2d<true><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nwaves);
+    else
+      sweep_x2d<false><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nwaves);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace mtvd

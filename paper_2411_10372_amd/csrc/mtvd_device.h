@@ -1,0 +1,153 @@
+// mtvd_device.h -- device-side pieces shared by the MacCormack-TVD kernels.
+//
+// Equations: Tiwari, Sharma & Verma, arXiv:2411.10372, Sec. 2 (p, E, tau_ij
+// of the nondimensional equations) and Sec. 3.1 (fluxes F_alpha, the TVD
+// coefficient G, phi and C).  All arithmetic is FP64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mtvd {
+
+// Constants of one problem, passed by value to every kernel.
+struct Coef {
+  int nx, ny, nz, M;            // M = nz - 1
+  int ndim, nf;
+  long long plane;              // nx * ny
+  long long cnt;                // nodes = plane * nz (field stride)
+  double hx, hy, hz;            // spacings
+  double ihx, ihy, ihz;         // 1/h
+  double gamma, cv, icv;        // c_v = 1/(gamma eps D), icv = 1/c_v
+  double a;                     // p = a rho T, a = (gamma-1)/(gamma eps D)
+  double gam_a;                 // c^2 = gamma a T
+  double g;                     // gravity: momentum source -g rho, E has g z
+  double mu, K, lam;            // sqrt(Pr/Ra), 1/(eps D sqrt(Ra Pr)), bulk coef
+  double Tb, Tt;                // plate temperatures 1 and 1 - (eps + D)
+  double cfl;
+  double D, eps, sRP;           // D, eps, sqrt(Ra Pr) (diagnostics)
+  double init_delta, init_expo; // T0 = 1 - delta z, rho0 = T0^expo
+  double noise_amp;
+  uint64_t seed;
+  int limiter_form, tvd_on, wall_order, dt_mode;
+};
+
+// Scalars the kernels share through the workspace.
+struct Shared {
+  unsigned long long smax[2][4];  // max over nodes of |u_a| + c (bit patterns
+                                  // of positive doubles), two step slots
+  double time;                    // simulated time of the current state
+  double dt_last;                 // dt used by the latest step
+  double dt_frozen;               // dt when dt_mode = 1
+  unsigned int flags;             // bit 0: non-finite / non-positive seen
+  unsigned int pad[7];
+};
+
+__device__ __forceinline__ double u2d(unsigned long long b) {
+  return __longlong_as_double((long long)b);
+}
+__device__ __forceinline__ unsigned long long d2u(double d) {
+  return (unsigned long long)__double_as_longlong(d);
+}
+
+// dt of the current step from the maxima in `slot` (or the frozen value):
+// dt = cfl * min_a h_a / max_nodes(|u_a| + c), the same number as the
+// minimum over nodes of h_a/(|u_a| + c) because division by a positive
+// number is monotone.
+__device__ __forceinline__ double step_dt(const Coef& c, const Shared* sh, int slot) {
+  if (c.dt_mode) return sh->dt_frozen;
+  double m = c.hx / u2d(sh->smax[slot][0]);
+  double mz = c.hz / u2d(sh->smax[slot][2]);
+  m = fmin(m, mz);
+  if (c.ndim == 3) m = fmin(m, c.hy / u2d(sh->smax[slot][1]));
+  return c.cfl * m;
+}
+
+// ---- 2D node values -------------------------------------------------------
+
+struct N2 { double r, mx, mz, E; };
+struct P2 { double ux, uz, T, p; };
+
+__device__ __forceinline__ N2 operator-(const N2& a, const N2& b) {
+  return N2{a.r - b.r, a.mx - b.mx, a.mz - b.mz, a.E - b.E};
+}
+
+// primitives (Sec. 2): u = m/rho, T = (E/rho - |u|^2/2 - g z)/c_v, p = a rho T
+__device__ __forceinline__ P2 prim2(const Coef& c, const N2& x, double z) {
+  double ri = 1.0 / x.r;
+  P2 q;
+  q.ux = x.mx * ri;
+  q.uz = x.mz * ri;
+  double ke = 0.5 * (q.ux * q.ux + q.uz * q.uz);
+  q.T = (x.E * ri - ke - c.g * z) * c.icv;
+  q.p = c.a * x.r * q.T;
+  return q;
+}
+
+// sound speed c = sqrt(gamma p / rho) = sqrt(gamma a T)
+__device__ __forceinline__ double sound(const Coef& c, double T) {
+  return sqrt(c.gam_a * T);
+}
+
+// Flux along z (Sec. 3.1 F_3; tau_zz, tau_xz of Sec. 2) given the inner
+// z-derivatives (dzux, dzuz, dzT) and central x-derivatives (dxux, dxuz).
+__device__ __forceinline__ N2 flux_z2(const Coef& c, const N2& x, const P2& q,
+                                      double dzux, double dzuz, double dzT,
+                                      double dxux, double dxuz) {
+  double div = dxux + dzuz;
+  double tzz = c.mu * ((dzuz + dzuz) + c.lam * div);
+  double txz = c.mu * (dzux + dxuz);
+  N2 F;
+  F.r = x.mz;
+  F.mx = x.mx * q.uz - txz;
+  F.mz = (x.mz * q.uz - tzz) + q.p;
+  F.E = (q.uz * (x.E + q.p) - c.K * dzT) - (q.ux * txz + q.uz * tzz);
+  return F;
+}
+
+// Flux along x (Sec. 3.1 F_1; tau_xx, tau_zx of Sec. 2) given the inner
+// x-derivatives and central z-derivatives.
+__device__ __forceinline__ N2 flux_x2(const Coef& c, const N2& x, const P2& q,
+                                      double dxux, double dxuz, double dxT,
+                                      double dzux, double dzuz) {
+  double div = dxux + dzuz;
+  double txx = c.mu * ((dxux + dxux) + c.lam * div);
+  double tzx = c.mu * (dxuz + dzux);
+  N2 F;
+  F.r = x.mx;
+  F.mx = (x.mx * q.ux - txx) + q.p;
+  F.mz = x.mz * q.ux - tzx;
+  F.E = (q.ux * (x.E + q.p) - c.K * dxT) - (q.ux * txx + q.uz * tzx);
+  return F;
+}
+
+// phi(x) = max(0, min(2x, 1))  (Sec. 3.1)
+__device__ __forceinline__ double phi(double x) { return fmax(0.0, fmin(2.0 * x, 1.0)); }
+
+// TVD coefficient G of the face between two nodes (Sec. 3.1): a_m, a_p are
+// the dot products dX_{-1/2}.dX_{+1/2} and dX_{+1/2}.dX_{+3/2}, den the
+// squared norm of dX_{+1/2}; Co = lam_h * max(|u|+c) over the two nodes.  A
+// face with den == 0 has no TVD flux.
+__device__ __forceinline__ double tvd_G(const Coef& c, double a_m, double a_p,
+                                        double den, double Co) {
+  if (den == 0.0) return 0.0;
+  double C = (Co <= 0.5) ? Co * (1.0 - Co) : 0.25;
+  double id = 1.0 / den;
+  if (c.limiter_form == 0) {
+    return 0.5 * C * (1.0 - phi(a_m * id + a_p * id));
+  }
+  return 0.5 * C * (1.0 - phi(a_m * id)) + 0.5 * C * (1.0 - phi(a_p * id));
+}
+
+__device__ __forceinline__ double dot2(const N2& a, const N2& b) {
+  return ((a.r * b.r + a.mx * b.mx) + a.mz * b.mz) + a.E * b.E;
+}
+
+// wave-wide max (64 lanes)
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+}  // namespace mtvd

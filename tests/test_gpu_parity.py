@@ -1,0 +1,263 @@
+"""GPU (HIP, through the C ABI) against the CPU oracle, element by element.
+
+Bar (parity error of tests/helpers.parity_error): <= 1e-13 after one
+operator or one step, <= 1e-10 after 200 steps of the 256x64 case;
+diagnostics <= 1e-12 relative.  Grids are chosen to span several 60-column
+strips with a ragged last strip and several row chunks with a ragged last
+chunk; the minimum grid (nz = 5) and grids narrower than a wave are edge
+cases.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import both, gpu_or_skip, parity_error
+from inputs import perturb, roll_x
+
+pytestmark = pytest.mark.gpu
+
+SWEEP_TOL = 1e-13
+
+
+def _solver(pg, tiling=None):
+    gpu_or_skip()
+    import paper_2411_10372_amd as mtvd
+    s = mtvd.Solver(pg)
+    if tiling is not None:
+        s.set_tiling(*tiling)
+    return s
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# initial state and dt
+
+
+@pytest.mark.parametrize("nx,nz,seed", [(256, 64, 0), (150, 37, 3), (4096, 1024, 1)])
+def test_init_state_matches_oracle(nx, nz, seed):
+    _say("init", nx, nz, seed)
+    po, pg = both(nx=nx, nz=nz, seed=seed, Ra=1e6)
+    s = _solver(pg)
+    s.init_state()
+    Xg = s.get_state()
+    Xo = oracle.init(po)
+    # identical noise bits; rho = pow(T0, m-1) may differ by an ulp
+    assert np.array_equal(Xg[1], Xo[1]) and np.array_equal(Xg[2], Xo[2])
+    assert np.max(np.abs(Xg[0] - Xo[0]) / Xo[0]) <= 4e-16
+    assert np.max(np.abs(Xg[3] - Xo[3]) / Xo[3]) <= 8e-16
+    d = s.diagnostics()
+    assert abs(d["dt"] - oracle.dt(po, Xo)) <= 1e-14 * d["dt"]
+    assert d["time"] == 0.0 and d["step"] == 0
+
+
+# ---------------------------------------------------------------------------
+# one directional operator at a time
+
+
+SWEEP_GRIDS = [(150, 37), (8, 5), (60, 9), (61, 11), (121, 16), (64, 64)]
+
+
+@pytest.mark.parametrize("axis", [0, 2])
+@pytest.mark.parametrize("nx,nz", SWEEP_GRIDS)
+@pytest.mark.parametrize("rows", [0, 1, 3])
+def test_single_operator_parity(axis, nx, nz, rows):
+    _say("sweep", axis, nx, nz, rows)
+    po, pg = both(nx=nx, nz=nz, Ra=1e5, seed=5)
+    X0 = perturb(oracle.init(po), seed=nx * 31 + nz, amp=0.03)
+    s = _solver(pg, (rows, rows))
+    s.set_state(X0)
+    s.sweep(axis)
+    Xg = s.get_state()
+    Xo = oracle.sweep(po, axis, 0.5 * oracle.dt(po, X0), X0)
+    e = parity_error(Xg, Xo, po)
+    assert e <= SWEEP_TOL, e
+
+
+KNOBS = [
+    {},
+    {"limiter_form": 1},
+    {"sweep_order": 1},
+    {"tvd_on": 0},
+    {"wall_order": 1},
+    {"dt_mode": 1},
+    {"bulk_coef": 2.0 / 3.0},
+    {"gravity_scale": 0.0},
+]
+
+
+@pytest.mark.parametrize("knobs", KNOBS, ids=lambda k: ",".join(f"{a}={b:g}" for a, b in k.items()) or "default")
+def test_steps_parity_with_reading_knobs(knobs):
+    _say("knobs", knobs)
+    po, pg = both(nx=150, nz=37, Ra=1e5, seed=8, **knobs)
+    X0 = perturb(oracle.init(po), seed=17, amp=0.02)
+    s = _solver(pg, (5, 6))
+    s.set_state(X0)
+    s.step(3)
+    Xg = s.get_state()
+    Xo, t, dt = oracle.step(po, X0, 3)
+    e = parity_error(Xg, Xo, po)
+    assert e <= 3 * SWEEP_TOL, e
+    d = s.diagnostics()
+    assert abs(d["time"] - t) <= 1e-14 * t
+
+
+# ---------------------------------------------------------------------------
+# the 256 x 64 case: 1 step and 200 steps from the GPU's own initial state
+
+
+def test_256x64_one_and_200_steps():
+    from paper_2411_10372_amd.workloads import params_dict
+    kw = params_dict("2d_256x64_ra1e6")
+    po, pg = both(**kw)
+    s = _solver(pg)
+    s.init_state()
+    Xo = oracle.init(po)
+    _say("256x64 step 1")
+    s.step(1)
+    Xo1, t1, _ = oracle.step(po, Xo, 1)
+    e1 = parity_error(s.get_state(), Xo1, po)
+    assert e1 <= SWEEP_TOL, e1
+    _say("256x64 steps 2..200")
+    s.step(199)
+    Xo200, t200, dt200 = oracle.step(po, Xo1, 199, time=t1)
+    Xg200 = s.get_state()
+    e200 = parity_error(Xg200, Xo200, po)
+    print("parity e after 1 step", e1, "after 200 steps", e200, flush=True)
+    assert e200 <= 1e-10, e200
+    dg = s.diagnostics()
+    do = oracle.diag(po, Xo200)
+    assert dg["step"] == 200
+    assert abs(dg["time"] - t200) <= 1e-13 * t200
+    for k in ("mass", "kinetic", "total_energy", "nu_bottom", "nu_top", "nu_mean"):
+        assert abs(dg[k] - do[k]) <= 1e-12 * abs(do[k]), (k, dg[k], do[k])
+    # bulk Nu terms are tiny differences of large sums: absolute bound
+    for k in ("nu_bulk", "nu_conv"):
+        assert abs(dg[k] - do[k]) <= 1e-10, (k, dg[k], do[k])
+
+
+# ---------------------------------------------------------------------------
+# the 4096 x 1024 case in the launch configuration the benchmark times
+
+
+def test_4096x1024_two_steps_full_field():
+    from paper_2411_10372_amd.workloads import params_dict
+    kw = params_dict("2d_4096x1024_ra1e10")
+    po, pg = both(**kw)
+    s = _solver(pg)
+    s.init_state()
+    _say("4096x1024 two steps")
+    s.step(2)
+    Xg = s.get_state()
+    Xo, t, _ = oracle.step(po, oracle.init(po), 2)
+    e = parity_error(Xg, Xo, po)
+    print("4096x1024 parity e after 2 steps", e, flush=True)
+    assert e <= 2 * SWEEP_TOL, e
+    d = s.diagnostics()
+    do = oracle.diag(po, Xo)
+    assert abs(d["mass"] - do["mass"]) <= 1e-13 * do["mass"]
+    assert abs(d["nu_mean"] - do["nu_mean"]) <= 1e-12 * abs(do["nu_mean"])
+
+
+# ---------------------------------------------------------------------------
+# invariants that need no oracle
+
+
+def test_bitwise_determinism():
+    _, pg = both(nx=256, nz=64, Ra=1e6, seed=3, noise_amp=1e-2)
+    a, b = _solver(pg), _solver(pg)
+    a.init_state()
+    b.init_state()
+    a.step(50)
+    b.step(50)
+    assert np.array_equal(a.get_state(), b.get_state())
+
+
+def test_x_uniform_state_stays_uniform_on_gpu():
+    _, pg = both(nx=256, nz=64, Ra=1e6, noise_amp=0.0)
+    s = _solver(pg)
+    s.init_state()
+    s.step(20)
+    X = s.get_state()
+    assert np.all(X == X[:, :, :1])
+
+
+@pytest.mark.parametrize("shift", [37, 60, 1])
+def test_translation_equivariance_on_gpu(shift):
+    """Tile seams: a shifted start gives the shifted result, bit for bit."""
+    po, pg = both(nx=256, nz=40, Ra=1e5, seed=2, noise_amp=1e-2)
+    X0 = perturb(oracle.init(po), seed=4, amp=0.02)
+    a, b = _solver(pg), _solver(pg)
+    a.set_state(X0)
+    b.set_state(roll_x(X0, shift))
+    a.step(5)
+    b.step(5)
+    assert np.array_equal(roll_x(a.get_state(), shift), b.get_state())
+
+
+def test_mass_conserved_on_gpu():
+    _, pg = both(nx=256, nz=64, Ra=1e6, seed=0, noise_amp=1e-2)
+    s = _solver(pg)
+    s.init_state()
+    m0 = s.diagnostics()["mass"]
+    s.step(200)
+    m1 = s.diagnostics()["mass"]
+    assert abs(m1 - m0) / m0 <= 1e-13
+
+
+def test_conduction_nu_is_one_on_gpu():
+    _, pg = both(nx=128, nz=33, Ra=1e6, noise_amp=0.0)
+    s = _solver(pg)
+    s.init_state()
+    d = s.diagnostics()
+    for k in ("nu_bottom", "nu_top", "nu_mean", "nu_bulk"):
+        assert abs(d[k] - 1.0) < 1e-12, (k, d[k])
+
+
+def test_restart_is_bitwise():
+    """200 steps = 100 steps, save, restore, 100 steps (checkpoint/resume)."""
+    _, pg = both(nx=256, nz=64, Ra=1e6, seed=6)
+    a = _solver(pg)
+    a.init_state()
+    a.step(100)
+    mid = a.get_state()
+    d_mid = a.diagnostics()
+    a.step(100)
+    b = _solver(pg)
+    b.set_state(mid, time=d_mid["time"], step=100)
+    b.step(100)
+    assert np.array_equal(a.get_state(), b.get_state())
+    assert b.diagnostics()["step"] == 200
+
+
+# ---------------------------------------------------------------------------
+# failure handling (conditions forced from the host)
+
+
+def test_errors_are_reported_not_crashes():
+    import paper_2411_10372_amd as mtvd
+    _, pg = both(nx=64, nz=9, Ra=1e5)
+    s = _solver(pg)
+    with pytest.raises(mtvd.MtvdError) as ei:
+        s.step(1)
+    assert ei.value.code == mtvd.MTVD_ESTATE
+    po, _ = both(nx=64, nz=9, Ra=1e5)
+    X = oracle.init(po)
+    X[0, 4, 10] = np.nan
+    s.set_state(X)
+    with pytest.raises(mtvd.MtvdError) as ei:
+        s.diagnostics()
+    assert ei.value.code == mtvd.MTVD_ENONFINITE
+    X = oracle.init(po)
+    X[0, 3, 7] = -1.0
+    s.set_state(X)
+    with pytest.raises(mtvd.MtvdError) as ei:
+        s.sync()
+    assert ei.value.code == mtvd.MTVD_ENONFINITE
+    X = oracle.init(po)
+    s.set_state(X)
+    s.sync()
+    with pytest.raises(ValueError):
+        s.set_state(X[:, :-1])
