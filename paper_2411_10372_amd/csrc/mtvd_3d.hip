@@ -1,11 +1,601 @@
-// mtvd_3d.hip -- 3D sweep kernels (placeholder until the 3D kernels land).
+// mtvd_3d.hip -- fused predictor/corrector/TVD kernels of the directional
+// operators L_x, L_y, L_z in 3D (Sec. 3.1 of arXiv:2411.10372).
+//
+// Launch shape: a block of kNW = 8 waves.  Lanes run along x (60 output
+// columns per wave plus two halo columns each side, exchanged with
+// cross-lane shuffles); each wave marches along one axis with its values
+// in period-4 register rings; the 8 waves of a block sit at consecutive
+// indices of the third axis, 4 of them produce output and 2 on each side
+// are halo, and they exchange two scalars per row through LDS.
+//   L_z: march z (flux direction, plates), waves along y (periodic)
+//   L_y: march y (flux direction, periodic), waves along z (plate rows are
+//        copied through; waves outside the plates idle)
+//   L_x: flux across lanes, march z, waves along y
+// Every kernel reads and writes each field of each node once (5 fields x 8 B
+// in and out); halo re-reads hit in L2.
+#include "mtvd_device.h"
 #include "mtvd_launch.h"
 
 namespace mtvd {
 
-hipError_t launch_sweep_3d(int, const Coef&, Shared*, const double*, int, int, bool,
-                           const double*, double*, int, hipStream_t) {
-  return hipErrorNotSupported;
+constexpr int kStrip3 = 60;
+constexpr int kNW = 8;
+
+struct N3 { double r, m[3], E; };
+struct P3 { double u[3], T, p; };
+
+__device__ __forceinline__ N3 sub3(const N3& a, const N3& b) {
+  return N3{a.r - b.r, {a.m[0] - b.m[0], a.m[1] - b.m[1], a.m[2] - b.m[2]}, a.E - b.E};
+}
+
+__device__ __forceinline__ P3 prim3(const Coef& c, const N3& x, double z) {
+  double ri = 1.0 / x.r;
+  P3 q;
+  q.u[0] = x.m[0] * ri;
+  q.u[1] = x.m[1] * ri;
+  q.u[2] = x.m[2] * ri;
+  double ke = 0.5 * ((q.u[0] * q.u[0] + q.u[1] * q.u[1]) + q.u[2] * q.u[2]);
+  q.T = (x.E * ri - ke - c.g * z) * c.icv;
+  q.p = c.a * x.r * q.T;
+  return q;
+}
+
+__device__ __forceinline__ double dot3(const N3& a, const N3& b) {
+  return (((a.r * b.r + a.m[0] * b.m[0]) + a.m[1] * b.m[1]) + a.m[2] * b.m[2]) + a.E * b.E;
+}
+
+// Flux F_AL (Sec. 3.1) from the velocity gradient du[g][d] = d_d u_g and
+// d_AL T; only the entries the flux uses are read: du[g][AL] (inner),
+// du[AL][g] (cross) and the diagonal (divergence).
+template <int AL>
+__device__ __forceinline__ N3 flux3(const Coef& c, const N3& x, const P3& q,
+                                    const double (&du)[3][3], double dT) {
+  double div = (du[0][0] + du[1][1]) + du[2][2];
+  double tau[3];
+#pragma unroll
+  for (int g = 0; g < 3; ++g) {
+    if (g == AL)
+      tau[g] = c.mu * ((du[AL][AL] + du[AL][AL]) + c.lam * div);
+    else
+      tau[g] = c.mu * (du[g][AL] + du[AL][g]);
+  }
+  const double ua = q.u[AL];
+  N3 F;
+  F.r = x.m[AL];
+#pragma unroll
+  for (int g = 0; g < 3; ++g) {
+    double v = x.m[g] * ua - tau[g];
+    if (g == AL) v = v + q.p;
+    F.m[g] = v;
+  }
+  double work = (q.u[0] * tau[0] + q.u[1] * tau[1]) + q.u[2] * tau[2];
+  F.E = (ua * (x.E + q.p) - c.K * dT) - work;
+  return F;
+}
+
+__device__ __forceinline__ double shd(double v) { return __shfl_down(v, 1, 64); }
+__device__ __forceinline__ double shu(double v) { return __shfl_up(v, 1, 64); }
+__device__ __forceinline__ N3 shd(const N3& v) {
+  return N3{shd(v.r), {shd(v.m[0]), shd(v.m[1]), shd(v.m[2])}, shd(v.E)};
+}
+__device__ __forceinline__ N3 shu(const N3& v) {
+  return N3{shu(v.r), {shu(v.m[0]), shu(v.m[1]), shu(v.m[2])}, shu(v.E)};
+}
+
+struct Lane3 {
+  int col;
+  bool out;
+};
+
+__device__ __forceinline__ Lane3 lane3(const Coef& c, int strip, int lane) {
+  Lane3 r;
+  int i0 = strip * kStrip3;
+  int i = i0 - 2 + lane;
+  int m = i % c.nx;
+  r.col = (m < 0) ? m + c.nx : m;
+  r.out = lane >= 2 && lane < 62 && (i0 + lane - 2) < c.nx;
+  return r;
+}
+
+__device__ __forceinline__ int wrap(int v, int n) {
+  int m = v % n;
+  return m < 0 ? m + n : m;
+}
+
+__device__ __forceinline__ N3 load3(const Coef& c, const double* __restrict__ X,
+                                    long long n) {
+  N3 v;
+  v.r = X[n];
+  v.m[0] = X[n + c.cnt];
+  v.m[1] = X[n + 2 * c.cnt];
+  v.m[2] = X[n + 3 * c.cnt];
+  v.E = X[n + 4 * c.cnt];
+  return v;
+}
+
+__device__ __forceinline__ void store3(const Coef& c, double* __restrict__ Y, long long n,
+                                       const N3& v) {
+  Y[n] = v.r;
+  Y[n + c.cnt] = v.m[0];
+  Y[n + 2 * c.cnt] = v.m[1];
+  Y[n + 3 * c.cnt] = v.m[2];
+  Y[n + 4 * c.cnt] = v.E;
+}
+
+// Two scalars of every wave to LDS, barrier, and their central differences
+// across neighbouring waves (dual buffers alternate so one barrier per
+// exchange suffices).
+__device__ __forceinline__ void exchange(double (&buf)[2][kNW][64], int w, int lane,
+                                         double a, double b, double ih2, double& da,
+                                         double& db) {
+  buf[0][w][lane] = a;
+  buf[1][w][lane] = b;
+  __syncthreads();
+  const int wm = (w > 0) ? w - 1 : w;
+  const int wp = (w < kNW - 1) ? w + 1 : w;
+  da = (buf[0][wp][lane] - buf[0][wm][lane]) * ih2;
+  db = (buf[1][wp][lane] - buf[1][wm][lane]) * ih2;
+}
+
+struct Acc3 {
+  double s[3];
+  bool bad;
+};
+
+__device__ __forceinline__ void acc_out(const Coef& c, const N3& o, double z, Acc3& a,
+                                        bool on) {
+  P3 q = prim3(c, o, z);
+  double cs = sound(c, q.T);
+  double s0 = fabs(q.u[0]) + cs, s1 = fabs(q.u[1]) + cs, s2 = fabs(q.u[2]) + cs;
+  if (on) {
+    a.s[0] = fmax(a.s[0], s0);
+    a.s[1] = fmax(a.s[1], s1);
+    a.s[2] = fmax(a.s[2], s2);
+    if (!(o.r > 0.0) || !(q.T > 0.0) || !(s0 < INFINITY) || !(s1 < INFINITY) ||
+        !(s2 < INFINITY))
+      a.bad = true;
+  }
+}
+
+__device__ __forceinline__ void fold3(Shared* sh, int slot, Acc3& a) {
+  double m0 = wave_max(a.s[0]), m1 = wave_max(a.s[1]), m2 = wave_max(a.s[2]);
+  unsigned long long anybad = __ballot(a.bad);
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(&sh->smax[slot ^ 1][0], d2u(m0));
+    atomicMax(&sh->smax[slot ^ 1][1], d2u(m1));
+    atomicMax(&sh->smax[slot ^ 1][2], d2u(m2));
+    if (anybad) atomicOr(&sh->flags, 1u);
+  }
+}
+
+__device__ __forceinline__ void head3(Shared* sh, int slot, int first, double dt) {
+  if (first && blockIdx.x == 0 && threadIdx.x == 0) {
+    sh->time += dt;
+    sh->dt_last = dt;
+    for (int a = 0; a < 4; ++a) sh->smax[slot ^ 1][a] = 0ull;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// L_z and L_y: flux along the march.  AX = 2: march z, waves along y;
+// AX = 1: march y, waves along z.
+
+struct MF {
+  N3 x[4];
+  P3 pn[4];
+  double s[4];             // |u_AX| + c of X^n
+  double bb[4], bm[4];     // d_B u_B and d_B u_AX of X^n (across waves)
+  N3 dl[4];                // dX_{row+1/2}
+  double G[4];
+  N3 F[2];
+  N3 xp[4];
+  P3 pp[4];
+  double pb[4], pm[4];     // d_B u_B and d_B u_AX of X^P
+  N3 FP[2];
+  Acc3 acc;
+};
+
+template <int AX, int S, bool FUSE>
+__device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, int fe, int m0,
+                                        int m1, int w, int lane, const Lane3& L, int bidx,
+                                        bool bval, bool bwall, bool owave,
+                                        double (&xa)[2][kNW][64], double (&xb)[2][kNW][64],
+                                        const double* __restrict__ zr,
+                                        const double* __restrict__ X, double* __restrict__ Y,
+                                        double tau, double lm) {
+  if (f < fs || f > fe) return;
+  constexpr int B = (AX == 2) ? 1 : 2;   // axis of the waves
+  const int M = c.M;
+  const double ihm = (AX == 2) ? c.ihz : c.ihy;
+  const double ihb2 = 0.5 * ((B == 1) ? c.ihy : c.ihz);
+  constexpr int c0 = S & 3, c1 = (S + 3) & 3, c2 = (S + 2) & 3, c3 = (S + 1) & 3, c4 = S & 3;
+  constexpr int e2 = S & 1, e3 = (S + 1) & 1;
+  const int role = (w == 0 || w == kNW - 1) ? 0 : ((w == 1 || w == kNW - 2) ? 1 : 2);
+  // node of march row `row`
+  auto node = [&](int row) -> long long {
+    if (AX == 2) return ((long long)row * c.ny + bidx) * c.nx + L.col;
+    return ((long long)bidx * c.ny + wrap(row, c.ny)) * c.nx + L.col;
+  };
+  auto zof = [&](int row) -> double { return (AX == 2) ? zr[row] : zr[bidx]; };
+
+  // A: row f of X^n, its primitives, dX of face f-1/2; exchange across waves
+  const bool have_f = (AX == 2) ? (f <= M) : true;
+  if (have_f) {
+    if (bval) {
+      st.x[c0] = load3(c, X, node(f));
+      st.pn[c0] = prim3(c, st.x[c0], zof(f));
+      st.s[c0] = fabs(st.pn[c0].u[AX]) + sound(c, st.pn[c0].T);
+      if (f - 1 >= fs) st.dl[c1] = sub3(st.x[c0], st.x[c1]);
+    }
+    double ub = bval ? st.pn[c0].u[B] : 0.0, um = bval ? st.pn[c0].u[AX] : 0.0;
+    exchange(xa, w, lane, ub, um, ihb2, st.bb[c0], st.bm[c0]);
+  }
+  const int r = f - 2;
+  const bool rin_F = (AX == 2) ? (r >= 0 && r <= M - 1) : true;
+  // B: predictor flux F_r (inner derivatives forward along the march)
+  if (r >= m0 - 2 && rin_F && role >= 1 && bval && !bwall) {
+    const P3& q0 = st.pn[c2];
+    const P3& q1 = st.pn[c1];
+    double du[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    double dT;
+    if (AX == 2 && r == 0 && c.wall_order == 2) {
+      const P3& q2 = st.pn[c0];
+      double h2 = 0.5 * ihm;
+#pragma unroll
+      for (int g = 0; g < 3; ++g) du[g][AX] = ((-3.0 * q0.u[g] + 4.0 * q1.u[g]) - q2.u[g]) * h2;
+      dT = ((-3.0 * q0.T + 4.0 * q1.T) - q2.T) * h2;
+    } else {
+#pragma unroll
+      for (int g = 0; g < 3; ++g) du[g][AX] = (q1.u[g] - q0.u[g]) * ihm;
+      dT = (q1.T - q0.T) * ihm;
+    }
+    du[0][0] = (shd(q0.u[0]) - shu(q0.u[0])) * (0.5 * c.ihx);
+    du[AX][0] = (shd(q0.u[AX]) - shu(q0.u[AX])) * (0.5 * c.ihx);
+    du[B][B] = st.bb[c2];
+    du[AX][B] = st.bm[c2];
+    st.F[e2] = flux3<AX>(c, st.x[c2], q0, du, dT);
+  }
+  // C: predictor X^P_r; exchange its velocities across waves
+  const bool rin_P = (AX == 2) ? (r >= 0 && r <= M) : true;
+  if (r >= m0 - 1 && rin_P) {
+    if (role >= 1 && bval) {
+      if (bwall) {
+        st.xp[c2] = st.x[c2];
+        st.pp[c2] = st.pn[c2];
+      } else if (AX == 2 && r == 0) {
+        double rho = st.x[c2].r;
+        st.xp[c2] = N3{rho, {0.0, 0.0, 0.0}, rho * (c.cv * c.Tb + c.g * zr[0])};
+        st.pp[c2] = P3{{0.0, 0.0, 0.0}, c.Tb, c.a * rho * c.Tb};
+      } else if (AX == 2 && r == M) {
+        double rho = st.x[c2].r - lm * (st.x[c2].m[2] - st.x[c3].m[2]);
+        st.xp[c2] = N3{rho, {0.0, 0.0, 0.0}, rho * (c.cv * c.Tt + c.g * zr[M])};
+        st.pp[c2] = P3{{0.0, 0.0, 0.0}, c.Tt, c.a * rho * c.Tt};
+      } else {
+        const N3& Fa = st.F[e2];
+        const N3& Fb = st.F[e3];
+        const N3& x0 = st.x[c2];
+        N3 v;
+        v.r = x0.r - lm * (Fa.r - Fb.r);
+#pragma unroll
+        for (int g = 0; g < 3; ++g) v.m[g] = x0.m[g] - lm * (Fa.m[g] - Fb.m[g]);
+        v.E = x0.E - lm * (Fa.E - Fb.E);
+        if (AX == 2) v.m[2] = v.m[2] + tau * (-c.g * x0.r);
+        st.xp[c2] = v;
+        st.pp[c2] = prim3(c, v, zof(r));
+      }
+    }
+    double ub = (role >= 1 && bval) ? st.pp[c2].u[B] : 0.0;
+    double um = (role >= 1 && bval) ? st.pp[c2].u[AX] : 0.0;
+    exchange(xb, w, lane, ub, um, ihb2, st.pb[c2], st.pm[c2]);
+  }
+  // D: corrector flux F^P_r (inner derivatives backward along the march)
+  const bool rin_FP = (AX == 2) ? (r >= 1 && r <= M) : true;
+  if (r >= m0 && rin_FP && role == 2 && bval && !bwall) {
+    const P3& q0 = st.pp[c2];
+    const P3& qm = st.pp[c3];
+    double du[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    double dT;
+    if (AX == 2 && r == M && c.wall_order == 2) {
+      const P3& qmm = st.pp[c4];
+      double h2 = 0.5 * ihm;
+#pragma unroll
+      for (int g = 0; g < 3; ++g) du[g][AX] = ((3.0 * q0.u[g] - 4.0 * qm.u[g]) + qmm.u[g]) * h2;
+      dT = ((3.0 * q0.T - 4.0 * qm.T) + qmm.T) * h2;
+    } else {
+#pragma unroll
+      for (int g = 0; g < 3; ++g) du[g][AX] = (q0.u[g] - qm.u[g]) * ihm;
+      dT = (q0.T - qm.T) * ihm;
+    }
+    du[0][0] = (shd(q0.u[0]) - shu(q0.u[0])) * (0.5 * c.ihx);
+    du[AX][0] = (shd(q0.u[AX]) - shu(q0.u[AX])) * (0.5 * c.ihx);
+    du[B][B] = st.pb[c2];
+    du[AX][B] = st.pm[c2];
+    st.FP[e2] = flux3<AX>(c, st.xp[c2], q0, du, dT);
+  }
+  // E: TVD coefficient of face r+1/2 along the march
+  const bool rin_G = (AX == 2) ? (r >= 0 && r <= M - 1) : true;
+  if (r >= m0 - 1 && rin_G && role == 2 && bval && !bwall) {
+    double G = 0.0;
+    const bool active = (AX == 2) ? (r >= 1 && r <= M - 2) : true;
+    if (c.tvd_on && active) {
+      const N3& dm = st.dl[c3];
+      const N3& d0 = st.dl[c2];
+      const N3& dp = st.dl[c1];
+      double Co = lm * fmax(st.s[c2], st.s[c1]);
+      G = tvd_G(c, dot3(dm, d0), dot3(d0, dp), dot3(d0, d0), Co);
+    }
+    st.G[c2] = G;
+  }
+  // F: output row f-3
+  const int o = f - 3;
+  if (o >= m0 && o < m1 && owave) {
+    N3 out;
+    if (bwall) {
+      out = st.x[c3];
+    } else if (AX == 2 && o == 0) {
+      double rho = st.x[c3].r - lm * (st.xp[c2].m[2] - 0.0);
+      out = N3{rho, {0.0, 0.0, 0.0}, rho * (c.cv * c.Tb + c.g * zr[0])};
+    } else if (AX == 2 && o == M) {
+      double rho = st.xp[c3].r;
+      out = N3{rho, {0.0, 0.0, 0.0}, rho * (c.cv * c.Tt + c.g * zr[M])};
+    } else {
+      const N3& fp1 = st.FP[e2];
+      const N3& fp0 = st.FP[e3];
+      const N3& x0 = st.x[c3];
+      const N3& xp = st.xp[c3];
+      N3 xc;
+      xc.r = x0.r - lm * (fp1.r - fp0.r);
+#pragma unroll
+      for (int g = 0; g < 3; ++g) xc.m[g] = x0.m[g] - lm * (fp1.m[g] - fp0.m[g]);
+      xc.E = x0.E - lm * (fp1.E - fp0.E);
+      if (AX == 2) xc.m[2] = xc.m[2] + tau * (-c.g * xp.r);
+      const N3& d0 = st.dl[c3];
+      const N3& dm = st.dl[c4];
+      const double G0 = st.G[c3], Gm = st.G[c4];
+      out.r = 0.5 * (xp.r + xc.r) + (G0 * d0.r - Gm * dm.r);
+#pragma unroll
+      for (int g = 0; g < 3; ++g) out.m[g] = 0.5 * (xp.m[g] + xc.m[g]) + (G0 * d0.m[g] - Gm * dm.m[g]);
+      out.E = 0.5 * (xp.E + xc.E) + (G0 * d0.E - Gm * dm.E);
+    }
+    if (FUSE) acc_out(c, out, zof(o), st.acc, L.out);
+    if (L.out) store3(c, Y, node(o), out);
+  }
+}
+
+template <int AX, bool FUSE>
+__global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const double* zr,
+                                                       int slot, int first,
+                                                       const double* __restrict__ X,
+                                                       double* __restrict__ Y, int kc,
+                                                       int nstrips, int nbb) {
+  __shared__ double xa[2][kNW][64];
+  __shared__ double xb[2][kNW][64];
+  constexpr int B = (AX == 2) ? 1 : 2;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const double dt = step_dt(c, sh, slot);
+  head3(sh, slot, first, dt);
+  int bid = blockIdx.x;
+  const int strip = bid % nstrips;
+  bid /= nstrips;
+  const int bb = bid % nbb;
+  const int chunk = bid / nbb;
+  const Lane3 L = lane3(c, strip, lane);
+  const int nb_len = (B == 1) ? c.ny : c.nz;
+  const int braw = bb * (kNW - 4) - 2 + w;   // index of this wave along B
+  int bidx;
+  bool bval, bwall;
+  if (B == 1) {
+    bidx = wrap(braw, c.ny);
+    bval = true;
+    bwall = false;
+  } else {
+    bidx = braw;
+    bval = braw >= 0 && braw <= c.M;
+    bwall = bval && (braw == 0 || braw == c.M);
+  }
+  const bool owave = w >= 2 && w < kNW - 2 && braw >= 0 && braw < nb_len;
+  const int mlen = (AX == 2) ? c.nz : c.ny;
+  const int m0 = chunk * kc;
+  const int m1 = min(m0 + kc, mlen);
+  const double tau = 0.5 * dt;
+  const double lm = tau * ((AX == 2) ? c.ihz : c.ihy);
+  MF st;
+  st.acc.s[0] = st.acc.s[1] = st.acc.s[2] = 0.0;
+  st.acc.bad = false;
+  const int fs = (AX == 2) ? max(0, m0 - 2) : m0 - 2;
+  const int fe = m1 + 2;
+  for (int fb = fs & ~3; fb <= fe; fb += 4) {
+    mf_iter<AX, 0, FUSE>(c, st, fb + 0, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm);
+    mf_iter<AX, 1, FUSE>(c, st, fb + 1, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm);
+    mf_iter<AX, 2, FUSE>(c, st, fb + 2, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm);
+    mf_iter<AX, 3, FUSE>(c, st, fb + 3, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm);
+  }
+  if (FUSE) fold3(sh, slot, st.acc);
+}
+
+// ---------------------------------------------------------------------------
+// L_x: flux across lanes, march z, waves along y.
+
+struct LF {
+  N3 x[4];
+  P3 pn[4];
+  double s[4];             // |u_x| + c of X^n
+  double yx[4], yy[4];     // d_y u_x, d_y u_y of X^n
+  N3 xp[4];
+  P3 pp[4];
+  double pyx[4], pyy[4];   // d_y u_x, d_y u_y of X^P
+  Acc3 acc;
+};
+
+template <int S, bool FUSE>
+__device__ __forceinline__ void lf_iter(const Coef& c, LF& st, int f, int fs, int fe, int k0,
+                                        int k1, int w, int lane, const Lane3& L, int j,
+                                        bool owave, double (&xa)[2][kNW][64],
+                                        double (&xb)[2][kNW][64],
+                                        const double* __restrict__ zr,
+                                        const double* __restrict__ X, double* __restrict__ Y,
+                                        double lx) {
+  if (f < fs || f > fe) return;
+  const int M = c.M;
+  constexpr int c0 = S & 3, c1 = (S + 3) & 3, c2 = (S + 2) & 3, c3 = (S + 1) & 3;
+  const int role = (w == 0 || w == kNW - 1) ? 0 : ((w == 1 || w == kNW - 2) ? 1 : 2);
+  const double ihy2 = 0.5 * c.ihy;
+  auto node = [&](int k) -> long long { return ((long long)k * c.ny + j) * c.nx + L.col; };
+
+  if (f <= M) {
+    st.x[c0] = load3(c, X, node(f));
+    st.pn[c0] = prim3(c, st.x[c0], zr[f]);
+    st.s[c0] = fabs(st.pn[c0].u[0]) + sound(c, st.pn[c0].T);
+    exchange(xa, w, lane, st.pn[c0].u[0], st.pn[c0].u[1], ihy2, st.yx[c0], st.yy[c0]);
+  }
+  // predictor on row f-1
+  const int r1 = f - 1;
+  if (r1 >= k0 - 1 && r1 >= 0 && r1 <= M) {
+    if (role >= 1) {
+      if (r1 == 0 || r1 == M) {
+        st.xp[c1] = st.x[c1];
+        st.pp[c1] = st.pn[c1];
+      } else {
+        const P3& q = st.pn[c1];
+        double du[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+        for (int g = 0; g < 3; ++g) du[g][0] = (shd(q.u[g]) - q.u[g]) * c.ihx;
+        double dT = (shd(q.T) - q.T) * c.ihx;
+        du[0][1] = st.yx[c1];
+        du[1][1] = st.yy[c1];
+        du[0][2] = (st.pn[c0].u[0] - st.pn[c2].u[0]) * (0.5 * c.ihz);
+        du[2][2] = (st.pn[c0].u[2] - st.pn[c2].u[2]) * (0.5 * c.ihz);
+        N3 Fi = flux3<0>(c, st.x[c1], q, du, dT);
+        N3 Fm = shu(Fi);
+        const N3& x0 = st.x[c1];
+        N3 v;
+        v.r = x0.r - lx * (Fi.r - Fm.r);
+#pragma unroll
+        for (int g = 0; g < 3; ++g) v.m[g] = x0.m[g] - lx * (Fi.m[g] - Fm.m[g]);
+        v.E = x0.E - lx * (Fi.E - Fm.E);
+        st.xp[c1] = v;
+        st.pp[c1] = prim3(c, v, zr[r1]);
+      }
+    }
+    double a = (role >= 1) ? st.pp[c1].u[0] : 0.0;
+    double b = (role >= 1) ? st.pp[c1].u[1] : 0.0;
+    exchange(xb, w, lane, a, b, ihy2, st.pyx[c1], st.pyy[c1]);
+  }
+  // corrector, average and TVD term on row f-2
+  const int r = f - 2;
+  if (r >= k0 && r < k1 && owave) {
+    N3 out;
+    if (r == 0 || r == M) {
+      out = st.x[c2];
+    } else {
+      const P3& q = st.pp[c2];
+      double du[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+      for (int g = 0; g < 3; ++g) du[g][0] = (q.u[g] - shu(q.u[g])) * c.ihx;
+      double dT = (q.T - shu(q.T)) * c.ihx;
+      du[0][1] = st.pyx[c2];
+      du[1][1] = st.pyy[c2];
+      du[0][2] = (st.pp[c1].u[0] - st.pp[c3].u[0]) * (0.5 * c.ihz);
+      du[2][2] = (st.pp[c1].u[2] - st.pp[c3].u[2]) * (0.5 * c.ihz);
+      N3 Fi = flux3<0>(c, st.xp[c2], q, du, dT);
+      N3 Fp = shd(Fi);
+      const N3& x0 = st.x[c2];
+      N3 xc;
+      xc.r = x0.r - lx * (Fp.r - Fi.r);
+#pragma unroll
+      for (int g = 0; g < 3; ++g) xc.m[g] = x0.m[g] - lx * (Fp.m[g] - Fi.m[g]);
+      xc.E = x0.E - lx * (Fp.E - Fi.E);
+      N3 d0 = sub3(shd(x0), x0);
+      double G = 0.0;
+      if (c.tvd_on) {
+        N3 dm = shu(d0);
+        N3 dp = shd(d0);
+        double Co = lx * fmax(st.s[c2], shd(st.s[c2]));
+        G = tvd_G(c, dot3(dm, d0), dot3(d0, dp), dot3(d0, d0), Co);
+      }
+      N3 D{G * d0.r, {G * d0.m[0], G * d0.m[1], G * d0.m[2]}, G * d0.E};
+      N3 Dm = shu(D);
+      const N3& xp = st.xp[c2];
+      out.r = 0.5 * (xp.r + xc.r) + (D.r - Dm.r);
+#pragma unroll
+      for (int g = 0; g < 3; ++g) out.m[g] = 0.5 * (xp.m[g] + xc.m[g]) + (D.m[g] - Dm.m[g]);
+      out.E = 0.5 * (xp.E + xc.E) + (D.E - Dm.E);
+    }
+    if (FUSE) acc_out(c, out, zr[r], st.acc, L.out);
+    if (L.out) store3(c, Y, node(r), out);
+  }
+}
+
+template <bool FUSE>
+__global__ __launch_bounds__(64 * kNW) void sweep_lf3d(Coef c, Shared* sh, const double* zr,
+                                                       int slot, int first,
+                                                       const double* __restrict__ X,
+                                                       double* __restrict__ Y, int kc,
+                                                       int nstrips, int nbb) {
+  __shared__ double xa[2][kNW][64];
+  __shared__ double xb[2][kNW][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const double dt = step_dt(c, sh, slot);
+  head3(sh, slot, first, dt);
+  int bid = blockIdx.x;
+  const int strip = bid % nstrips;
+  bid /= nstrips;
+  const int bb = bid % nbb;
+  const int chunk = bid / nbb;
+  const Lane3 L = lane3(c, strip, lane);
+  const int jraw = bb * (kNW - 4) - 2 + w;
+  const int j = wrap(jraw, c.ny);
+  const bool owave = w >= 2 && w < kNW - 2 && jraw >= 0 && jraw < c.ny;
+  const int k0 = chunk * kc;
+  const int k1 = min(k0 + kc, c.nz);
+  const double lx = 0.5 * dt * c.ihx;
+  LF st;
+  st.acc.s[0] = st.acc.s[1] = st.acc.s[2] = 0.0;
+  st.acc.bad = false;
+  const int fs = max(0, k0 - 2);
+  const int fe = k1 + 1;
+  for (int fb = fs & ~3; fb <= fe; fb += 4) {
+    lf_iter<0, FUSE>(c, st, fb + 0, fs, fe, k0, k1, w, lane, L, j, owave, xa, xb, zr, X, Y, lx);
+    lf_iter<1, FUSE>(c, st, fb + 1, fs, fe, k0, k1, w, lane, L, j, owave, xa, xb, zr, X, Y, lx);
+    lf_iter<2, FUSE>(c, st, fb + 2, fs, fe, k0, k1, w, lane, L, j, owave, xa, xb, zr, X, Y, lx);
+    lf_iter<3, FUSE>(c, st, fb + 3, fs, fe, k0, k1, w, lane, L, j, owave, xa, xb, zr, X, Y, lx);
+  }
+  if (FUSE) fold3(sh, slot, st.acc);
+}
+
+// ---------------------------------------------------------------------------
+
+hipError_t launch_sweep_3d(int axis, const Coef& c, Shared* sh, const double* zr, int slot,
+                           int first, bool fuse, const double* X, double* Y, int kc,
+                           hipStream_t s) {
+  const int nstrips = (c.nx + kStrip3 - 1) / kStrip3;
+  const int per = kNW - 4;
+  const dim3 block(64 * kNW);
+  if (axis == 0 || axis == 2) {
+    // waves along y
+    const int nbb = (c.ny + per - 1) / per;
+    const int nch = (c.nz + kc - 1) / kc;
+    const long long nblk = (long long)nstrips * nbb * nch;
+    if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)nblk);
+    if (axis == 0) {
+      if (fuse) sweep_lf3d<true><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nbb);
+      else sweep_lf3d<false><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nbb);
+    } else {
+      if (fuse) sweep_mf3d<2, true><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nbb);
+      else sweep_mf3d<2, false><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nbb);
+    }
+  } else {
+    // march y, waves along z
+    const int nbb = (c.nz + per - 1) / per;
+    const int nch = (c.ny + kc - 1) / kc;
+    const long long nblk = (long long)nstrips * nbb * nch;
+    if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)nblk);
+    if (fuse) sweep_mf3d<1, true><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nbb);
+    else sweep_mf3d<1, false><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nbb);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace mtvd

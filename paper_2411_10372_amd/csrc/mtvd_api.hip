@@ -392,9 +392,16 @@ Shared* shared_of(mtvd_ctx* c) { return (Shared*)(c->ws + c->L.shared); }
 double* zrow_of(mtvd_ctx* c) { return (double*)(c->ws + c->L.zrow); }
 
 int default_rows(const mtvd_ctx* c) {
-  // about four waves per SIMD (1024 SIMDs) when the grid allows it
-  long long cols = (long long)strips_2d(c->c.nx) * c->c.ny;
-  long long kc = cols * c->c.nz / 4096;
+  long long kc;
+  if (c->c.ndim == 2) {
+    // about four waves per SIMD (1024 SIMDs) when the grid allows it
+    long long cols = (long long)strips_2d(c->c.nx);
+    kc = cols * c->c.nz / 4096;
+  } else {
+    // 3D: blocks of 8 waves; a quarter of the marched extent, 4..32 rows
+    kc = c->c.nz / 4;
+    if (kc > 32) kc = 32;
+  }
   if (kc < 4) kc = 4;
   if (kc > 64) kc = 64;
   return (int)kc;

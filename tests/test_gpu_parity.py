@@ -36,10 +36,11 @@ def _say(*a):
 # initial state and dt
 
 
-@pytest.mark.parametrize("nx,nz,seed", [(256, 64, 0), (150, 37, 3), (4096, 1024, 1)])
-def test_init_state_matches_oracle(nx, nz, seed):
+@pytest.mark.parametrize("nx,nz,seed,Ra", [(256, 64, 0, 1e6), (150, 37, 3, 1e6),
+                                           (4096, 1024, 1, 1e10)])
+def test_init_state_matches_oracle(nx, nz, seed, Ra):
     _say("init", nx, nz, seed)
-    po, pg = both(nx=nx, nz=nz, seed=seed, Ra=1e6)
+    po, pg = both(nx=nx, nz=nz, seed=seed, Ra=Ra)
     s = _solver(pg)
     s.init_state()
     Xg = s.get_state()
