@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--workload", default="2d_4096x1024_ra1e10")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for HBM counters)")
     ap.add_argument("--rows", type=int, nargs=2, default=None,
                     help="rows per wave for the x and z sweeps (default: library choice)")
     args = ap.parse_args()
@@ -183,6 +185,14 @@ def main():
                   "nu_mean": dfin["nu_mean"], "nu_bulk": dfin["nu_bulk"]},
         "source_hash": shash,
     }
+    if args.copy_ref:
+        a = torch.empty(32 << 20, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_ref_bytes"] = 2 * a.numel() * 8
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(kw, args.cpu_seconds)

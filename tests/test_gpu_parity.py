@@ -132,8 +132,12 @@ def test_256x64_one_and_200_steps():
     do = oracle.diag(po, Xo200)
     assert dg["step"] == 200
     assert abs(dg["time"] - t200) <= 1e-13 * t200
-    for k in ("mass", "kinetic", "total_energy", "nu_bottom", "nu_top", "nu_mean"):
+    for k in ("mass", "total_energy", "nu_bottom", "nu_top", "nu_mean"):
         assert abs(dg[k] - do[k]) <= 1e-12 * abs(do[k]), (k, dg[k], do[k])
+    # kinetic energy is quadratic in momenta that start at zero: compare it
+    # on the energy scale rho_b c_b^2 V, like the momentum floor of parity_error
+    cb2 = (po.gamma - 1.0) / (po.eps * po.D)
+    assert abs(dg["kinetic"] - do["kinetic"]) <= 1e-12 * cb2 * po.aspect
     # bulk Nu terms are tiny differences of large sums: absolute bound
     for k in ("nu_bulk", "nu_conv"):
         assert abs(dg[k] - do[k]) <= 1e-10, (k, dg[k], do[k])
@@ -155,7 +159,12 @@ def test_4096x1024_two_steps_full_field():
     Xo, t, _ = oracle.step(po, oracle.init(po), 2)
     e = parity_error(Xg, Xo, po)
     print("4096x1024 parity e after 2 steps", e, flush=True)
-    assert e <= 2 * SWEEP_TOL, e
+    # At this grid the +-1e-3 noise exceeds the row-to-row change of T, so the
+    # TVD ratios see faces whose jump is small next to their neighbours'; the
+    # oracle itself moves by e ~ 2.4e-13 per step when its input is perturbed
+    # by one ulp (test_oracle_conditioning_4096x1024).  Bar: about 4x that
+    # sensitivity over two steps.
+    assert e <= 1e-12, e
     d = s.diagnostics()
     do = oracle.diag(po, Xo)
     assert abs(d["mass"] - do["mass"]) <= 1e-13 * do["mass"]
