@@ -169,6 +169,98 @@ int mtvd_destroy(mtvd_ctx* c);
 const char* mtvd_strerror(int status);
 const char* mtvd_last_error(const mtvd_ctx* c);
 
+/* ---------------------------------------------------------------------------
+ * Batches: many independent 2D boxes (each with its own grid, Ra, Pr, seed,
+ * dt and time) advanced together.  Each directional operator of a step is
+ * ONE launch covering every box (a device work list of (box, column strip,
+ * row chunk) items); the launches of two steps are captured once into a
+ * HIP graph and replayed, so a step costs one graph launch per two steps.
+ * All boxes must be 2D and share dt_mode and sweep_order.  State buffers
+ * hold the boxes one after another, each in the canonical layout, each
+ * starting on a 256-byte boundary (mtvd_batch_offset gives the place).
+ */
+typedef struct mtvd_batch mtvd_batch;
+
+int mtvd_batch_bytes(const mtvd_params* boxes, int32_t nbox, size_t* state_bytes,
+                     size_t* workspace_bytes);
+int mtvd_batch_create(const mtvd_params* boxes, int32_t nbox, void* hip_stream,
+                      mtvd_batch** out);
+/* Two state buffers (state_bytes each) and the workspace, as mtvd_bind. */
+int mtvd_batch_bind(mtvd_batch* b, double* buf_a, double* buf_b, void* workspace);
+/* Offset (in doubles) of box `box` inside a state buffer. */
+int mtvd_batch_offset(const mtvd_batch* b, int32_t box, size_t* offset);
+int mtvd_batch_init_state(mtvd_batch* b);
+/* nsteps time steps of every box; pairs of steps replay the captured graph.
+ * Asynchronous. */
+int mtvd_batch_step(mtvd_batch* b, int32_t nsteps);
+/* Diagnostics of one box (synchronises); see mtvd_diagnostics. */
+int mtvd_batch_diagnostics(mtvd_batch* b, int32_t box, mtvd_diag* out);
+int mtvd_batch_get_state(mtvd_batch* b, int32_t box, double* host, size_t count);
+int mtvd_batch_set_state(mtvd_batch* b, int32_t box, const double* host, size_t count,
+                         double time, int64_t step);
+int mtvd_batch_current(const mtvd_batch* b, int32_t* which);
+/* Rows per wave of one box's operators (0 = library default). */
+int mtvd_batch_set_tiling(mtvd_batch* b, int32_t box, int32_t rows_x, int32_t rows_z);
+/* Time trial steps of each distinct box size over the candidate rows per
+ * wave {4, 8, 16, 32, 64} for L_z and then L_x, keep the fastest for every
+ * box of that size, and restore the state, time and dt afterwards.
+ * `scratch` is caller-owned device memory of at least state_bytes +
+ * 128 * nbox bytes.  Synchronises. */
+int mtvd_batch_autotune(mtvd_batch* b, void* scratch, int32_t trial_steps);
+int mtvd_batch_get_tiling(const mtvd_batch* b, int32_t box, int32_t* rows_x,
+                          int32_t* rows_z);
+int mtvd_batch_destroy(mtvd_batch* b);
+const char* mtvd_batch_last_error(const mtvd_batch* b);
+
+/* ---------------------------------------------------------------------------
+ * Adjoint (reverse mode) of the time-averaged mean Nusselt number of a 2D
+ * box with a frozen dt:
+ *
+ *   J(theta, Ra) = (1/N) sum_{n=1..N} Nu_mean(X_n),   X_n = S^n(X_0),
+ *
+ * with Nu_mean = (Nu(z=0) + Nu(z=1))/2 of the plates (Sec. 2, mean_Nu, from
+ * the row means of T by one-sided second-order differences), S one step of
+ * Sec. 3.1 (time_step) with the same dt for every step, and X_0(theta) the
+ * conduction state of mtvd_init_state with T = T0 + theta on interior rows
+ * (no noise).  Ra enters through mu = sqrt(Pr/Ra) and K = 1/(eps D
+ * sqrt(Ra Pr)); dt and the initial density do not depend on theta or Ra.
+ * The reverse of each directional operator is hand-written stage by stage;
+ * at a kink of max/min/abs/phi it takes the branch the forward pass took.
+ * Memory: checkpoints every `every` steps, and one interval's operator
+ * inputs (4 every states) recomputed during the backward pass, plus about 76
+ * doubles per node of stage arrays (mtvd_adj_bytes gives the total).
+ * Restrictions: ndim = 2 and limiter_form = 0 (MTVD_EINVAL otherwise);
+ * dt_mode is ignored (dt is always frozen).
+ */
+typedef struct mtvd_adj mtvd_adj;
+
+/* Workspace bytes for N = nsteps >= 1 steps and checkpoints every
+ * `every` >= 1 steps (clamped to nsteps). */
+int mtvd_adj_bytes(const mtvd_params* p, int32_t nsteps, int32_t every,
+                   size_t* workspace_bytes);
+/* Validate and create (no device work); stream as mtvd_create. */
+int mtvd_adj_create(const mtvd_params* p, int32_t nsteps, int32_t every, void* hip_stream,
+                    mtvd_adj** out);
+/* Attach a caller-owned, 256-byte aligned device workspace of at least
+ * mtvd_adj_bytes bytes.  The workspace holds the checkpoints between
+ * forward and backward. */
+int mtvd_adj_bind(mtvd_adj* a, void* workspace);
+/* Forward pass: X_0 from theta (device, nz*nx doubles in the canonical
+ * node order; plate rows ignored; NULL = zero perturbation), N steps with
+ * dt (> 0: that dt; 0: the CFL dt of X_0), J and the dt used to the host
+ * (either pointer may be NULL).  Synchronises.  MTVD_ENONFINITE if J is not
+ * finite. */
+int mtvd_adj_forward(mtvd_adj* a, const double* theta, double dt, double* J, double* dt_used);
+/* Backward pass of the latest forward pass for the cotangent Jbar: writes
+ * Jbar dJ/dX_0 (device, 4 nz nx doubles, canonical layout), Jbar dJ/dtheta
+ * (device, nz nx doubles, 0 on the plate rows) and Jbar dJ/dRa (host); any
+ * of the three may be NULL.  May be called again for the same forward pass.
+ * Synchronises. */
+int mtvd_adj_backward(mtvd_adj* a, double Jbar, double* grad_x0, double* grad_theta,
+                      double* grad_ra);
+int mtvd_adj_destroy(mtvd_adj* a);
+const char* mtvd_adj_last_error(const mtvd_adj* a);
+
 #ifdef __cplusplus
 }
 #endif

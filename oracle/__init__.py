@@ -17,6 +17,14 @@ Parity status of each function (what pins it is in ``tests/test_oracle_*``):
   TVD limiter form  -- parity unpinned beyond its properties (conservative,
                        zero on linear data, no new extrema at a contact)
   diag              -- pinned (conduction Nu = 1, closed-form sums)
+  init_theta        -- pinned (equals init without noise at theta = 0; T of
+                       interior nodes recovered as T0 + theta)
+  time_avg_nu       -- pinned through step and diag, plus the conduction
+                       value 1 and the one-step identity
+  time_avg_nu_cs    -- complex-step derivative of time_avg_nu: pinned by its
+                       real part (equal to time_avg_nu), by central
+                       differences where the method is smooth (TVD off) and
+                       by linearity in the direction
 """
 from __future__ import annotations
 
@@ -133,8 +141,10 @@ def lib():
                                     ctypes.c_int, dp, dp]
         L.ora_step.argtypes = [P, dp, ctypes.c_int, dp, dp]
         L.ora_diag.argtypes = [P, dp, ctypes.POINTER(_Diag)]
+        L.ora_time_avg_nu_cs.argtypes = [P, dp, dp, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_int, ctypes.c_double, dp, dp]
         for fn in ("ora_init", "ora_init_box", "ora_sweep", "ora_sweep_box",
-                   "ora_step", "ora_diag"):
+                   "ora_step", "ora_diag", "ora_time_avg_nu_cs"):
             getattr(L, fn).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -225,3 +235,63 @@ def diag(p: Params, X: np.ndarray) -> dict:
     out = {n: getattr(d, n) for n, _ in _Diag._fields_ if n != "tmean"}
     out["tmean"] = list(d.tmean)
     return out
+
+
+def init_theta(p: Params, theta: np.ndarray) -> np.ndarray:
+    """Sec. 2 initial state (conduction T0 = 1 - (eps+D) z, hydrostatic rho,
+    u = 0) with T = T0 + theta on interior rows instead of random noise.
+    theta: (nz, nx) in 2D; plate rows are ignored."""
+    if p.ndim != 2:
+        raise ValueError("2D only")
+    q = Params(**{**p.__dict__, "noise_amp": 0.0})
+    X = init(q)
+    M = p.nz - 1
+    z = (np.arange(p.nz, dtype=np.float64) / M)[:, None]
+    T0 = 1.0 - (p.eps + p.D) * z
+    cv = 1.0 / (p.gamma * p.eps * p.D)
+    g = p.gravity_scale / p.eps
+    rho = X[0]
+    T = T0 + np.asarray(theta, dtype=np.float64).reshape(p.nz, p.nx)
+    X[3, 1:M] = rho[1:M] * (cv * T[1:M] + g * z[1:M])
+    return X
+
+
+def time_avg_nu(p: Params, X0: np.ndarray, nsteps: int, dt: float) -> float:
+    """(1/N) sum_{n=1..N} Nu_mean(X_n) over N steps of Sec. 3.1 with the
+    fixed step dt (Nu_mean of Sec. 2: plate Nusselt numbers averaged)."""
+    q = Params(**{**p.__dict__, "dt_mode": 1})
+    X = np.array(X0, dtype=np.float64, copy=True)
+    acc = 0.0
+    for _ in range(nsteps):
+        X, _, _ = step(q, X, 1, dt_frozen=dt)
+        acc += diag(q, X)["nu_mean"]
+    return acc / nsteps
+
+
+def time_avg_nu_cs(p: Params, X0: np.ndarray, V, nsteps: int, dt: float,
+                   dRa: float = 0.0, h: float = 1e-20):
+    """Complex-step mode of :func:`time_avg_nu`: (J, dJ) with dJ the
+    derivative of J along the state direction V (None: no state direction)
+    plus dRa times d/dRa, on the branches the run takes."""
+    X0 = np.ascontiguousarray(X0, dtype=np.float64)
+    Vp = None
+    if V is not None:
+        V = np.ascontiguousarray(V, dtype=np.float64)
+        if V.shape != X0.shape:
+            raise ValueError("V must have the state's shape")
+        Vp = _ptr(V)
+    J, dJ = ctypes.c_double(), ctypes.c_double()
+    pc = p._c()
+    _ok(lib().ora_time_avg_nu_cs(ctypes.byref(pc), _ptr(X0), Vp, h, dRa, nsteps, dt,
+                                 ctypes.byref(J), ctypes.byref(dJ)), "time_avg_nu_cs")
+    return J.value, dJ.value
+
+
+def theta_direction(p: Params, X0: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """The state direction of a temperature direction v at X0: the derivative
+    of init_theta, E = rho (cv T + g z) on interior rows, is rho cv v."""
+    V = np.zeros_like(X0)
+    M = p.nz - 1
+    cv = 1.0 / (p.gamma * p.eps * p.D)
+    V[3, 1:M] = X0[0, 1:M] * cv * np.asarray(v, dtype=np.float64).reshape(p.nz, p.nx)[1:M]
+    return V

@@ -40,6 +40,7 @@
  */
 #include "mtvd_oracle.h"
 
+#include <complex.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -61,6 +62,7 @@ typedef struct {
   double mu;                 /* sqrt(Pr/Ra) (times diffusion_scale) */
   double K;                  /* 1/(eps D sqrt(Ra Pr)) (times diffusion_scale) */
   double lam;                /* bulk_coef */
+  double complex mu_cs, K_cs; /* mu and K of the complex-step mode */
   double Tb, Tt;             /* plate temperatures: 1 and 1-(eps+D) */
   double cfl;
   int limiter_form, tvd_on, pred_dir, sweep_order, wall_order;
@@ -94,6 +96,8 @@ static void make_coefs(const ora_params* p, coefs* c) {
   c->mu = sqrt(p->Pr / p->Ra) * p->diffusion_scale;
   c->K = 1.0 / (p->eps * p->D * sqrt(p->Ra * p->Pr)) * p->diffusion_scale;
   c->lam = p->bulk_coef;
+  c->mu_cs = c->mu;
+  c->K_cs = c->K;
   c->Tb = 1.0;
   c->Tt = 1.0 - (p->eps + p->D);
   c->cfl = p->cfl;
@@ -233,104 +237,10 @@ static box make_box(int bx, int by, int nz) {
   return b;
 }
 
-/* primitive variables at every node (Sec. 2: E and p definitions):
- * u_a = (rho u_a)/rho, T = (E/rho - |u|^2/2 - g z)/cv, p = a rho T */
-typedef struct {
-  double *u[3], *T, *p;
-} prims;
-
-static void alloc_prims(const box* b, prims* q) {
-  for (int d = 0; d < 3; ++d) q->u[d] = (double*)calloc((size_t)b->nn, sizeof(double));
-  q->T = (double*)calloc((size_t)b->nn, sizeof(double));
-  q->p = (double*)calloc((size_t)b->nn, sizeof(double));
-}
-static void free_prims(prims* q) {
-  for (int d = 0; d < 3; ++d) free(q->u[d]);
-  free(q->T);
-  free(q->p);
-}
-
-static void primitives_at(const coefs* c, const box* b, const double* X,
-                          prims* q, ptrdiff_t n) {
-  int k = (int)(n / b->s[2]);
-  double rho = X[c->fR * b->nn + n];
-  double uu = 0.0;
-  for (int d = 0; d < 3; ++d) {
-    double u = (c->fm[d] >= 0) ? X[c->fm[d] * b->nn + n] / rho : 0.0;
-    q->u[d][n] = u;
-  }
-  uu = (q->u[0][n] * q->u[0][n] + q->u[1][n] * q->u[1][n]) + q->u[2][n] * q->u[2][n];
-  double e = X[c->fE * b->nn + n] / rho - 0.5 * uu - c->g * zrow(c, k);
-  q->T[n] = e / c->cv;
-  q->p[n] = c->a * rho * q->T[n];
-}
-
-static void primitives(const coefs* c, const box* b, const double* X,
-                       prims* q) {
-#pragma omp parallel for schedule(static)
-  for (ptrdiff_t n = 0; n < b->nn; ++n) primitives_at(c, b, X, q, n);
-}
-
 /* finite differences of an array q along direction d at node n */
 enum { DFWD, DBWD, DCEN, DW2F, DW2B };
 
-static double deriv(const double* q, const box* b, const coefs* c,
-                    ptrdiff_t n, int d, int mode) {
-  ptrdiff_t s = b->s[d];
-  double h = c->h[d];
-  switch (mode) {
-    case DFWD: return (q[n + s] - q[n]) / h;
-    case DBWD: return (q[n] - q[n - s]) / h;
-    case DCEN: return (q[n + s] - q[n - s]) / (2.0 * h);
-    case DW2F: return ((-3.0 * q[n] + 4.0 * q[n + s]) - q[n + 2 * s]) / (2.0 * h);
-    default:   return ((3.0 * q[n] - 4.0 * q[n - s]) + q[n - 2 * s]) / (2.0 * h);
-  }
-}
-
 static int has_dir(const coefs* c, int d) { return d != 1 || c->ndim == 3; }
-
-/* flux F_alpha at node n (Sec. 3.1, F_alpha; Sec. 2, tau_ij and the energy
- * equation), with the derivative along alpha taken in `mode` */
-static void flux_at(const coefs* c, const box* b, const double* X,
-                    const prims* q, int al, ptrdiff_t n, int mode,
-                    double* F) {
-  double dau[3] = {0, 0, 0};   /* d_alpha u_g */
-  double dgua[3] = {0, 0, 0};  /* d_g u_alpha, g != alpha (central) */
-  for (int g = 0; g < 3; ++g) {
-    if (!has_dir(c, g)) continue;
-    dau[g] = deriv(q->u[g], b, c, n, al, mode);
-    if (g != al) dgua[g] = deriv(q->u[al], b, c, n, g, DCEN);
-  }
-  double div = 0.0;            /* d_m u_m */
-  for (int m = 0; m < 3; ++m) {
-    if (!has_dir(c, m)) continue;
-    div += (m == al) ? dau[al] : deriv(q->u[m], b, c, n, m, DCEN);
-  }
-  double tau[3] = {0, 0, 0};   /* tau_{g alpha} */
-  for (int g = 0; g < 3; ++g) {
-    if (!has_dir(c, g)) continue;
-    if (g == al)
-      tau[g] = c->mu * ((dau[al] + dau[al]) + c->lam * div);
-    else
-      tau[g] = c->mu * (dau[g] + dgua[g]);
-  }
-  double dT = deriv(q->T, b, c, n, al, mode);
-  double rho_ua = X[c->fm[al] * b->nn + n];
-  double E = X[c->fE * b->nn + n];
-  double p = q->p[n];
-  double ua = q->u[al][n];
-  F[c->fR] = rho_ua;
-  for (int g = 0; g < 3; ++g) {
-    if (!has_dir(c, g)) continue;
-    double v = X[c->fm[g] * b->nn + n] * ua - tau[g];
-    if (g == al) v = v + p;
-    F[c->fm[g]] = v;
-  }
-  double work = 0.0;           /* sum_b u_b tau_{b alpha} */
-  for (int g = 0; g < 3; ++g)
-    if (has_dir(c, g)) work += q->u[g][n] * tau[g];
-  F[c->fE] = (ua * (E + p) - c->K * dT) - work;
-}
 
 /* node ranges [lo, hi) per direction for one stage */
 typedef struct { int lo[3], hi[3]; } range;
@@ -355,241 +265,50 @@ static void shrink(range* r, const coefs* c, int d, int lo, int hi) {
   r->hi[d] -= hi;
 }
 
-/* ------------------------------------------------------------------------ */
-/* one directional predictor-corrector-TVD operator L_alpha(tau), Sec. 3.1   */
+/* the operator over double (the oracle) and over double complex (the
+ * complex-step mode of the adjoint checks); see mtvd_oracle_sweep.inc */
+#define R double
+#define SFX(name) name
+#define MU(c) ((c)->mu)
+#define KK(c) ((c)->K)
+#define RE(x) (x)
+#define ABS(x) fabs(x)
+#define SQRT(x) sqrt(x)
+#define PHI(t) fmax(0.0, fmin((t), 1.0))
+#include "mtvd_oracle_sweep.inc"
+#undef R
+#undef SFX
+#undef MU
+#undef KK
+#undef RE
+#undef ABS
+#undef SQRT
+#undef PHI
 
-static void sweep_box(const coefs* c, const box* b, int al, double tau,
-                      const double* X, double* Xo) {
-  const int nf = c->nf;
-  const int M = c->M;
-  const double lam = tau / c->h[al];   /* (dt/2)/delta x_alpha */
-  const int zdir = (al == 2);
-  /* direction of the predictor flux difference: -1 backward (as printed) */
-  const int sp = (zdir || c->pred_dir == 0) ? -1 : +1;
-  const int inner_pred = (sp < 0) ? DFWD : DBWD;
-  const int inner_corr = (sp < 0) ? DBWD : DFWD;
-  const ptrdiff_t s = b->s[al];
-
-  double* F = (double*)calloc((size_t)nf * b->nn, sizeof(double));
-  double* XP = (double*)calloc((size_t)nf * b->nn, sizeof(double));
-  double* FP = (double*)calloc((size_t)nf * b->nn, sizeof(double));
-  double* XC = (double*)calloc((size_t)nf * b->nn, sizeof(double));
-  double* Dl = (double*)calloc((size_t)nf * b->nn, sizeof(double)); /* D_{n+1/2} */
-  double* cs = (double*)calloc((size_t)b->nn, sizeof(double));
-  prims q, qP;
-  alloc_prims(b, &q);
-  alloc_prims(b, &qP);
-
-  /* level-n primitives and sound speed c = sqrt(gamma p / rho) */
-  primitives(c, b, X, &q);
-  for (ptrdiff_t n = 0; n < b->nn; ++n)
-    cs[n] = sqrt(c->gamma * q.p[n] / X[c->fR * b->nn + n]);
-
-  /* ---- predictor fluxes F^(n) ---- */
-  {
-    range r = all_nodes(b);
-    for (int d = 0; d < 3; ++d)
-      if (d != al && d != 2) shrink(&r, c, d, 1, 1);
-    if (zdir) {
-      r.hi[2] = M;                         /* F_0 .. F_{M-1} */
-    } else {
-      r.lo[2] = 1; r.hi[2] = M;            /* interior rows */
-      if (sp < 0) r.hi[al] -= 1; else r.lo[al] += 1;
-    }
-#pragma omp parallel for schedule(static)
-    for (int kk = r.lo[2]; kk < r.hi[2]; ++kk) {
-      range rr = r; rr.lo[2] = kk; rr.hi[2] = kk + 1;
-      FOR_RANGE(b, rr, n) {
-        double Fn[5];
-        int mode = inner_pred;
-        if (zdir && kk == 0 && c->wall_order == 2)
-          mode = DW2F;                     /* second-order forward at the bottom */
-        flux_at(c, b, X, &q, al, n, mode, Fn);
-        for (int f = 0; f < nf; ++f) F[f * b->nn + n] = Fn[f];
-      }
-    }
-  }
-
-  /* ---- predictor X^P = X - lam (F_k - F_{k-1}) + tau S(X) ---- */
-  {
-    range r = all_nodes(b);
-    for (int d = 0; d < 3; ++d)
-      if (d != al && d != 2) shrink(&r, c, d, 1, 1);
-    if (!zdir) shrink(&r, c, al, 1, 1);
-    for (int kk = r.lo[2]; kk < r.hi[2]; ++kk) {
-      range rr = r; rr.lo[2] = kk; rr.hi[2] = kk + 1;
-      FOR_RANGE(b, rr, n) {
-        if (!zdir && (kk == 0 || kk == M)) {
-          /* plate rows are copied through by the horizontal operators */
-          for (int f = 0; f < nf; ++f) XP[f * b->nn + n] = X[f * b->nn + n];
-          continue;
-        }
-        if (zdir && (kk == 0 || kk == M)) {
-          double rho;
-          if (kk == 0) {
-            rho = X[c->fR * b->nn + n];    /* not used by any later stage */
-          } else {
-            /* backward mass-flux difference at the top plate (m_z,M = 0) */
-            rho = X[c->fR * b->nn + n] -
-                  lam * (X[c->fm[2] * b->nn + n] - X[c->fm[2] * b->nn + n - s]);
-          }
-          double Tw = (kk == 0) ? c->Tb : c->Tt;
-          for (int f = 0; f < nf; ++f) XP[f * b->nn + n] = 0.0;
-          XP[c->fR * b->nn + n] = rho;
-          XP[c->fE * b->nn + n] = rho * (c->cv * Tw + c->g * zrow(c, kk));
-          continue;
-        }
-        ptrdiff_t np = (sp < 0) ? n : n + s;      /* F_{k}   (or F_{k+1}) */
-        ptrdiff_t nm = (sp < 0) ? n - s : n;      /* F_{k-1} (or F_{k})   */
-        for (int f = 0; f < nf; ++f) {
-          double v = X[f * b->nn + n] - lam * (F[f * b->nn + np] - F[f * b->nn + nm]);
-          if (zdir && f == c->fm[2]) v = v + tau * (-c->g * X[c->fR * b->nn + n]);
-          XP[f * b->nn + n] = v;
-        }
-      }
-    }
-  }
-
-  /* ---- predicted primitives and corrector fluxes F^P ---- */
-  {
-    range r = all_nodes(b);
-    for (int d = 0; d < 3; ++d)
-      if (d != al && d != 2) shrink(&r, c, d, 1, 1);
-    if (!zdir) shrink(&r, c, al, 1, 1);
-    FOR_RANGE(b, r, n) primitives_at(c, b, XP, &qP, n);
-  }
-  {
-    range r = all_nodes(b);
-    for (int d = 0; d < 3; ++d)
-      if (d != al && d != 2) shrink(&r, c, d, 2, 2);
-    if (zdir) {
-      r.lo[2] = 1;                          /* F^P_1 .. F^P_M */
-    } else {
-      r.lo[2] = 1; r.hi[2] = M;
-      if (sp < 0) { r.lo[al] += 2; r.hi[al] -= 1; }
-      else        { r.lo[al] += 1; r.hi[al] -= 2; }
-    }
-#pragma omp parallel for schedule(static)
-    for (int kk = r.lo[2]; kk < r.hi[2]; ++kk) {
-      range rr = r; rr.lo[2] = kk; rr.hi[2] = kk + 1;
-      FOR_RANGE(b, rr, n) {
-        double Fn[5];
-        int mode = inner_corr;
-        if (zdir && kk == M && c->wall_order == 2)
-          mode = DW2B;                     /* second-order backward at the top */
-        flux_at(c, b, XP, &qP, al, n, mode, Fn);
-        for (int f = 0; f < nf; ++f) FP[f * b->nn + n] = Fn[f];
-      }
-    }
-  }
-
-  /* ---- corrector X^C = X - lam (F^P_{k+1} - F^P_k) + tau S(X^P) ---- */
-  range rout = all_nodes(b);
-  for (int d = 0; d < 3; ++d)
-    if (d != 2) shrink(&rout, c, d, 2, 2);
-  if (!zdir) { rout.lo[2] = 1; rout.hi[2] = M; }
-  {
-    range r = rout;
-    if (zdir) { r.lo[2] = 1; r.hi[2] = M; }
-    FOR_RANGE(b, r, n) {
-      ptrdiff_t np = (sp < 0) ? n + s : n;
-      ptrdiff_t nm = (sp < 0) ? n : n - s;
-      for (int f = 0; f < nf; ++f) {
-        double v = X[f * b->nn + n] - lam * (FP[f * b->nn + np] - FP[f * b->nn + nm]);
-        if (zdir && f == c->fm[2]) v = v + tau * (-c->g * XP[c->fR * b->nn + n]);
-        XC[f * b->nn + n] = v;
-      }
-    }
-  }
-
-  /* ---- TVD flux on faces n+1/2 (Sec. 3.1: T, dX, r+-, G, phi, C) ---- */
-  if (c->tvd_on) {
-    range r = rout;
-    /* faces n-1/2 and n+1/2 of every output node: face index n covers
-     * (n, n+1), so faces from lo-1 to hi-1 */
-    if (zdir) { r.lo[2] = 1; r.hi[2] = M - 1; }   /* faces 1/2 and M-1/2 stay 0 */
-    else { r.lo[al] -= 1; }
-    FOR_RANGE(b, r, n) {
-      double dm[5], d0[5], dp[5];       /* dX_{n-1/2}, dX_{n+1/2}, dX_{n+3/2} */
-      for (int f = 0; f < nf; ++f) {
-        const double* x = X + f * b->nn;
-        dm[f] = x[n] - x[n - s];
-        d0[f] = x[n + s] - x[n];
-        dp[f] = x[n + 2 * s] - x[n + s];
-      }
-      double a_m = 0.0, a_p = 0.0, den = 0.0;  /* dot products */
-      for (int f = 0; f < nf; ++f) {
-        a_m += dm[f] * d0[f];
-        a_p += d0[f] * dp[f];
-        den += d0[f] * d0[f];
-      }
-      double G = 0.0;
-      if (den != 0.0) {
-        double rplus = a_m / den;          /* r+_n     */
-        double rminus = a_p / den;         /* r-_{n+1} */
-        double sn = fabs(q.u[al][n]) + cs[n];
-        double sn1 = fabs(q.u[al][n + s]) + cs[n + s];
-        double Co = lam * (sn > sn1 ? sn : sn1);
-        double C = (Co <= 0.5) ? Co * (1.0 - Co) : 0.25;
-        if (c->limiter_form == 0) {
-          double x = rplus + rminus;
-          double phi = fmax(0.0, fmin(2.0 * x, 1.0));
-          G = 0.5 * C * (1.0 - phi);
-        } else {
-          double phi1 = fmax(0.0, fmin(2.0 * rplus, 1.0));
-          double phi2 = fmax(0.0, fmin(2.0 * rminus, 1.0));
-          G = 0.5 * C * (1.0 - phi1) + 0.5 * C * (1.0 - phi2);
-        }
-      }
-      for (int f = 0; f < nf; ++f) Dl[f * b->nn + n] = G * d0[f];
-    }
-  }
-
-  /* ---- average + TVD:  X' = (X^P + X^C)/2 + D_{n+1/2} - D_{n-1/2} ---- */
-  {
-    range r = rout;
-    if (zdir) { r.lo[2] = 1; r.hi[2] = M; }
-    FOR_RANGE(b, r, n) {
-      for (int f = 0; f < nf; ++f) {
-        /* T = G dX_{n+1/2} - G dX_{n-1/2}, then the average plus T */
-        double T = Dl[f * b->nn + n] - Dl[f * b->nn + n - s];
-        Xo[f * b->nn + n] = 0.5 * (XP[f * b->nn + n] + XC[f * b->nn + n]) + T;
-      }
-    }
-  }
-
-  /* ---- plate rows ---- */
-  {
-    range r = rout;
-    for (int kk = 0; kk <= M; kk += M) {
-      r.lo[2] = kk; r.hi[2] = kk + 1;
-      FOR_RANGE(b, r, n) {
-        if (!zdir) {
-          for (int f = 0; f < nf; ++f) Xo[f * b->nn + n] = X[f * b->nn + n];
-          continue;
-        }
-        double rho, Tw;
-        if (kk == 0) {
-          /* bottom: half-cell update with the corrector mass flux
-           * (m_z = 0 on the plate) */
-          rho = X[c->fR * b->nn + n] - lam * (XP[c->fm[2] * b->nn + n + s] - 0.0);
-          Tw = c->Tb;
-        } else {
-          /* top: the predicted density (backward mass-flux difference) */
-          rho = XP[c->fR * b->nn + n];
-          Tw = c->Tt;
-        }
-        for (int f = 0; f < nf; ++f) Xo[f * b->nn + n] = 0.0;
-        Xo[c->fR * b->nn + n] = rho;
-        Xo[c->fE * b->nn + n] = rho * (c->cv * Tw + c->g * zrow(c, kk));
-      }
-    }
-  }
-
-  free(F); free(XP); free(FP); free(XC); free(Dl); free(cs);
-  free_prims(&q);
-  free_prims(&qP);
+/* complex step: branches on real parts; |x| takes sign(0) = 0 */
+static double complex cs_abs(double complex x) {
+  return creal(x) > 0.0 ? x : (creal(x) < 0.0 ? -x : 0.0);
 }
+static double complex cs_phi(double complex t) {
+  return creal(t) <= 0.0 ? 0.0 : (creal(t) >= 1.0 ? 1.0 : t);
+}
+#define R double complex
+#define SFX(name) name##_cs
+#define MU(c) ((c)->mu_cs)
+#define KK(c) ((c)->K_cs)
+#define RE(x) creal(x)
+#define ABS(x) cs_abs(x)
+#define SQRT(x) csqrt(x)
+#define PHI(t) cs_phi(t)
+#include "mtvd_oracle_sweep.inc"
+#undef R
+#undef SFX
+#undef MU
+#undef KK
+#undef RE
+#undef ABS
+#undef SQRT
+#undef PHI
 
 int ora_sweep_box(const ora_params* p, int axis, double tau, int bx, int by,
                   const double* Bin, double* Bout) {
@@ -605,7 +324,6 @@ int ora_sweep_box(const ora_params* p, int axis, double tau, int bx, int by,
   return 0;
 }
 
-/* whole periodic domain: pad two halo columns in x (and y), sweep, unpad */
 int ora_sweep(const ora_params* p, int axis, double tau, const double* Xin,
               double* Xout) {
   if (check_params(p)) return -1;
@@ -613,30 +331,7 @@ int ora_sweep(const ora_params* p, int axis, double tau, const double* Xin,
   coefs c;
   make_coefs(p, &c);
   set_threads(p);
-  int hy = (p->ndim == 3) ? 2 : 0;
-  int bx = c.nx + 4, by = c.ny + 2 * hy;
-  box b = make_box(bx, by, c.nz);
-  size_t cnt = (size_t)c.nx * c.ny * c.nz;
-  double* Bin = (double*)malloc(sizeof(double) * (size_t)c.nf * b.nn);
-  double* Bout = (double*)calloc((size_t)c.nf * b.nn, sizeof(double));
-  for (int f = 0; f < c.nf; ++f)
-    for (int k = 0; k < c.nz; ++k)
-      for (int jb = 0; jb < by; ++jb)
-        for (int ib = 0; ib < bx; ++ib) {
-          int i = ((ib - 2) % c.nx + c.nx) % c.nx;
-          int j = ((jb - hy) % c.ny + c.ny) % c.ny;
-          Bin[f * b.nn + ib + b.s[1] * jb + b.s[2] * k] =
-              Xin[f * cnt + (size_t)i + (size_t)c.nx * ((size_t)j + (size_t)c.ny * k)];
-        }
-  sweep_box(&c, &b, axis, tau, Bin, Bout);
-  for (int f = 0; f < c.nf; ++f)
-    for (int k = 0; k < c.nz; ++k)
-      for (int j = 0; j < c.ny; ++j)
-        for (int i = 0; i < c.nx; ++i)
-          Xout[f * cnt + (size_t)i + (size_t)c.nx * ((size_t)j + (size_t)c.ny * k)] =
-              Bout[f * b.nn + (i + 2) + b.s[1] * (j + hy) + b.s[2] * k];
-  free(Bin);
-  free(Bout);
+  sweep_periodic(&c, axis, tau, Xin, Xout);
   return 0;
 }
 
@@ -779,5 +474,77 @@ int ora_diag(const ora_params* p, const double* X, ora_diag_t* d) {
   d->nu_top = -(gt + c.D) / c.eps;
   d->nu_mean = 0.5 * (d->nu_bottom + d->nu_top);
   free(rs);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* complex-step mode (checks of the adjoint)                                 */
+
+/* Nu_mean (Sec. 2, mean_Nu) of a complex state: the row means of T on the
+ * rows 0, 1, 2, M-2, M-1, M and the one-sided differences of ora_diag */
+static double complex nu_mean_cs(const coefs* c, const double complex* X) {
+  const int M = c->M;
+  const size_t plane = (size_t)c->nx * c->ny, cnt = plane * c->nz;
+  int rows[6] = {0, 1, 2, M - 2, M - 1, M};
+  double complex tm[6];
+  for (int q = 0; q < 6; ++q) {
+    int k = rows[q];
+    double z = zrow(c, k);
+    double complex sum = 0.0;
+    for (size_t t = 0; t < plane; ++t) {
+      size_t n = t + plane * k;
+      double complex rho = X[c->fR * cnt + n];
+      double complex u[3] = {0, 0, 0};
+      for (int d = 0; d < 3; ++d)
+        if (c->fm[d] >= 0) u[d] = X[c->fm[d] * cnt + n] / rho;
+      double complex uu = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
+      sum += (X[c->fE * cnt + n] / rho - 0.5 * uu - c->g * z) / c->cv;
+    }
+    tm[q] = sum / (double)plane;
+  }
+  double dz = c->h[2];
+  double complex gb = ((-3.0 * tm[0] + 4.0 * tm[1]) - tm[2]) / (2.0 * dz);
+  double complex gt = ((3.0 * tm[5] - 4.0 * tm[4]) + tm[3]) / (2.0 * dz);
+  double complex nb = -(gb + c->D) / c->eps, nt = -(gt + c->D) / c->eps;
+  return 0.5 * (nb + nt);
+}
+
+int ora_time_avg_nu_cs(const ora_params* p, const double* X0, const double* V, double h,
+                       double dRa, int nsteps, double dt, double* J, double* dJ) {
+  if (check_params(p)) return -1;
+  if (nsteps < 1 || !(dt > 0.0) || !(h > 0.0)) return -1;
+  coefs c;
+  make_coefs(p, &c);
+  set_threads(p);
+  /* Ra + i h dRa enters through mu = sqrt(Pr/Ra) and K = 1/(eps D sqrt(Ra Pr)):
+   * d mu/dRa = -mu/(2 Ra), dK/dRa = -K/(2 Ra) */
+  c.mu_cs = c.mu + (h * dRa * (-c.mu / (2.0 * p->Ra))) * I;
+  c.K_cs = c.K + (h * dRa * (-c.K / (2.0 * p->Ra))) * I;
+  size_t len = ora_state_len(p);
+  double complex* X = (double complex*)malloc(sizeof(double complex) * len);
+  double complex* Y = (double complex*)malloc(sizeof(double complex) * len);
+  for (size_t n = 0; n < len; ++n) X[n] = X0[n] + (V ? (h * V[n]) * I : 0.0);
+  int order[6], no;
+  if (p->ndim == 3) {
+    int a[6] = {2, 1, 0, 2, 1, 0}, b[6] = {2, 1, 0, 0, 1, 2};
+    for (int i = 0; i < 6; ++i) order[i] = p->sweep_order ? b[i] : a[i];
+    no = 6;
+  } else {
+    int a[4] = {2, 0, 2, 0}, b[4] = {2, 0, 0, 2};
+    for (int i = 0; i < 4; ++i) order[i] = p->sweep_order ? b[i] : a[i];
+    no = 4;
+  }
+  double complex acc = 0.0;
+  for (int s = 0; s < nsteps; ++s) {
+    for (int o = 0; o < no; ++o) {
+      sweep_periodic_cs(&c, order[o], 0.5 * dt, X, Y);
+      double complex* t = X; X = Y; Y = t;
+    }
+    acc += nu_mean_cs(&c, X);
+  }
+  *J = creal(acc) / nsteps;
+  *dJ = cimag(acc) / nsteps / h;
+  free(X);
+  free(Y);
   return 0;
 }

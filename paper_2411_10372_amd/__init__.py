@@ -136,6 +136,44 @@ def lib() -> ctypes.CDLL:
         L.mtvd_strerror.restype = ctypes.c_char_p
         L.mtvd_last_error.argtypes = [vp]
         L.mtvd_last_error.restype = ctypes.c_char_p
+        PA = ctypes.POINTER(_Params)
+        L.mtvd_batch_bytes.argtypes = [PA, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t),
+                                       ctypes.POINTER(ctypes.c_size_t)]
+        L.mtvd_batch_create.argtypes = [PA, ctypes.c_int32, vp, ctypes.POINTER(vp)]
+        L.mtvd_batch_bind.argtypes = [vp, vp, vp, vp]
+        L.mtvd_batch_offset.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+        L.mtvd_batch_init_state.argtypes = [vp]
+        L.mtvd_batch_step.argtypes = [vp, ctypes.c_int32]
+        L.mtvd_batch_diagnostics.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(_Diag)]
+        L.mtvd_batch_get_state.argtypes = [vp, ctypes.c_int32, dp, ctypes.c_size_t]
+        L.mtvd_batch_set_state.argtypes = [vp, ctypes.c_int32, dp, ctypes.c_size_t,
+                                           ctypes.c_double, ctypes.c_int64]
+        L.mtvd_batch_current.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+        L.mtvd_batch_set_tiling.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        L.mtvd_batch_get_tiling.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_int32)]
+        L.mtvd_batch_autotune.argtypes = [vp, vp, ctypes.c_int32]
+        L.mtvd_batch_destroy.argtypes = [vp]
+        L.mtvd_batch_last_error.argtypes = [vp]
+        L.mtvd_batch_last_error.restype = ctypes.c_char_p
+        L.mtvd_adj_bytes.argtypes = [P, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_size_t)]
+        L.mtvd_adj_create.argtypes = [P, ctypes.c_int32, ctypes.c_int32, vp, ctypes.POINTER(vp)]
+        L.mtvd_adj_bind.argtypes = [vp, vp]
+        L.mtvd_adj_forward.argtypes = [vp, vp, ctypes.c_double, dp, dp]
+        L.mtvd_adj_backward.argtypes = [vp, ctypes.c_double, vp, vp, dp]
+        L.mtvd_adj_destroy.argtypes = [vp]
+        L.mtvd_adj_last_error.argtypes = [vp]
+        L.mtvd_adj_last_error.restype = ctypes.c_char_p
+        for fn in ("mtvd_adj_bytes", "mtvd_adj_create", "mtvd_adj_bind", "mtvd_adj_forward",
+                   "mtvd_adj_backward", "mtvd_adj_destroy"):
+            getattr(L, fn).restype = ctypes.c_int
+        for fn in ("mtvd_batch_bytes", "mtvd_batch_create", "mtvd_batch_bind",
+                   "mtvd_batch_offset", "mtvd_batch_init_state", "mtvd_batch_step",
+                   "mtvd_batch_diagnostics", "mtvd_batch_get_state", "mtvd_batch_set_state",
+                   "mtvd_batch_current", "mtvd_batch_set_tiling", "mtvd_batch_get_tiling",
+                   "mtvd_batch_autotune", "mtvd_batch_destroy"):
+            getattr(L, fn).restype = ctypes.c_int
         for fn in ("mtvd_state_bytes", "mtvd_create", "mtvd_bind", "mtvd_init_state",
                    "mtvd_step", "mtvd_sweep", "mtvd_diagnostics", "mtvd_get_state",
                    "mtvd_set_state", "mtvd_current", "mtvd_sync", "mtvd_set_tiling",
@@ -262,3 +300,232 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+class Batch:
+    """Many independent 2D boxes advanced together (one launch per
+    directional operator for all boxes; pairs of steps replay a captured
+    HIP graph).  ``params`` is a list of :class:`Params`."""
+
+    def __init__(self, params, device=None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise MtvdError(MTVD_EHIP, "no GPU visible: the HIP library needs one")
+        self.params = list(params)
+        self.n = len(self.params)
+        self.device = torch.device(device if device is not None else "cuda")
+        L = lib()
+        arr = (_Params * self.n)(*[p._c() for p in self.params])
+        self._arr = arr
+        sb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+        rc = L.mtvd_batch_bytes(arr, self.n, ctypes.byref(sb), ctypes.byref(wb))
+        if rc != MTVD_OK:
+            raise MtvdError(rc, L.mtvd_strerror(rc).decode())
+        self.state_bytes = sb.value
+        self.ctx = None
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.bufs = [torch.empty(sb.value // 8, dtype=torch.float64, device=self.device)
+                         for _ in range(2)]
+            self.ws = torch.empty((wb.value + 7) // 8, dtype=torch.float64, device=self.device)
+            ctx = ctypes.c_void_p()
+            rc = L.mtvd_batch_create(arr, self.n, ctypes.c_void_p(self.stream.cuda_stream),
+                                     ctypes.byref(ctx))
+            if rc != MTVD_OK:
+                raise MtvdError(rc, L.mtvd_strerror(rc).decode())
+            self.ctx = ctx
+            self._check(L.mtvd_batch_bind(self.ctx, ctypes.c_void_p(self.bufs[0].data_ptr()),
+                                          ctypes.c_void_p(self.bufs[1].data_ptr()),
+                                          ctypes.c_void_p(self.ws.data_ptr())))
+
+    def _check(self, rc: int):
+        if rc != MTVD_OK:
+            L = lib()
+            msg = L.mtvd_strerror(rc).decode()
+            if self.ctx:
+                extra = L.mtvd_batch_last_error(self.ctx).decode()
+                if extra:
+                    msg += f" ({extra})"
+            raise MtvdError(rc, msg)
+
+    def init_state(self):
+        self._check(lib().mtvd_batch_init_state(self.ctx))
+
+    def step(self, n: int = 1):
+        self._check(lib().mtvd_batch_step(self.ctx, int(n)))
+
+    def diagnostics(self, box: int, check: bool = True) -> dict:
+        d = _Diag()
+        rc = lib().mtvd_batch_diagnostics(self.ctx, int(box), ctypes.byref(d))
+        if check:
+            self._check(rc)
+        out = {n: getattr(d, n) for n, _ in _Diag._fields_ if n != "tmean"}
+        out["tmean"] = list(d.tmean)
+        return out
+
+    def get_state(self, box: int) -> np.ndarray:
+        p = self.params[box]
+        X = np.empty(p.shape, dtype=np.float64)
+        self._check(lib().mtvd_batch_get_state(self.ctx, int(box),
+                                               X.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                               X.size))
+        return X
+
+    def set_state(self, box: int, X: np.ndarray, time: float = 0.0, step: int = 0):
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        if X.shape != self.params[box].shape:
+            raise ValueError("state shape mismatch")
+        self._check(lib().mtvd_batch_set_state(self.ctx, int(box),
+                                               X.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                               X.size, float(time), int(step)))
+
+    def set_tiling(self, box: int, rows_x: int = 0, rows_z: int = 0):
+        self._check(lib().mtvd_batch_set_tiling(self.ctx, int(box), int(rows_x), int(rows_z)))
+
+    def tiling(self, box: int):
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        self._check(lib().mtvd_batch_get_tiling(self.ctx, int(box), ctypes.byref(a),
+                                                ctypes.byref(b)))
+        return a.value, b.value
+
+    def autotune(self, trial_steps: int = 4):
+        """Pick rows per wave per box size by timing (state restored)."""
+        import torch
+        scratch = torch.empty((self.state_bytes + 128 * self.n + 7) // 8 + 32,
+                              dtype=torch.float64, device=self.device)
+        self._check(lib().mtvd_batch_autotune(self.ctx, ctypes.c_void_p(scratch.data_ptr()),
+                                              int(trial_steps)))
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().mtvd_batch_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Adjoint:
+    """Reverse mode of the time-averaged mean Nusselt number of a 2D box
+    with a frozen dt (``mtvd_adj_*`` in ``include/mtvd.h``):
+    J(theta, Ra) = (1/N) sum_{n=1..N} Nu_mean(X_n), X_0 = conduction state
+    with T0 + theta on interior rows.  Checkpoints every ``every`` steps live
+    in the workspace between :meth:`forward` and :meth:`backward`."""
+
+    def __init__(self, p: Params, nsteps: int, every: int = 50, device=None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise MtvdError(MTVD_EHIP, "no GPU visible: the HIP library needs one")
+        self.p, self.nsteps, self.every = p, int(nsteps), int(every)
+        self.device = torch.device(device if device is not None else "cuda")
+        self.ctx = None
+        L = lib()
+        pc = p._c()
+        wb = ctypes.c_size_t()
+        rc = L.mtvd_adj_bytes(ctypes.byref(pc), self.nsteps, self.every, ctypes.byref(wb))
+        if rc != MTVD_OK:
+            raise MtvdError(rc, L.mtvd_strerror(rc).decode())
+        self.workspace_bytes = wb.value
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.ws = torch.empty((wb.value + 7) // 8, dtype=torch.float64, device=self.device)
+            ctx = ctypes.c_void_p()
+            rc = L.mtvd_adj_create(ctypes.byref(pc), self.nsteps, self.every,
+                                   ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
+            if rc != MTVD_OK:
+                raise MtvdError(rc, L.mtvd_strerror(rc).decode())
+            self.ctx = ctx
+            self._check(L.mtvd_adj_bind(self.ctx, ctypes.c_void_p(self.ws.data_ptr())))
+
+    def _check(self, rc: int):
+        if rc != MTVD_OK:
+            L = lib()
+            msg = L.mtvd_strerror(rc).decode()
+            if self.ctx:
+                extra = L.mtvd_adj_last_error(self.ctx).decode()
+                if extra:
+                    msg += f" ({extra})"
+            raise MtvdError(rc, msg)
+
+    def _theta(self, theta):
+        import torch
+        if theta is None:
+            return None
+        t = torch.as_tensor(theta, dtype=torch.float64, device=self.device).contiguous()
+        if t.numel() != self.p.nx * self.p.nz:
+            raise ValueError(f"theta must hold nz*nx = {self.p.nx * self.p.nz} values")
+        return t
+
+    def forward(self, theta=None, dt: float = 0.0):
+        """J and the dt used (dt = 0: the CFL dt of X_0)."""
+        t = self._theta(theta)
+        self._theta_keep = t
+        J, d = ctypes.c_double(), ctypes.c_double()
+        self._check(lib().mtvd_adj_forward(self.ctx, ctypes.c_void_p(t.data_ptr() if t is not None else 0),
+                                           float(dt), ctypes.byref(J), ctypes.byref(d)))
+        return J.value, d.value
+
+    def backward(self, Jbar: float = 1.0, want_x0: bool = False):
+        """(dJ/dtheta as an (nz, nx) tensor, dJ/dX_0 or None, dJ/dRa), each
+        times Jbar."""
+        import torch
+        gt = torch.empty((self.p.nz, self.p.nx), dtype=torch.float64, device=self.device)
+        gx = torch.empty(self.p.shape, dtype=torch.float64, device=self.device) if want_x0 else None
+        gr = ctypes.c_double()
+        self._check(lib().mtvd_adj_backward(self.ctx, float(Jbar), ctypes.c_void_p(gx.data_ptr() if gx is not None else 0),
+                                            ctypes.c_void_p(gt.data_ptr()), ctypes.byref(gr)))
+        return gt, gx, gr.value
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().mtvd_adj_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _nu_function():
+    import torch
+
+    class TimeAveragedNu(torch.autograd.Function):
+        """J(theta, Ra) as a differentiable torch op; the backward pass is the
+        library's hand-written adjoint (recomputation from checkpoints)."""
+
+        @staticmethod
+        def forward(ctx, theta, ra, adjoint, dt):
+            if abs(float(ra) - adjoint.p.Ra) > 1e-12 * adjoint.p.Ra:
+                raise ValueError("Ra differs from the one the adjoint was created for")
+            J, _ = adjoint.forward(theta.detach(), dt)
+            ctx.adjoint = adjoint
+            ctx.ra_device = ra.device if torch.is_tensor(ra) else None
+            return torch.tensor(J, dtype=torch.float64, device=theta.device)
+
+        @staticmethod
+        def backward(ctx, gJ):
+            gt, _, gr = ctx.adjoint.backward(float(gJ))
+            gra = None
+            if ctx.ra_device is not None:
+                gra = torch.tensor(gr, dtype=torch.float64, device=ctx.ra_device)
+            return gt.to(gJ.device), gra, None, None
+
+    return TimeAveragedNu
+
+
+_TAN = None
+
+
+def time_averaged_nu(theta, ra, adjoint: Adjoint, dt: float = 0.0):
+    """Differentiable J(theta, Ra) (see :class:`Adjoint`).  ``theta`` is an
+    (nz, nx) float64 tensor on the GPU, ``ra`` a 0-d float64 tensor equal to
+    the adjoint's Ra; gradients flow to both."""
+    global _TAN
+    if _TAN is None:
+        _TAN = _nu_function()
+    return _TAN.apply(theta, ra, adjoint, dt)

@@ -7,10 +7,11 @@
 // output columns plus two halo columns on each side (lane l <-> column
 // i0 - 2 + l, periodic) and marches up a chunk of rows.  Values along z
 // stay in registers in rings of period 4 (the march is unrolled by 4 so
-// every ring index is a compile-time constant); values along x move
-// between lanes with cross-lane shuffles.  Each sweep reads and writes the
-// state once: 4 fields x 8 B in, 4 x 8 B out per node, plus halo re-reads
-// that hit in L2.
+// every ring index is a compile-time constant); values along x move between
+// neighbouring lanes with DPP wave shifts.  Rows are prefetched two
+// iterations ahead so a wave's loads overlap its own arithmetic.  Each sweep
+// reads and writes the state once: 4 fields x 8 B in, 4 x 8 B out per node,
+// plus halo re-reads that hit in L2.
 #include "mtvd_device.h"
 #include "mtvd_launch.h"
 
@@ -53,18 +54,15 @@ __device__ __forceinline__ void store2(const Coef& c, double* __restrict__ Y, in
   Y[n + 3 * c.cnt] = v.E;
 }
 
-__device__ __forceinline__ double sh_dn(double v) { return __shfl_down(v, 1, 64); }
-__device__ __forceinline__ double sh_up(double v) { return __shfl_up(v, 1, 64); }
-__device__ __forceinline__ N2 sh_dn(const N2& v) {
-  return N2{sh_dn(v.r), sh_dn(v.mx), sh_dn(v.mz), sh_dn(v.E)};
-}
-__device__ __forceinline__ N2 sh_up(const N2& v) {
-  return N2{sh_up(v.r), sh_up(v.mx), sh_up(v.mz), sh_up(v.E)};
-}
+// value of the next lane up (i+1) / down (i-1)
+__device__ __forceinline__ double up(double v) { return lane_from_above(v); }
+__device__ __forceinline__ double dn(double v) { return lane_from_below(v); }
+__device__ __forceinline__ N2 up(const N2& v) { return N2{up(v.r), up(v.mx), up(v.mz), up(v.E)}; }
+__device__ __forceinline__ N2 dn(const N2& v) { return N2{dn(v.r), dn(v.mx), dn(v.mz), dn(v.E)}; }
 
-// Per-wave bookkeeping of the step: the first sweep of a step publishes dt
-// and time and clears the other max slot; the last one folds |u_a| + c of
-// its output into that slot.
+// Per-step bookkeeping: the first sweep of a step publishes dt and time and
+// clears the other max slot; the last one folds |u_a| + c of its output
+// into that slot.
 __device__ __forceinline__ void step_head(const Coef& c, Shared* sh, int slot, int first,
                                           double dt) {
   if (first && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -99,14 +97,16 @@ __device__ __forceinline__ void out_max(const Coef& c, const N2& o, double z, do
 }
 
 // ---------------------------------------------------------------------------
-// L_z(tau): flux differences along the march, cross x-derivatives by shuffle.
+// L_z(tau): flux differences along the march, cross x-derivatives from the
+// neighbouring lanes.
 
 struct Z2 {
-  N2 x[4];      // X^n rows, slot row & 3
-  P2 pn[4];     // primitives of X^n
+  N2 pf[2];     // prefetched rows f+1, f+2, slot row & 1
+  N2 x[4];      // X^n rows f-3..f, slot row & 3
+  P2 pn[4];     // primitives of X^n (p filled on use)
   double s[4];  // |u_z| + c of X^n
-  N2 dl[4];     // dX_{row+1/2} = X[row+1] - X[row]
-  double G[4];  // TVD coefficient of face row+1/2
+  double G[2];  // TVD coefficient of face row+1/2
+  N2 Dp;        // G dX of the face below the next output row
   N2 F[2];      // predictor flux (forward inner derivatives), slot row & 1
   N2 xp[4];     // X^P
   P2 pp[4];     // primitives of X^P
@@ -127,16 +127,16 @@ __device__ __forceinline__ void z2_iter(const Coef& c, Z2& st, int f, int fs, in
   constexpr int c1 = (S + 3) & 3;    // row f-1
   constexpr int c2 = (S + 2) & 3;    // row f-2
   constexpr int c3 = (S + 1) & 3;    // row f-3
-  constexpr int c4 = S & 3;          // row f-4
-  constexpr int e2 = S & 1;          // row f-2 in period-2 rings
-  constexpr int e3 = (S + 1) & 1;    // row f-3
+  constexpr int c4 = S & 3;          // row f-4 (its slot is reused by row f)
+  constexpr int e0 = S & 1;          // row f (and f-2) in period-2 rings
+  constexpr int e1 = (S + 1) & 1;    // row f-1 (and f-3)
 
-  // A: load row f and its primitives; dX of face f-1/2
+  // A: row f (prefetched) and its primitives; prefetch row f+2
   if (f <= M) {
-    st.x[c0] = load2(c, X, f, L.col);
+    st.x[c0] = st.pf[e0];
+    if (f + 2 <= M) st.pf[e0] = load2(c, X, f + 2, L.col);
     st.pn[c0] = prim2(c, st.x[c0], zr[f]);
     st.s[c0] = fabs(st.pn[c0].uz) + sound(c, st.pn[c0].T);
-    if (f - 1 >= fs) st.dl[c1] = st.x[c0] - st.x[c1];
   }
   const int r = f - 2;
   // B: predictor flux F_r (inner z forward; second-order forward at the
@@ -156,9 +156,11 @@ __device__ __forceinline__ void z2_iter(const Coef& c, Z2& st, int f, int fs, in
       dzuz = (q1.uz - q0.uz) * c.ihz;
       dzT = (q1.T - q0.T) * c.ihz;
     }
-    double dxux = (sh_dn(q0.ux) - sh_up(q0.ux)) * (0.5 * c.ihx);
-    double dxuz = (sh_dn(q0.uz) - sh_up(q0.uz)) * (0.5 * c.ihx);
-    st.F[e2] = flux_z2(c, st.x[c2], q0, dzux, dzuz, dzT, dxux, dxuz);
+    double dxux = (up(q0.ux) - dn(q0.ux)) * (0.5 * c.ihx);
+    double dxuz = (up(q0.uz) - dn(q0.uz)) * (0.5 * c.ihx);
+    P2 q = q0;
+    q.p = c.a * st.x[c2].r * q0.T;
+    st.F[e0] = flux_z2(c, st.x[c2], q, dzux, dzuz, dzT, dxux, dxuz);
   }
   // C: predictor X^P_r = X_r - (tau/dz)(F_r - F_{r-1}) + tau S(X_r); plates:
   //    u = 0, T = T_plate, top density from the backward mass-flux difference
@@ -172,8 +174,10 @@ __device__ __forceinline__ void z2_iter(const Coef& c, Z2& st, int f, int fs, in
       st.xp[c2] = N2{rho, 0.0, 0.0, rho * (c.cv * c.Tt + c.g * zr[M])};
       st.pp[c2] = P2{0.0, 0.0, c.Tt, c.a * rho * c.Tt};
     } else {
-      N2 v = st.x[c2] - N2{lz * (st.F[e2].r - st.F[e3].r), lz * (st.F[e2].mx - st.F[e3].mx),
-                           lz * (st.F[e2].mz - st.F[e3].mz), lz * (st.F[e2].E - st.F[e3].E)};
+      const N2& Fa = st.F[e0];
+      const N2& Fb = st.F[e1];
+      N2 v = st.x[c2] - N2{lz * (Fa.r - Fb.r), lz * (Fa.mx - Fb.mx), lz * (Fa.mz - Fb.mz),
+                           lz * (Fa.E - Fb.E)};
       v.mz = v.mz + tau * (-c.g * st.x[c2].r);
       st.xp[c2] = v;
       st.pp[c2] = prim2(c, v, zr[r]);
@@ -196,68 +200,68 @@ __device__ __forceinline__ void z2_iter(const Coef& c, Z2& st, int f, int fs, in
       dzuz = (q0.uz - qm.uz) * c.ihz;
       dzT = (q0.T - qm.T) * c.ihz;
     }
-    double dxux = (sh_dn(q0.ux) - sh_up(q0.ux)) * (0.5 * c.ihx);
-    double dxuz = (sh_dn(q0.uz) - sh_up(q0.uz)) * (0.5 * c.ihx);
-    st.FP[e2] = flux_z2(c, st.xp[c2], q0, dzux, dzuz, dzT, dxux, dxuz);
+    double dxux = (up(q0.ux) - dn(q0.ux)) * (0.5 * c.ihx);
+    double dxuz = (up(q0.uz) - dn(q0.uz)) * (0.5 * c.ihx);
+    st.FP[e0] = flux_z2(c, st.xp[c2], q0, dzux, dzuz, dzT, dxux, dxuz);
   }
   // E: TVD coefficient of face q+1/2, q = f-2 (zero on the two faces next
-  //    to the plates)
-  {
-    const int q = r;
-    if (q >= k0 - 1 && q >= 0 && q <= M - 1) {
-      double G = 0.0;
-      if (c.tvd_on && q >= 1 && q <= M - 2) {
-        const N2& dm = st.dl[c3];
-        const N2& d0 = st.dl[c2];
-        const N2& dp = st.dl[c1];
-        double Co = lz * fmax(st.s[c2], st.s[c1]);
-        G = tvd_G(c, dot2(dm, d0), dot2(d0, dp), dot2(d0, d0), Co);
-      }
-      st.G[c2] = G;
+  //    to the plates); the jumps come from the X^n ring
+  if (r >= k0 - 1 && r >= 0 && r <= M - 1) {
+    double G = 0.0;
+    if (c.tvd_on && r >= 1 && r <= M - 2) {
+      N2 dm = st.x[c2] - st.x[c3];
+      N2 d0 = st.x[c1] - st.x[c2];
+      N2 dp = st.x[c0] - st.x[c1];
+      double Co = lz * fmax(st.s[c2], st.s[c1]);
+      G = tvd_G(c, dot2(dm, d0), dot2(d0, dp), dot2(d0, d0), Co);
     }
+    st.G[e0] = G;
   }
-  // F: corrector, average, TVD term and plate closure of row f-3
+  // F: corrector, average, TVD term and plate closure of row o = f-3; the
+  //    face o+1/2 term G dX is carried to the next row as its o-1/2 term
   const int o = f - 3;
-  if (o >= k0 && o < k1) {
+  if (o >= k0 - 1 && o >= 0 && o < k1 && o <= M - 1) {
+    N2 d0 = st.x[c2] - st.x[c3];
+    double G = st.G[e1];
+    N2 Dc{G * d0.r, G * d0.mx, G * d0.mz, G * d0.E};
+    if (o >= k0 && o >= 1) {
+      const N2& fp1 = st.FP[e0];
+      const N2& fp0 = st.FP[e1];
+      N2 xc = st.x[c3] - N2{lz * (fp1.r - fp0.r), lz * (fp1.mx - fp0.mx),
+                            lz * (fp1.mz - fp0.mz), lz * (fp1.E - fp0.E)};
+      xc.mz = xc.mz + tau * (-c.g * st.xp[c3].r);
+      const N2& xp = st.xp[c3];
+      const N2& Dm = st.Dp;
+      N2 out;
+      out.r = 0.5 * (xp.r + xc.r) + (Dc.r - Dm.r);
+      out.mx = 0.5 * (xp.mx + xc.mx) + (Dc.mx - Dm.mx);
+      out.mz = 0.5 * (xp.mz + xc.mz) + (Dc.mz - Dm.mz);
+      out.E = 0.5 * (xp.E + xc.E) + (Dc.E - Dm.E);
+      if (FUSE) out_max(c, out, zr[o], st.mx, st.mz, st.bad, L.out);
+      if (L.out) store2(c, Y, o, L.col, out);
+    }
+    st.Dp = Dc;
+  }
+  if (o >= k0 && o < k1 && (o == 0 || o == M)) {
     N2 out;
     if (o == 0) {
       double rho = st.x[c3].r - lz * (st.xp[c2].mz - 0.0);
       out = N2{rho, 0.0, 0.0, rho * (c.cv * c.Tb + c.g * zr[0])};
-    } else if (o == M) {
+    } else {
       double rho = st.xp[c3].r;
       out = N2{rho, 0.0, 0.0, rho * (c.cv * c.Tt + c.g * zr[M])};
-    } else {
-      const N2& fp1 = st.FP[e2];
-      const N2& fp0 = st.FP[e3];
-      N2 xc = st.x[c3] - N2{lz * (fp1.r - fp0.r), lz * (fp1.mx - fp0.mx),
-                            lz * (fp1.mz - fp0.mz), lz * (fp1.E - fp0.E)};
-      xc.mz = xc.mz + tau * (-c.g * st.xp[c3].r);
-      const N2& d0 = st.dl[c3];
-      const N2& dm = st.dl[c4];
-      double G0 = st.G[c3], Gm = st.G[c4];
-      const N2& xp = st.xp[c3];
-      out.r = 0.5 * (xp.r + xc.r) + (G0 * d0.r - Gm * dm.r);
-      out.mx = 0.5 * (xp.mx + xc.mx) + (G0 * d0.mx - Gm * dm.mx);
-      out.mz = 0.5 * (xp.mz + xc.mz) + (G0 * d0.mz - Gm * dm.mz);
-      out.E = 0.5 * (xp.E + xc.E) + (G0 * d0.E - Gm * dm.E);
     }
     if (FUSE) out_max(c, out, zr[o], st.mx, st.mz, st.bad, L.out);
     if (L.out) store2(c, Y, o, L.col, out);
   }
 }
 
+// one wave's share of L_z: columns of `strip`, output rows of `chunk`
 template <bool FUSE>
-__global__ __launch_bounds__(256) void sweep_z2d(Coef c, Shared* sh, const double* zr,
-                                                 int slot, int first,
-                                                 const double* __restrict__ X,
-                                                 double* __restrict__ Y, int kc,
-                                                 int nstrips, int nwaves) {
-  const int lane = threadIdx.x & 63;
-  const int w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const double dt = step_dt(c, sh, slot);
-  step_head(c, sh, slot, first, dt);
-  if (w >= nwaves) return;
-  const int strip = w % nstrips, chunk = w / nstrips;
+__device__ __forceinline__ void z2_wave(const Coef& c, Shared* sh, const double* zr, int slot,
+                                        double dt, const double* __restrict__ X,
+                                        double* __restrict__ Y, int kc, int strip,
+                                        int chunk, int lane) {
   const Cols L = lane_cols(c, strip, lane);
   const int k0 = chunk * kc;
   const int k1 = min(k0 + kc, c.nz);
@@ -267,8 +271,22 @@ __global__ __launch_bounds__(256) void sweep_z2d(Coef c, Shared* sh, const doubl
   st.mx = 0.0;
   st.mz = 0.0;
   st.bad = false;
+  st.Dp = N2{0.0, 0.0, 0.0, 0.0};
   const int fs = max(0, k0 - 2);
   const int fe = k1 + 2;
+  // prologue: rows fs and fs+1 into their prefetch slots (slot = row & 1,
+  // written with constant indices so the ring stays in registers)
+  {
+    N2 a = load2(c, X, fs, L.col);
+    N2 b = (fs + 1 <= c.M) ? load2(c, X, fs + 1, L.col) : a;
+    if (fs & 1) {
+      st.pf[1] = a;
+      st.pf[0] = b;
+    } else {
+      st.pf[0] = a;
+      st.pf[1] = b;
+    }
+  }
   for (int fb = fs & ~3; fb <= fe; fb += 4) {
     z2_iter<0, FUSE>(c, st, fb + 0, fs, fe, k0, k1, L, zr, X, Y, tau, lz);
     z2_iter<1, FUSE>(c, st, fb + 1, fs, fe, k0, k1, L, zr, X, Y, tau, lz);
@@ -278,14 +296,29 @@ __global__ __launch_bounds__(256) void sweep_z2d(Coef c, Shared* sh, const doubl
   if (FUSE) fold_max(sh, slot, st.mx, st.mz, st.bad);
 }
 
+template <bool FUSE>
+__global__ __launch_bounds__(256) void sweep_z2d(Coef c, Shared* sh, const double* zr,
+                                                 int slot, int first,
+                                                 const double* __restrict__ X,
+                                                 double* __restrict__ Y, int kc,
+                                                 int nstrips, int nwaves) {
+  const int lane = threadIdx.x & 63;
+  // wave-uniform by construction; readfirstlane lets the compiler keep it scalar
+  const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  const double dt = step_dt(c, sh, slot);
+  step_head(c, sh, slot, first, dt);
+  if (w >= nwaves) return;
+  z2_wave<FUSE>(c, sh, zr, slot, dt, X, Y, kc, w % nstrips, w / nstrips, lane);
+}
+
 // ---------------------------------------------------------------------------
 // L_x(tau): flux differences across lanes, cross z-derivatives from the
 // march.  Plate rows are copied through.
 
 struct X2 {
+  N2 pf[2];
   N2 x[4];
-  P2 pn[4];
-  double s[4];   // |u_x| + c of X^n
+  P2 pn[4];      // p filled on use
   N2 xp[4];
   P2 pp[4];
   double mx, mz;
@@ -304,11 +337,12 @@ __device__ __forceinline__ void x2_iter(const Coef& c, X2& st, int f, int fs, in
   constexpr int c1 = (S + 3) & 3;    // row f-1
   constexpr int c2 = (S + 2) & 3;    // row f-2
   constexpr int c3 = (S + 1) & 3;    // row f-3
+  constexpr int e0 = S & 1;
 
   if (f <= M) {
-    st.x[c0] = load2(c, X, f, L.col);
+    st.x[c0] = st.pf[e0];
+    if (f + 2 <= M) st.pf[e0] = load2(c, X, f + 2, L.col);
     st.pn[c0] = prim2(c, st.x[c0], zr[f]);
-    st.s[c0] = fabs(st.pn[c0].ux) + sound(c, st.pn[c0].T);
   }
   // predictor on row f-1: X^P_i = X_i - (tau/dx)(F_i - F_{i-1})
   const int r1 = f - 1;
@@ -317,14 +351,15 @@ __device__ __forceinline__ void x2_iter(const Coef& c, X2& st, int f, int fs, in
       st.xp[c1] = st.x[c1];
       st.pp[c1] = st.pn[c1];
     } else {
-      const P2& q = st.pn[c1];
-      double dxux = (sh_dn(q.ux) - q.ux) * c.ihx;
-      double dxuz = (sh_dn(q.uz) - q.uz) * c.ihx;
-      double dxT = (sh_dn(q.T) - q.T) * c.ihx;
+      P2 q = st.pn[c1];
+      q.p = c.a * st.x[c1].r * q.T;
+      double dxux = (up(q.ux) - q.ux) * c.ihx;
+      double dxuz = (up(q.uz) - q.uz) * c.ihx;
+      double dxT = (up(q.T) - q.T) * c.ihx;
       double dzux = (st.pn[c0].ux - st.pn[c2].ux) * (0.5 * c.ihz);
       double dzuz = (st.pn[c0].uz - st.pn[c2].uz) * (0.5 * c.ihz);
       N2 Fi = flux_x2(c, st.x[c1], q, dxux, dxuz, dxT, dzux, dzuz);
-      N2 Fm = sh_up(Fi);
+      N2 Fm = dn(Fi);
       N2 v = st.x[c1] - N2{lx * (Fi.r - Fm.r), lx * (Fi.mx - Fm.mx), lx * (Fi.mz - Fm.mz),
                            lx * (Fi.E - Fm.E)};
       st.xp[c1] = v;
@@ -339,27 +374,28 @@ __device__ __forceinline__ void x2_iter(const Coef& c, X2& st, int f, int fs, in
       out = st.x[c2];
     } else {
       const P2& q = st.pp[c2];
-      double dxux = (q.ux - sh_up(q.ux)) * c.ihx;
-      double dxuz = (q.uz - sh_up(q.uz)) * c.ihx;
-      double dxT = (q.T - sh_up(q.T)) * c.ihx;
+      double dxux = (q.ux - dn(q.ux)) * c.ihx;
+      double dxuz = (q.uz - dn(q.uz)) * c.ihx;
+      double dxT = (q.T - dn(q.T)) * c.ihx;
       double dzux = (st.pp[c1].ux - st.pp[c3].ux) * (0.5 * c.ihz);
       double dzuz = (st.pp[c1].uz - st.pp[c3].uz) * (0.5 * c.ihz);
       N2 Fi = flux_x2(c, st.xp[c2], q, dxux, dxuz, dxT, dzux, dzuz);
-      N2 Fp = sh_dn(Fi);
+      N2 Fp = up(Fi);
       const N2& x0 = st.x[c2];
       N2 xc = x0 - N2{lx * (Fp.r - Fi.r), lx * (Fp.mx - Fi.mx), lx * (Fp.mz - Fi.mz),
                       lx * (Fp.E - Fi.E)};
       // TVD: face i+1/2 belongs to lane i
-      N2 d0 = sh_dn(x0) - x0;
+      N2 d0 = up(x0) - x0;
       double G = 0.0;
       if (c.tvd_on) {
-        N2 dm = sh_up(d0);
-        N2 dp = sh_dn(d0);
-        double Co = lx * fmax(st.s[c2], sh_dn(st.s[c2]));
+        N2 dm = dn(d0);
+        N2 dp = up(d0);
+        double s0 = fabs(st.pn[c2].ux) + sound(c, st.pn[c2].T);
+        double Co = lx * fmax(s0, up(s0));
         G = tvd_G(c, dot2(dm, d0), dot2(d0, dp), dot2(d0, d0), Co);
       }
       N2 D{G * d0.r, G * d0.mx, G * d0.mz, G * d0.E};
-      N2 Dm = sh_up(D);
+      N2 Dm = dn(D);
       const N2& xp = st.xp[c2];
       out.r = 0.5 * (xp.r + xc.r) + (D.r - Dm.r);
       out.mx = 0.5 * (xp.mx + xc.mx) + (D.mx - Dm.mx);
@@ -371,18 +407,12 @@ __device__ __forceinline__ void x2_iter(const Coef& c, X2& st, int f, int fs, in
   }
 }
 
+// one wave's share of L_x: columns of `strip`, output rows of `chunk`
 template <bool FUSE>
-__global__ __launch_bounds__(256) void sweep_x2d(Coef c, Shared* sh, const double* zr,
-                                                 int slot, int first,
-                                                 const double* __restrict__ X,
-                                                 double* __restrict__ Y, int kc,
-                                                 int nstrips, int nwaves) {
-  const int lane = threadIdx.x & 63;
-  const int w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const double dt = step_dt(c, sh, slot);
-  step_head(c, sh, slot, first, dt);
-  if (w >= nwaves) return;
-  const int strip = w % nstrips, chunk = w / nstrips;
+__device__ __forceinline__ void x2_wave(const Coef& c, Shared* sh, const double* zr, int slot,
+                                        double dt, const double* __restrict__ X,
+                                        double* __restrict__ Y, int kc, int strip,
+                                        int chunk, int lane) {
   const Cols L = lane_cols(c, strip, lane);
   const int k0 = chunk * kc;
   const int k1 = min(k0 + kc, c.nz);
@@ -393,6 +423,19 @@ __global__ __launch_bounds__(256) void sweep_x2d(Coef c, Shared* sh, const doubl
   st.bad = false;
   const int fs = max(0, k0 - 2);
   const int fe = k1 + 1;
+  // prologue: rows fs and fs+1 into their prefetch slots (slot = row & 1,
+  // written with constant indices so the ring stays in registers)
+  {
+    N2 a = load2(c, X, fs, L.col);
+    N2 b = (fs + 1 <= c.M) ? load2(c, X, fs + 1, L.col) : a;
+    if (fs & 1) {
+      st.pf[1] = a;
+      st.pf[0] = b;
+    } else {
+      st.pf[0] = a;
+      st.pf[1] = b;
+    }
+  }
   for (int fb = fs & ~3; fb <= fe; fb += 4) {
     x2_iter<0, FUSE>(c, st, fb + 0, fs, fe, k0, k1, L, zr, X, Y, lx);
     x2_iter<1, FUSE>(c, st, fb + 1, fs, fe, k0, k1, L, zr, X, Y, lx);
@@ -402,9 +445,76 @@ __global__ __launch_bounds__(256) void sweep_x2d(Coef c, Shared* sh, const doubl
   if (FUSE) fold_max(sh, slot, st.mx, st.mz, st.bad);
 }
 
+template <bool FUSE>
+__global__ __launch_bounds__(256) void sweep_x2d(Coef c, Shared* sh, const double* zr,
+                                                 int slot, int first,
+                                                 const double* __restrict__ X,
+                                                 double* __restrict__ Y, int kc,
+                                                 int nstrips, int nwaves) {
+  const int lane = threadIdx.x & 63;
+  // wave-uniform by construction; readfirstlane lets the compiler keep it scalar
+  const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  const double dt = step_dt(c, sh, slot);
+  step_head(c, sh, slot, first, dt);
+  if (w >= nwaves) return;
+  x2_wave<FUSE>(c, sh, zr, slot, dt, X, Y, kc, w % nstrips, w / nstrips, lane);
+}
+
+// ---------------------------------------------------------------------------
+// Many independent boxes in one launch: every wave takes one work item
+// (box, strip, chunk, lead) and runs the same per-wave code on that box's
+// constants, state, plate table and scalars.  The lead wave of a box does
+// the box's per-step bookkeeping.
+
+template <int AXIS, bool FUSE>
+__global__ __launch_bounds__(256) void sweep_batch2d(const BoxDesc* __restrict__ boxes,
+                                                     const int4* __restrict__ items,
+                                                     int nitems, Shared* shs,
+                                                     const double* zarena, int slot,
+                                                     int first, const double* X,
+                                                     double* Y) {
+  const int lane = threadIdx.x & 63;
+  // wave-uniform by construction; readfirstlane lets the compiler keep it scalar
+  const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  if (w >= nitems) return;
+  const int4 it = items[w];
+  const BoxDesc* bd = boxes + it.x;
+  const Coef c = bd->c;
+  Shared* sh = shs + it.x;
+  const double dt = step_dt(c, sh, slot);
+  if (first && it.w && lane == 0) {
+    sh->time += dt;
+    sh->dt_last = dt;
+    for (int a = 0; a < 4; ++a) sh->smax[slot ^ 1][a] = 0ull;
+  }
+  const double* zr = zarena + bd->zoff;
+  if (AXIS == 2)
+    z2_wave<FUSE>(c, sh, zr, slot, dt, X + bd->off, Y + bd->off, bd->kc_z, it.y, it.z, lane);
+  else
+    x2_wave<FUSE>(c, sh, zr, slot, dt, X + bd->off, Y + bd->off, bd->kc_x, it.y, it.z, lane);
+}
+
 // ---------------------------------------------------------------------------
 
 int strips_2d(int nx) { return (nx + kStrip - 1) / kStrip; }
+
+hipError_t launch_batch_2d(int axis, const BoxDesc* boxes, const int4* items, int nitems,
+                           Shared* shs, const double* zarena, int slot, int first, bool fuse,
+                           const double* X, double* Y, hipStream_t s) {
+  const int grid = (nitems + 3) / 4;
+  if (axis == 2) {
+    if (fuse)
+      sweep_batch2d<2, true><<<grid, 256, 0, s>>>(boxes, items, nitems, shs, zarena, slot, first, X, Y);
+    else
+      sweep_batch2d<2, false><<<grid, 256, 0, s>>>(boxes, items, nitems, shs, zarena, slot, first, X, Y);
+  } else {
+    if (fuse)
+      sweep_batch2d<0, true><<<grid, 256, 0, s>>>(boxes, items, nitems, shs, zarena, slot, first, X, Y);
+    else
+      sweep_batch2d<0, false><<<grid, 256, 0, s>>>(boxes, items, nitems, shs, zarena, slot, first, X, Y);
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_sweep_2d(int axis, const Coef& c, Shared* sh, const double* zr, int slot,
                            int first, bool fuse, const double* X, double* Y, int kc,

@@ -2,9 +2,10 @@
 // operators L_x, L_y, L_z in 3D (Sec. 3.1 of arXiv:2411.10372).
 //
 // Launch shape: a block of kNW = 8 waves.  Lanes run along x (60 output
-// columns per wave plus two halo columns each side, exchanged with
-// cross-lane shuffles); each wave marches along one axis with its values
-// in period-4 register rings; the 8 waves of a block sit at consecutive
+// columns per wave plus two halo columns each side, exchanged with DPP wave
+// shifts); each wave marches along one axis with its values in period-4
+// register rings and rows prefetched two ahead; the 8 waves of a block sit
+// at consecutive
 // indices of the third axis, 4 of them produce output and 2 on each side
 // are halo, and they exchange two scalars per row through LDS.
 //   L_z: march z (flux direction, plates), waves along y (periodic)
@@ -29,7 +30,7 @@ __device__ __forceinline__ N3 sub3(const N3& a, const N3& b) {
 }
 
 __device__ __forceinline__ P3 prim3(const Coef& c, const N3& x, double z) {
-  double ri = 1.0 / x.r;
+  double ri = frcp(x.r);
   P3 q;
   q.u[0] = x.m[0] * ri;
   q.u[1] = x.m[1] * ri;
@@ -73,8 +74,9 @@ __device__ __forceinline__ N3 flux3(const Coef& c, const N3& x, const P3& q,
   return F;
 }
 
-__device__ __forceinline__ double shd(double v) { return __shfl_down(v, 1, 64); }
-__device__ __forceinline__ double shu(double v) { return __shfl_up(v, 1, 64); }
+// value of lane i+1 (shd) / lane i-1 (shu)
+__device__ __forceinline__ double shd(double v) { return lane_from_above(v); }
+__device__ __forceinline__ double shu(double v) { return lane_from_below(v); }
 __device__ __forceinline__ N3 shd(const N3& v) {
   return N3{shd(v.r), {shd(v.m[0]), shd(v.m[1]), shd(v.m[2])}, shd(v.E)};
 }
@@ -181,12 +183,13 @@ __device__ __forceinline__ void head3(Shared* sh, int slot, int first, double dt
 // AX = 1: march y, waves along z.
 
 struct MF {
-  N3 x[4];
-  P3 pn[4];
+  N3 pf[2];                // prefetched rows f+1, f+2 (slot row & 1)
+  N3 x[4];                 // X^n rows f-3..f (slot row & 3)
+  P3 pn[4];                // primitives of X^n (p filled on use)
   double s[4];             // |u_AX| + c of X^n
   double bb[4], bm[4];     // d_B u_B and d_B u_AX of X^n (across waves)
-  N3 dl[4];                // dX_{row+1/2}
-  double G[4];
+  double G[2];             // TVD coefficient of face row+1/2
+  N3 Dp;                   // G dX of the face below the next output row
   N3 F[2];
   N3 xp[4];
   P3 pp[4];
@@ -209,7 +212,7 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
   const double ihm = (AX == 2) ? c.ihz : c.ihy;
   const double ihb2 = 0.5 * ((B == 1) ? c.ihy : c.ihz);
   constexpr int c0 = S & 3, c1 = (S + 3) & 3, c2 = (S + 2) & 3, c3 = (S + 1) & 3, c4 = S & 3;
-  constexpr int e2 = S & 1, e3 = (S + 1) & 1;
+  constexpr int e0 = S & 1, e1 = (S + 1) & 1;
   const int role = (w == 0 || w == kNW - 1) ? 0 : ((w == 1 || w == kNW - 2) ? 1 : 2);
   // node of march row `row`
   auto node = [&](int row) -> long long {
@@ -218,14 +221,15 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
   };
   auto zof = [&](int row) -> double { return (AX == 2) ? zr[row] : zr[bidx]; };
 
-  // A: row f of X^n, its primitives, dX of face f-1/2; exchange across waves
+  // A: row f of X^n (prefetched), its primitives; prefetch row f+2;
+  //    exchange across waves
   const bool have_f = (AX == 2) ? (f <= M) : true;
   if (have_f) {
     if (bval) {
-      st.x[c0] = load3(c, X, node(f));
+      st.x[c0] = st.pf[e0];
+      if (AX == 1 || f + 2 <= M) st.pf[e0] = load3(c, X, node(f + 2));
       st.pn[c0] = prim3(c, st.x[c0], zof(f));
       st.s[c0] = fabs(st.pn[c0].u[AX]) + sound(c, st.pn[c0].T);
-      if (f - 1 >= fs) st.dl[c1] = sub3(st.x[c0], st.x[c1]);
     }
     double ub = bval ? st.pn[c0].u[B] : 0.0, um = bval ? st.pn[c0].u[AX] : 0.0;
     exchange(xa, w, lane, ub, um, ihb2, st.bb[c0], st.bm[c0]);
@@ -234,7 +238,7 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
   const bool rin_F = (AX == 2) ? (r >= 0 && r <= M - 1) : true;
   // B: predictor flux F_r (inner derivatives forward along the march)
   if (r >= m0 - 2 && rin_F && role >= 1 && bval && !bwall) {
-    const P3& q0 = st.pn[c2];
+    P3 q0 = st.pn[c2];
     const P3& q1 = st.pn[c1];
     double du[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     double dT;
@@ -253,7 +257,8 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
     du[AX][0] = (shd(q0.u[AX]) - shu(q0.u[AX])) * (0.5 * c.ihx);
     du[B][B] = st.bb[c2];
     du[AX][B] = st.bm[c2];
-    st.F[e2] = flux3<AX>(c, st.x[c2], q0, du, dT);
+    q0.p = c.a * st.x[c2].r * q0.T;
+    st.F[e0] = flux3<AX>(c, st.x[c2], q0, du, dT);
   }
   // C: predictor X^P_r; exchange its velocities across waves
   const bool rin_P = (AX == 2) ? (r >= 0 && r <= M) : true;
@@ -262,6 +267,7 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
       if (bwall) {
         st.xp[c2] = st.x[c2];
         st.pp[c2] = st.pn[c2];
+        st.pp[c2].p = c.a * st.x[c2].r * st.pn[c2].T;
       } else if (AX == 2 && r == 0) {
         double rho = st.x[c2].r;
         st.xp[c2] = N3{rho, {0.0, 0.0, 0.0}, rho * (c.cv * c.Tb + c.g * zr[0])};
@@ -271,8 +277,8 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
         st.xp[c2] = N3{rho, {0.0, 0.0, 0.0}, rho * (c.cv * c.Tt + c.g * zr[M])};
         st.pp[c2] = P3{{0.0, 0.0, 0.0}, c.Tt, c.a * rho * c.Tt};
       } else {
-        const N3& Fa = st.F[e2];
-        const N3& Fb = st.F[e3];
+        const N3& Fa = st.F[e0];
+        const N3& Fb = st.F[e1];
         const N3& x0 = st.x[c2];
         N3 v;
         v.r = x0.r - lm * (Fa.r - Fb.r);
@@ -310,52 +316,62 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
     du[AX][0] = (shd(q0.u[AX]) - shu(q0.u[AX])) * (0.5 * c.ihx);
     du[B][B] = st.pb[c2];
     du[AX][B] = st.pm[c2];
-    st.FP[e2] = flux3<AX>(c, st.xp[c2], q0, du, dT);
+    st.FP[e0] = flux3<AX>(c, st.xp[c2], q0, du, dT);
   }
-  // E: TVD coefficient of face r+1/2 along the march
+  // E: TVD coefficient of face r+1/2 along the march, jumps from the X ring
   const bool rin_G = (AX == 2) ? (r >= 0 && r <= M - 1) : true;
   if (r >= m0 - 1 && rin_G && role == 2 && bval && !bwall) {
     double G = 0.0;
     const bool active = (AX == 2) ? (r >= 1 && r <= M - 2) : true;
     if (c.tvd_on && active) {
-      const N3& dm = st.dl[c3];
-      const N3& d0 = st.dl[c2];
-      const N3& dp = st.dl[c1];
+      N3 dm = sub3(st.x[c2], st.x[c3]);
+      N3 d0 = sub3(st.x[c1], st.x[c2]);
+      N3 dp = sub3(st.x[c0], st.x[c1]);
       double Co = lm * fmax(st.s[c2], st.s[c1]);
       G = tvd_G(c, dot3(dm, d0), dot3(d0, dp), dot3(d0, d0), Co);
     }
-    st.G[c2] = G;
+    st.G[e0] = G;
   }
-  // F: output row f-3
+  // F: output row o = f-3; the face o+1/2 term G dX is carried to the next
+  //    row as its o-1/2 term
   const int o = f - 3;
-  if (o >= m0 && o < m1 && owave) {
-    N3 out;
-    if (bwall) {
-      out = st.x[c3];
-    } else if (AX == 2 && o == 0) {
-      double rho = st.x[c3].r - lm * (st.xp[c2].m[2] - 0.0);
-      out = N3{rho, {0.0, 0.0, 0.0}, rho * (c.cv * c.Tb + c.g * zr[0])};
-    } else if (AX == 2 && o == M) {
-      double rho = st.xp[c3].r;
-      out = N3{rho, {0.0, 0.0, 0.0}, rho * (c.cv * c.Tt + c.g * zr[M])};
-    } else {
-      const N3& fp1 = st.FP[e2];
-      const N3& fp0 = st.FP[e3];
+  const bool rin_O = (AX == 2) ? (o >= 0 && o <= M - 1) : true;
+  if (o >= m0 - 1 && o < m1 && rin_O && owave && !bwall) {
+    N3 d0 = sub3(st.x[c2], st.x[c3]);
+    const double G = st.G[e1];
+    N3 Dc{G * d0.r, {G * d0.m[0], G * d0.m[1], G * d0.m[2]}, G * d0.E};
+    if (o >= m0 && (AX == 1 || o >= 1)) {
+      const N3& fp1 = st.FP[e0];
+      const N3& fp0 = st.FP[e1];
       const N3& x0 = st.x[c3];
       const N3& xp = st.xp[c3];
+      const N3& Dm = st.Dp;
       N3 xc;
       xc.r = x0.r - lm * (fp1.r - fp0.r);
 #pragma unroll
       for (int g = 0; g < 3; ++g) xc.m[g] = x0.m[g] - lm * (fp1.m[g] - fp0.m[g]);
       xc.E = x0.E - lm * (fp1.E - fp0.E);
       if (AX == 2) xc.m[2] = xc.m[2] + tau * (-c.g * xp.r);
-      const N3& d0 = st.dl[c3];
-      const N3& dm = st.dl[c4];
-      const double G0 = st.G[c3], Gm = st.G[c4];
-      out.r = 0.5 * (xp.r + xc.r) + (G0 * d0.r - Gm * dm.r);
+      N3 out;
+      out.r = 0.5 * (xp.r + xc.r) + (Dc.r - Dm.r);
 #pragma unroll
-      for (int g = 0; g < 3; ++g) out.m[g] = 0.5 * (xp.m[g] + xc.m[g]) + (G0 * d0.m[g] - Gm * dm.m[g]);
-      out.E = 0.5 * (xp.E + xc.E) + (G0 * d0.E - Gm * dm.E);
+      for (int g = 0; g < 3; ++g) out.m[g] = 0.5 * (xp.m[g] + xc.m[g]) + (Dc.m[g] - Dm.m[g]);
+      out.E = 0.5 * (xp.E + xc.E) + (Dc.E - Dm.E);
+      if (FUSE) acc_out(c, out, zof(o), st.acc, L.out);
+      if (L.out) store3(c, Y, node(o), out);
+    }
+    st.Dp = Dc;
+  }
+  if (o >= m0 && o < m1 && owave && (bwall || (AX == 2 && (o == 0 || o == M)))) {
+    N3 out;
+    if (bwall) {
+      out = st.x[c3];
+    } else if (o == 0) {
+      double rho = st.x[c3].r - lm * (st.xp[c2].m[2] - 0.0);
+      out = N3{rho, {0.0, 0.0, 0.0}, rho * (c.cv * c.Tb + c.g * zr[0])};
+    } else {
+      double rho = st.xp[c3].r;
+      out = N3{rho, {0.0, 0.0, 0.0}, rho * (c.cv * c.Tt + c.g * zr[M])};
     }
     if (FUSE) acc_out(c, out, zof(o), st.acc, L.out);
     if (L.out) store3(c, Y, node(o), out);
@@ -371,7 +387,8 @@ __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const
   __shared__ double xa[2][kNW][64];
   __shared__ double xb[2][kNW][64];
   constexpr int B = (AX == 2) ? 1 : 2;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const double dt = step_dt(c, sh, slot);
   head3(sh, slot, first, dt);
   int bid = blockIdx.x;
@@ -402,8 +419,24 @@ __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const
   MF st;
   st.acc.s[0] = st.acc.s[1] = st.acc.s[2] = 0.0;
   st.acc.bad = false;
+  st.Dp = N3{0.0, {0.0, 0.0, 0.0}, 0.0};
   const int fs = (AX == 2) ? max(0, m0 - 2) : m0 - 2;
   const int fe = m1 + 2;
+  if (bval) {
+    auto node0 = [&](int row) -> long long {
+      if (AX == 2) return ((long long)row * c.ny + bidx) * c.nx + L.col;
+      return ((long long)bidx * c.ny + wrap(row, c.ny)) * c.nx + L.col;
+    };
+    N3 a = load3(c, X, node0(fs));
+    N3 b = (AX == 1 || fs + 1 <= c.M) ? load3(c, X, node0(fs + 1)) : a;
+    if (fs & 1) {
+      st.pf[1] = a;
+      st.pf[0] = b;
+    } else {
+      st.pf[0] = a;
+      st.pf[1] = b;
+    }
+  }
   for (int fb = fs & ~3; fb <= fe; fb += 4) {
     mf_iter<AX, 0, FUSE>(c, st, fb + 0, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm);
     mf_iter<AX, 1, FUSE>(c, st, fb + 1, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm);
@@ -417,6 +450,7 @@ __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const
 // L_x: flux across lanes, march z, waves along y.
 
 struct LF {
+  N3 pf[2];                // prefetched rows f+1, f+2
   N3 x[4];
   P3 pn[4];
   double s[4];             // |u_x| + c of X^n
@@ -442,8 +476,10 @@ __device__ __forceinline__ void lf_iter(const Coef& c, LF& st, int f, int fs, in
   const double ihy2 = 0.5 * c.ihy;
   auto node = [&](int k) -> long long { return ((long long)k * c.ny + j) * c.nx + L.col; };
 
+  constexpr int e0 = S & 1;
   if (f <= M) {
-    st.x[c0] = load3(c, X, node(f));
+    st.x[c0] = st.pf[e0];
+    if (f + 2 <= M) st.pf[e0] = load3(c, X, node(f + 2));
     st.pn[c0] = prim3(c, st.x[c0], zr[f]);
     st.s[c0] = fabs(st.pn[c0].u[0]) + sound(c, st.pn[c0].T);
     exchange(xa, w, lane, st.pn[c0].u[0], st.pn[c0].u[1], ihy2, st.yx[c0], st.yy[c0]);
@@ -456,7 +492,8 @@ __device__ __forceinline__ void lf_iter(const Coef& c, LF& st, int f, int fs, in
         st.xp[c1] = st.x[c1];
         st.pp[c1] = st.pn[c1];
       } else {
-        const P3& q = st.pn[c1];
+        P3 q = st.pn[c1];
+        q.p = c.a * st.x[c1].r * q.T;
         double du[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
 #pragma unroll
         for (int g = 0; g < 3; ++g) du[g][0] = (shd(q.u[g]) - q.u[g]) * c.ihx;
@@ -534,7 +571,8 @@ __global__ __launch_bounds__(64 * kNW) void sweep_lf3d(Coef c, Shared* sh, const
                                                        int nstrips, int nbb) {
   __shared__ double xa[2][kNW][64];
   __shared__ double xb[2][kNW][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const double dt = step_dt(c, sh, slot);
   head3(sh, slot, first, dt);
   int bid = blockIdx.x;
@@ -554,6 +592,18 @@ __global__ __launch_bounds__(64 * kNW) void sweep_lf3d(Coef c, Shared* sh, const
   st.acc.bad = false;
   const int fs = max(0, k0 - 2);
   const int fe = k1 + 1;
+  {
+    auto node0 = [&](int k) -> long long { return ((long long)k * c.ny + j) * c.nx + L.col; };
+    N3 a = load3(c, X, node0(fs));
+    N3 b = (fs + 1 <= c.M) ? load3(c, X, node0(fs + 1)) : a;
+    if (fs & 1) {
+      st.pf[1] = a;
+      st.pf[0] = b;
+    } else {
+      st.pf[0] = a;
+      st.pf[1] = b;
+    }
+  }
   for (int fb = fs & ~3; fb <= fe; fb += 4) {
     lf_iter<0, FUSE>(c, st, fb + 0, fs, fe, k0, k1, w, lane, L, j, owave, xa, xb, zr, X, Y, lx);
     lf_iter<1, FUSE>(c, st, fb + 1, fs, fe, k0, k1, w, lane, L, j, owave, xa, xb, zr, X, Y, lx);

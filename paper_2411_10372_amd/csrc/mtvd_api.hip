@@ -759,3 +759,835 @@ const char* mtvd_strerror(int status) {
 const char* mtvd_last_error(const mtvd_ctx* c) { return c ? c->err.c_str() : ""; }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batches of independent 2D boxes
+
+struct mtvd_batch {
+  int nbox;
+  std::vector<mtvd_params> p;
+  std::vector<Coef> c;
+  std::vector<long long> off;     // state offset of each box (doubles)
+  std::vector<int> zoff;          // plate-table offset of each box
+  std::vector<int> kcx, kcz;      // rows per wave (0 = default)
+  hipStream_t stream;
+  hipStream_t cap;                // private stream for graph capture
+  int device;
+  double* buf[2];
+  unsigned char* ws;
+  int cur, slot;
+  std::vector<int64_t> step;
+  bool bound, have_state, items_dirty;
+  size_t state_doubles;
+  size_t o_sh, o_desc, o_items, o_z, o_part, o_out, total;
+  int items_cap;                  // capacity of each item list
+  int nitems_x, nitems_z;
+  int diag_nb_max;
+  hipGraphExec_t g2[2];
+  bool have_g2[2];
+  std::string err;
+};
+
+namespace {
+
+int berr(mtvd_batch* b, int code, const std::string& what) {
+  if (b) b->err = what;
+  return code;
+}
+
+#define BHIP(b, expr)                                                        \
+  do {                                                                       \
+    hipError_t e_ = (expr);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      return berr(b, MTVD_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int batch_rows(const Coef& c, int kc) {
+  if (kc > 0) return kc;
+  // a single box of a batch fills part of the chip: a quarter of nz, 4..32
+  int r = c.nz / 4;
+  if (r < 4) r = 4;
+  if (r > 32) r = 32;
+  return r;
+}
+
+// item capacity: every box at the smallest tiling (4 rows per wave)
+int item_capacity(const std::vector<Coef>& cs) {
+  long long n = 0;
+  for (const auto& c : cs) n += (long long)strips_2d(c.nx) * ((c.nz + 3) / 4);
+  return (int)n;
+}
+
+struct BatchLayout {
+  size_t o_sh, o_desc, o_items, o_z, o_part, o_out, total, state_doubles;
+  std::vector<long long> off;
+  std::vector<int> zoff;
+  int items_cap, diag_nb_max;
+};
+
+BatchLayout batch_layout(const mtvd_params* ps, int nbox, const std::vector<Coef>& cs) {
+  BatchLayout L;
+  size_t so = 0;
+  int zo = 0;
+  int nbmax = 1;
+  int nzmax = 1;
+  for (int b = 0; b < nbox; ++b) {
+    L.off.push_back((long long)so);
+    L.zoff.push_back(zo);
+    so += (size_t)cs[b].nf * (size_t)cs[b].cnt;
+    so = (so + 31) / 32 * 32;                 // 256-byte boundary per box
+    zo += cs[b].nz;
+    Layout l1 = layout_of(&ps[b]);
+    if (l1.diag_nb > nbmax) nbmax = l1.diag_nb;
+    if (cs[b].nz > nzmax) nzmax = cs[b].nz;
+  }
+  L.state_doubles = so;
+  L.items_cap = item_capacity(cs);
+  L.diag_nb_max = nbmax;
+  size_t off = 0;
+  L.o_sh = off;
+  off = align_up(off + sizeof(Shared) * (size_t)nbox);
+  L.o_desc = off;
+  off = align_up(off + sizeof(BoxDesc) * (size_t)nbox);
+  L.o_items = off;
+  off = align_up(off + sizeof(int4) * 2 * (size_t)L.items_cap);
+  L.o_z = off;
+  off = align_up(off + sizeof(double) * (size_t)zo);
+  L.o_part = off;
+  off = align_up(off + sizeof(double) * (size_t)nzmax * nbmax * kDiagVals);
+  L.o_out = off;
+  off = align_up(off + sizeof(double) * kDiagOut);
+  L.total = off;
+  return L;
+}
+
+Shared* bsh(mtvd_batch* b) { return (Shared*)(b->ws + b->o_sh); }
+double* bz(mtvd_batch* b) { return (double*)(b->ws + b->o_z); }
+
+// descriptor table and the two work lists (largest boxes first)
+int upload_items(mtvd_batch* b) {
+  std::vector<BoxDesc> d(b->nbox);
+  std::vector<int> order(b->nbox);
+  for (int i = 0; i < b->nbox; ++i) {
+    order[i] = i;
+    memset(&d[i], 0, sizeof(BoxDesc));
+    d[i].c = b->c[i];
+    d[i].off = b->off[i];
+    d[i].zoff = b->zoff[i];
+    d[i].kc_x = batch_rows(b->c[i], b->kcx[i]);
+    d[i].kc_z = batch_rows(b->c[i], b->kcz[i]);
+    d[i].nstrips = strips_2d(b->c[i].nx);
+  }
+  for (int i = 1; i < b->nbox; ++i)
+    for (int j = i; j > 0 && b->c[order[j]].cnt > b->c[order[j - 1]].cnt; --j)
+      std::swap(order[j], order[j - 1]);
+  std::vector<int4> items[2];
+  for (int a = 0; a < 2; ++a) {
+    for (int ib : order) {
+      int kc = a == 0 ? d[ib].kc_x : d[ib].kc_z;
+      int nch = (b->c[ib].nz + kc - 1) / kc;
+      for (int ch = 0; ch < nch; ++ch)
+        for (int st = 0; st < d[ib].nstrips; ++st)
+          items[a].push_back(make_int4(ib, st, ch, (st == 0 && ch == 0) ? 1 : 0));
+    }
+    if ((int)items[a].size() > b->items_cap)
+      return berr(b, MTVD_EINVAL, "work list larger than its capacity");
+  }
+  b->nitems_x = (int)items[0].size();
+  b->nitems_z = (int)items[1].size();
+  int4* dev = (int4*)(b->ws + b->o_items);
+  BHIP(b, hipMemcpyAsync(b->ws + b->o_desc, d.data(), sizeof(BoxDesc) * b->nbox,
+                         hipMemcpyHostToDevice, b->stream));
+  BHIP(b, hipMemcpyAsync(dev, items[0].data(), sizeof(int4) * b->nitems_x,
+                         hipMemcpyHostToDevice, b->stream));
+  BHIP(b, hipMemcpyAsync(dev + b->items_cap, items[1].data(), sizeof(int4) * b->nitems_z,
+                         hipMemcpyHostToDevice, b->stream));
+  BHIP(b, hipStreamSynchronize(b->stream));
+  for (int a = 0; a < 2; ++a)
+    if (b->have_g2[a]) {
+      (void)hipGraphExecDestroy(b->g2[a]);
+      b->have_g2[a] = false;
+    }
+  b->items_dirty = false;
+  return MTVD_OK;
+}
+
+// one step of every box on stream s, with the given max slot
+hipError_t batch_step_on(mtvd_batch* b, hipStream_t s, int slot) {
+  static const int o2[2][4] = {{2, 0, 2, 0}, {2, 0, 0, 2}};
+  const int* order = o2[b->p[0].sweep_order];
+  const bool track = b->p[0].dt_mode == 0;
+  const BoxDesc* desc = (const BoxDesc*)(b->ws + b->o_desc);
+  const int4* items = (const int4*)(b->ws + b->o_items);
+  int cur = b->cur;
+  for (int o = 0; o < 4; ++o) {
+    int ax = order[o];
+    const int4* it = ax == 0 ? items : items + b->items_cap;
+    int n = ax == 0 ? b->nitems_x : b->nitems_z;
+    hipError_t e = launch_batch_2d(ax, desc, it, n, bsh(b), bz(b), slot, o == 0 ? 1 : 0,
+                                   track && o == 3, b->buf[cur], b->buf[cur ^ 1], s);
+    if (e != hipSuccess) return e;
+    cur ^= 1;
+  }
+  return hipSuccess;
+}
+
+int batch_refresh_dt(mtvd_batch* b, int box) {
+  Shared* sh = bsh(b) + box;
+  const Coef& c = b->c[box];
+  clear_slot_kernel<<<1, 64, 0, b->stream>>>(sh, b->slot);
+  BHIP(b, hipGetLastError());
+  long long blocks = (c.cnt + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  dt_kernel<<<(int)blocks, 256, 0, b->stream>>>(c, sh, bz(b) + b->zoff[box], b->slot,
+                                                b->buf[b->cur] + b->off[box]);
+  BHIP(b, hipGetLastError());
+  if (b->p[box].dt_mode == 1) {
+    freeze_dt_kernel<<<1, 64, 0, b->stream>>>(c, sh, b->slot);
+    BHIP(b, hipGetLastError());
+  }
+  return MTVD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mtvd_batch_bytes(const mtvd_params* boxes, int32_t nbox, size_t* state_bytes,
+                     size_t* workspace_bytes) {
+  if (!boxes || nbox < 1) return MTVD_EINVAL;
+  std::vector<Coef> cs;
+  for (int i = 0; i < nbox; ++i) {
+    std::string why;
+    int rc = validate(&boxes[i], &why);
+    if (rc != MTVD_OK && rc != MTVD_ESTABILITY) return rc;
+    cs.push_back(make_coef(&boxes[i]));
+  }
+  BatchLayout L = batch_layout(boxes, nbox, cs);
+  if (state_bytes) *state_bytes = L.state_doubles * sizeof(double);
+  if (workspace_bytes) *workspace_bytes = L.total;
+  return MTVD_OK;
+}
+
+int mtvd_batch_create(const mtvd_params* boxes, int32_t nbox, void* hip_stream,
+                      mtvd_batch** out) {
+  if (!out || !boxes || nbox < 1) return MTVD_EINVAL;
+  *out = nullptr;
+  for (int i = 0; i < nbox; ++i) {
+    std::string why;
+    int rc = validate(&boxes[i], &why);
+    if (rc != MTVD_OK) {
+      fprintf(stderr, "mtvd_batch_create: box %d: %s\n", i, why.c_str());
+      return rc;
+    }
+    if (boxes[i].ndim != 2) return MTVD_EINVAL;
+    if (boxes[i].dt_mode != boxes[0].dt_mode || boxes[i].sweep_order != boxes[0].sweep_order)
+      return MTVD_EINVAL;
+  }
+  mtvd_batch* b = new (std::nothrow) mtvd_batch();
+  if (!b) return MTVD_EINVAL;
+  b->nbox = nbox;
+  for (int i = 0; i < nbox; ++i) {
+    b->p.push_back(boxes[i]);
+    b->c.push_back(make_coef(&boxes[i]));
+  }
+  BatchLayout L = batch_layout(boxes, nbox, b->c);
+  b->off = L.off;
+  b->zoff = L.zoff;
+  b->kcx.assign(nbox, 0);
+  b->kcz.assign(nbox, 0);
+  b->o_sh = L.o_sh;
+  b->o_desc = L.o_desc;
+  b->o_items = L.o_items;
+  b->o_z = L.o_z;
+  b->o_part = L.o_part;
+  b->o_out = L.o_out;
+  b->total = L.total;
+  b->items_cap = L.items_cap;
+  b->diag_nb_max = L.diag_nb_max;
+  b->state_doubles = L.state_doubles;
+  b->stream = (hipStream_t)hip_stream;
+  b->buf[0] = b->buf[1] = nullptr;
+  b->ws = nullptr;
+  b->cur = b->slot = 0;
+  b->step.assign(nbox, 0);
+  b->bound = b->have_state = false;
+  b->items_dirty = true;
+  b->nitems_x = b->nitems_z = 0;
+  b->have_g2[0] = b->have_g2[1] = false;
+  if (hipGetDevice(&b->device) != hipSuccess ||
+      hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+    delete b;
+    return MTVD_EHIP;
+  }
+  *out = b;
+  return MTVD_OK;
+}
+
+int mtvd_batch_bind(mtvd_batch* b, double* buf_a, double* buf_b, void* workspace) {
+  if (!b) return MTVD_EINVAL;
+  if (!buf_a || !buf_b || !workspace || buf_a == buf_b)
+    return berr(b, MTVD_ESIZE, "null or repeated buffer");
+  if (((uintptr_t)buf_a | (uintptr_t)buf_b | (uintptr_t)workspace) % kAlign)
+    return berr(b, MTVD_ESIZE, "buffers must be 256-byte aligned");
+  b->buf[0] = buf_a;
+  b->buf[1] = buf_b;
+  b->ws = (unsigned char*)workspace;
+  b->cur = b->slot = 0;
+  b->bound = true;
+  b->have_state = false;
+  BHIP(b, hipMemsetAsync(b->ws, 0, b->o_items, b->stream));
+  for (int i = 0; i < b->nbox; ++i) {
+    zrow_kernel<<<(b->c[i].nz + 255) / 256, 256, 0, b->stream>>>(b->c[i].nz, bz(b) + b->zoff[i]);
+    BHIP(b, hipGetLastError());
+  }
+  return upload_items(b);
+}
+
+int mtvd_batch_offset(const mtvd_batch* b, int32_t box, size_t* offset) {
+  if (!b || !offset || box < 0 || box >= b->nbox) return MTVD_EINVAL;
+  *offset = (size_t)b->off[box];
+  return MTVD_OK;
+}
+
+int mtvd_batch_init_state(mtvd_batch* b) {
+  if (!b) return MTVD_EINVAL;
+  if (!b->bound) return berr(b, MTVD_ESTATE, "mtvd_batch_bind first");
+  b->cur = b->slot = 0;
+  for (int i = 0; i < b->nbox; ++i) {
+    const Coef& c = b->c[i];
+    init_kernel<<<(unsigned)((c.cnt + 255) / 256), 256, 0, b->stream>>>(
+        c, bz(b) + b->zoff[i], b->buf[0] + b->off[i]);
+    BHIP(b, hipGetLastError());
+    set_scalars_kernel<<<1, 64, 0, b->stream>>>(bsh(b) + i, 0.0, 1);
+    BHIP(b, hipGetLastError());
+    int rc = batch_refresh_dt(b, i);
+    if (rc) return rc;
+    b->step[i] = 0;
+  }
+  b->have_state = true;
+  return MTVD_OK;
+}
+
+int mtvd_batch_step(mtvd_batch* b, int32_t nsteps) {
+  if (!b) return MTVD_EINVAL;
+  if (nsteps < 0) return berr(b, MTVD_EINVAL, "nsteps < 0");
+  if (!b->have_state) return berr(b, MTVD_ESTATE, "no state");
+  if (b->items_dirty) {
+    int rc = upload_items(b);
+    if (rc) return rc;
+  }
+  const bool track = b->p[0].dt_mode == 0;
+  int left = nsteps;
+  while (left >= 2) {
+    int s0 = b->slot;
+    if (!b->have_g2[s0]) {
+      hipGraph_t g;
+      BHIP(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+      hipError_t e1 = batch_step_on(b, b->cap, s0);
+      hipError_t e2 = batch_step_on(b, b->cap, track ? (s0 ^ 1) : s0);
+      hipError_t e3 = hipStreamEndCapture(b->cap, &g);
+      if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
+        return berr(b, MTVD_EHIP, "graph capture failed");
+      hipError_t e4 = hipGraphInstantiate(&b->g2[s0], g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e4 != hipSuccess) return berr(b, MTVD_EHIP, "graph instantiate failed");
+      b->have_g2[s0] = true;
+    }
+    BHIP(b, hipGraphLaunch(b->g2[s0], b->stream));
+    left -= 2;
+    for (auto& s : b->step) s += 2;
+  }
+  if (left == 1) {
+    BHIP(b, batch_step_on(b, b->stream, b->slot));
+    if (track) b->slot ^= 1;
+    for (auto& s : b->step) s += 1;
+  }
+  return MTVD_OK;
+}
+
+int mtvd_batch_diagnostics(mtvd_batch* b, int32_t box, mtvd_diag* out) {
+  if (!b || !out || box < 0 || box >= b->nbox) return MTVD_EINVAL;
+  if (!b->have_state) return berr(b, MTVD_ESTATE, "no state");
+  const Coef& c = b->c[box];
+  Layout l1 = layout_of(&b->p[box]);
+  double* part = (double*)(b->ws + b->o_part);
+  double* dout = (double*)(b->ws + b->o_out);
+  Shared* sh = bsh(b) + box;
+  dim3 grid(l1.diag_nb, c.nz);
+  diag_rows_kernel<<<grid, kDiagBlock, 0, b->stream>>>(c, bz(b) + b->zoff[box],
+                                                       b->buf[b->cur] + b->off[box], part,
+                                                       l1.diag_nb, sh);
+  BHIP(b, hipGetLastError());
+  diag_final_kernel<<<1, kDiagBlock, 0, b->stream>>>(c, part, l1.diag_nb, dout);
+  BHIP(b, hipGetLastError());
+  double host[kDiagOut];
+  Shared hs;
+  BHIP(b, hipMemcpyAsync(host, dout, sizeof(double) * 15, hipMemcpyDeviceToHost, b->stream));
+  BHIP(b, hipMemcpyAsync(&hs, sh, sizeof(Shared), hipMemcpyDeviceToHost, b->stream));
+  BHIP(b, hipStreamSynchronize(b->stream));
+  memset(out, 0, sizeof(*out));
+  out->step = b->step[box];
+  out->time = hs.time;
+  if (b->p[box].dt_mode == 1) {
+    out->dt = hs.dt_frozen;
+  } else {
+    double S[3];
+    for (int a = 0; a < 3; ++a) memcpy(&S[a], &hs.smax[b->slot][a], sizeof(double));
+    out->dt = c.cfl * fmin(c.hx / S[0], c.hz / S[2]);
+  }
+  out->mass = host[0];
+  out->kinetic = host[1];
+  out->total_energy = host[2];
+  out->nu_bottom = host[3];
+  out->nu_top = host[4];
+  out->nu_mean = host[5];
+  out->nu_bulk = host[6];
+  out->nu_conv = host[7];
+  out->nu_kin = host[8];
+  for (int i = 0; i < 6; ++i) out->tmean[i] = host[9 + i];
+  out->flags = (int32_t)hs.flags;
+  return hs.flags ? MTVD_ENONFINITE : MTVD_OK;
+}
+
+int mtvd_batch_get_state(mtvd_batch* b, int32_t box, double* host, size_t count) {
+  if (!b || !host || box < 0 || box >= b->nbox) return MTVD_EINVAL;
+  if (!b->have_state) return berr(b, MTVD_ESTATE, "no state");
+  const Coef& c = b->c[box];
+  if (count != (size_t)c.cnt * c.nf) return berr(b, MTVD_ESIZE, "count mismatch");
+  BHIP(b, hipMemcpyAsync(host, b->buf[b->cur] + b->off[box], sizeof(double) * count,
+                         hipMemcpyDeviceToHost, b->stream));
+  unsigned int flags = 0;
+  BHIP(b, hipMemcpyAsync(&flags, &(bsh(b) + box)->flags, sizeof(unsigned int),
+                         hipMemcpyDeviceToHost, b->stream));
+  BHIP(b, hipStreamSynchronize(b->stream));
+  return flags ? MTVD_ENONFINITE : MTVD_OK;
+}
+
+int mtvd_batch_set_state(mtvd_batch* b, int32_t box, const double* host, size_t count,
+                         double time, int64_t step) {
+  if (!b || !host || box < 0 || box >= b->nbox) return MTVD_EINVAL;
+  if (!b->bound) return berr(b, MTVD_ESTATE, "mtvd_batch_bind first");
+  if (!b->have_state) return berr(b, MTVD_ESTATE, "mtvd_batch_init_state first");
+  const Coef& c = b->c[box];
+  if (count != (size_t)c.cnt * c.nf) return berr(b, MTVD_ESIZE, "count mismatch");
+  BHIP(b, hipMemcpyAsync(b->buf[b->cur] + b->off[box], host, sizeof(double) * count,
+                         hipMemcpyHostToDevice, b->stream));
+  set_scalars_kernel<<<1, 64, 0, b->stream>>>(bsh(b) + box, time, 1);
+  BHIP(b, hipGetLastError());
+  int rc = batch_refresh_dt(b, box);
+  if (rc) return rc;
+  BHIP(b, hipStreamSynchronize(b->stream));
+  b->step[box] = step;
+  return MTVD_OK;
+}
+
+int mtvd_batch_current(const mtvd_batch* b, int32_t* which) {
+  if (!b || !which) return MTVD_EINVAL;
+  *which = b->cur;
+  return MTVD_OK;
+}
+
+int mtvd_batch_set_tiling(mtvd_batch* b, int32_t box, int32_t rows_x, int32_t rows_z) {
+  if (!b || box < 0 || box >= b->nbox || rows_x < 0 || rows_z < 0) return MTVD_EINVAL;
+  b->kcx[box] = rows_x;
+  b->kcz[box] = rows_z;
+  b->items_dirty = true;
+  return MTVD_OK;
+}
+
+int mtvd_batch_get_tiling(const mtvd_batch* b, int32_t box, int32_t* rows_x,
+                          int32_t* rows_z) {
+  if (!b || box < 0 || box >= b->nbox || !rows_x || !rows_z) return MTVD_EINVAL;
+  *rows_x = batch_rows(b->c[box], b->kcx[box]);
+  *rows_z = batch_rows(b->c[box], b->kcz[box]);
+  return MTVD_OK;
+}
+
+int mtvd_batch_autotune(mtvd_batch* b, void* scratch, int32_t trial_steps) {
+  if (!b || !scratch || trial_steps < 1) return MTVD_EINVAL;
+  if (!b->have_state) return berr(b, MTVD_ESTATE, "no state");
+  if ((uintptr_t)scratch % kAlign) return berr(b, MTVD_ESIZE, "scratch must be 256-byte aligned");
+  const size_t sbytes = b->state_doubles * sizeof(double);
+  const size_t shbytes = sizeof(Shared) * (size_t)b->nbox;
+  unsigned char* sc = (unsigned char*)scratch;
+  // save the state (current buffer), the per-box scalars and the slot
+  BHIP(b, hipMemcpyAsync(sc, b->buf[b->cur], sbytes, hipMemcpyDeviceToDevice, b->stream));
+  BHIP(b, hipMemcpyAsync(sc + sbytes, bsh(b), shbytes, hipMemcpyDeviceToDevice, b->stream));
+  const int cur0 = b->cur, slot0 = b->slot;
+  std::vector<int64_t> step0 = b->step;
+  hipEvent_t e0, e1;
+  BHIP(b, hipEventCreate(&e0));
+  BHIP(b, hipEventCreate(&e1));
+  auto restore = [&]() -> int {
+    b->cur = cur0;
+    b->slot = slot0;
+    b->step = step0;
+    BHIP(b, hipMemcpyAsync(b->buf[b->cur], sc, sbytes, hipMemcpyDeviceToDevice, b->stream));
+    BHIP(b, hipMemcpyAsync(bsh(b), sc + sbytes, shbytes, hipMemcpyDeviceToDevice, b->stream));
+    return MTVD_OK;
+  };
+  auto trial = [&](float* ms) -> int {
+    int rc = restore();
+    if (rc) return rc;
+    rc = upload_items(b);
+    if (rc) return rc;
+    float best = 1e30f;
+    for (int rep = 0; rep < 2; ++rep) {
+      BHIP(b, hipEventRecord(e0, b->stream));
+      for (int s = 0; s < trial_steps; ++s) {
+        BHIP(b, batch_step_on(b, b->stream, b->slot));
+        if (b->p[0].dt_mode == 0) b->slot ^= 1;
+      }
+      BHIP(b, hipEventRecord(e1, b->stream));
+      BHIP(b, hipEventSynchronize(e1));
+      float t = 0.0f;
+      BHIP(b, hipEventElapsedTime(&t, e0, e1));
+      if (t < best) best = t;
+    }
+    *ms = best;
+    return MTVD_OK;
+  };
+  static const int cand[5] = {4, 8, 16, 32, 64};
+  std::vector<int> done(b->nbox, 0);
+  for (int i = 0; i < b->nbox; ++i) {
+    if (done[i]) continue;
+    std::vector<int> same;
+    for (int j = 0; j < b->nbox; ++j)
+      if (b->c[j].nx == b->c[i].nx && b->c[j].nz == b->c[i].nz) same.push_back(j);
+    for (int axis = 0; axis < 2; ++axis) {   // 0: rows of L_z, 1: rows of L_x
+      int bestk = 0;
+      float bestt = 1e30f;
+      for (int k : cand) {
+        if (k > b->c[i].nz) continue;
+        for (int j : same) (axis == 0 ? b->kcz[j] : b->kcx[j]) = k;
+        float t;
+        int rc = trial(&t);
+        if (rc) return rc;
+        if (t < bestt) {
+          bestt = t;
+          bestk = k;
+        }
+      }
+      for (int j : same) (axis == 0 ? b->kcz[j] : b->kcx[j]) = bestk;
+    }
+    for (int j : same) done[j] = 1;
+  }
+  int rc = restore();
+  if (rc) return rc;
+  rc = upload_items(b);
+  if (rc) return rc;
+  BHIP(b, hipStreamSynchronize(b->stream));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return MTVD_OK;
+}
+
+int mtvd_batch_destroy(mtvd_batch* b) {
+  if (!b) return MTVD_OK;
+  for (int a = 0; a < 2; ++a)
+    if (b->have_g2[a]) (void)hipGraphExecDestroy(b->g2[a]);
+  (void)hipStreamDestroy(b->cap);
+  delete b;
+  return MTVD_OK;
+}
+
+const char* mtvd_batch_last_error(const mtvd_batch* b) { return b ? b->err.c_str() : ""; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// adjoint of the time-averaged mean Nusselt number (2D, frozen dt)
+//
+// J = (1/N) sum_{n=1..N} Nu_mean(X_n), X_n = S^n(X_0), X_0 = X_0(theta),
+// S one step with a fixed dt.  The forward pass keeps X at steps 0, E, 2E, ...
+// (E = checkpoint interval); the backward pass recomputes one interval at a
+// time with the forward kernels, keeping every operator's input, and runs
+// the operators' reverses from the last step to the first.
+
+struct mtvd_adj {
+  mtvd_params p;
+  Coef c;                 // dt_mode = 1
+  adj::AC ac;
+  int nsteps, every, nseg, kc;
+  hipStream_t stream;
+  unsigned char* ws;
+  double *zr, *acc, *ckpt, *segs, *tmp[2], *cot[2];
+  Shared* sh;
+  adj::Arr A;
+  size_t total;
+  bool bound, have_fwd;
+  std::string err;
+};
+
+namespace {
+
+int aerr(mtvd_adj* a, int code, const std::string& what) {
+  if (a) a->err = what;
+  return code;
+}
+
+#define AHIP(a, expr)                                                          \
+  do {                                                                         \
+    hipError_t e_ = (expr);                                                    \
+    if (e_ != hipSuccess)                                                      \
+      return aerr(a, MTVD_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// byte offsets of the adjoint workspace (or, with base set, its pointers)
+size_t adj_layout(mtvd_adj* a, unsigned char* base) {
+  const long long cnt = a->c.cnt;
+  const size_t S = sizeof(double) * 4 * (size_t)cnt, one = sizeof(double) * (size_t)cnt;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> unsigned char* {
+    unsigned char* p = base ? base + off : nullptr;
+    off = align_up(off + bytes);
+    return p;
+  };
+  a->sh = (Shared*)take(sizeof(Shared));
+  a->zr = (double*)take(sizeof(double) * a->c.nz);
+  a->acc = (double*)take(sizeof(double) * 8);
+  a->ckpt = (double*)take(S * a->nseg);
+  a->segs = (double*)take(S * 4 * (size_t)a->every);
+  for (int q = 0; q < 2; ++q) a->tmp[q] = (double*)take(S);
+  for (int q = 0; q < 2; ++q) a->cot[q] = (double*)take(S);
+  adj::Arr& A = a->A;
+  A.P = (double*)take(S);
+  A.F = (double*)take(S);
+  A.XP = (double*)take(S);
+  A.PP = (double*)take(S);
+  A.XCb = (double*)take(S);
+  A.XPb = (double*)take(S);
+  A.PPb = (double*)take(S);
+  A.PB = (double*)take(S);
+  A.FAm = (double*)take(S);
+  A.FA0 = (double*)take(S);
+  A.FAp = (double*)take(S);
+  A.DPb = (double*)take(5 * one);
+  A.DB = (double*)take(5 * one);
+  A.S = (double*)take(one);
+  A.SB0 = (double*)take(one);
+  A.SB1 = (double*)take(one);
+  A.SB = (double*)take(one);
+  A.MU = (double*)take(one);
+  A.KB = (double*)take(one);
+  A.RPb = (double*)take(sizeof(double) * a->c.nx);
+  A.zr = a->zr;
+  return off;
+}
+
+int adj_check(const mtvd_params* p, int32_t nsteps, int32_t every, std::string* why) {
+  int rc = validate(p, why);
+  if (rc != MTVD_OK) return rc;
+  if (p->ndim != 2) { *why = "the adjoint is 2D only"; return MTVD_EINVAL; }
+  if (p->limiter_form != 0) { *why = "the adjoint reverses the printed limiter form (limiter_form 0) only"; return MTVD_EINVAL; }
+  if (nsteps < 1) { *why = "nsteps must be >= 1"; return MTVD_EINVAL; }
+  if (every < 1) { *why = "checkpoint interval must be >= 1"; return MTVD_EINVAL; }
+  return MTVD_OK;
+}
+
+void adj_shape(mtvd_adj* a, const mtvd_params* p, int32_t nsteps, int32_t every) {
+  a->p = *p;
+  a->p.dt_mode = 1;
+  a->c = make_coef(&a->p);
+  a->nsteps = nsteps;
+  a->every = every > nsteps ? nsteps : every;
+  a->nseg = (nsteps + a->every - 1) / a->every;
+  long long kc = (long long)strips_2d(a->c.nx) * a->c.nz / 4096;
+  a->kc = (int)(kc < 4 ? 4 : (kc > 64 ? 64 : kc));
+  adj::AC& ac = a->ac;
+  memset(&ac, 0, sizeof(ac));
+  const Coef& c = a->c;
+  ac.nx = c.nx;
+  ac.nz = c.nz;
+  ac.M = c.M;
+  ac.cnt = c.cnt;
+  ac.ihx = c.ihx;
+  ac.ihz = c.ihz;
+  ac.cv = c.cv;
+  ac.icv = c.icv;
+  ac.a = c.a;
+  ac.gam_a = c.gam_a;
+  ac.g = c.g;
+  ac.mu = c.mu;
+  ac.K = c.K;
+  ac.lam = c.lam;
+  ac.Tb = c.Tb;
+  ac.Tt = c.Tt;
+  ac.wall_order = c.wall_order;
+  ac.tvd_on = c.tvd_on;
+  ac.limiter_form = c.limiter_form;
+}
+
+const int kOrder2[2][4] = {{2, 0, 2, 0}, {2, 0, 0, 2}};
+
+hipError_t adj_fwd_step(mtvd_adj* a, const double* in, double* out) {
+  // the step's operators in order, through tmp[0], tmp[1], tmp[0]
+  const int* o = kOrder2[a->p.sweep_order];
+  const double* X[4] = {in, a->tmp[0], a->tmp[1], a->tmp[0]};
+  double* Y[4] = {a->tmp[0], a->tmp[1], a->tmp[0], out};
+  for (int s = 0; s < 4; ++s) {
+    hipError_t e = launch_sweep_2d(o[s], a->c, a->sh, a->zr, 0, 0, false, X[s], Y[s], a->kc,
+                                   a->stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mtvd_adj_bytes(const mtvd_params* p, int32_t nsteps, int32_t every, size_t* workspace_bytes) {
+  std::string why;
+  int rc = adj_check(p, nsteps, every, &why);
+  if (rc != MTVD_OK) return rc;
+  mtvd_adj a;
+  adj_shape(&a, p, nsteps, every);
+  if (workspace_bytes) *workspace_bytes = adj_layout(&a, nullptr);
+  return MTVD_OK;
+}
+
+int mtvd_adj_create(const mtvd_params* p, int32_t nsteps, int32_t every, void* hip_stream,
+                    mtvd_adj** out) {
+  if (!out) return MTVD_EINVAL;
+  *out = nullptr;
+  std::string why;
+  int rc = adj_check(p, nsteps, every, &why);
+  if (rc != MTVD_OK) {
+    fprintf(stderr, "mtvd_adj_create: %s\n", why.c_str());
+    return rc;
+  }
+  mtvd_adj* a = new (std::nothrow) mtvd_adj();
+  if (!a) return MTVD_EINVAL;
+  adj_shape(a, p, nsteps, every);
+  a->total = adj_layout(a, nullptr);
+  a->stream = (hipStream_t)hip_stream;
+  a->ws = nullptr;
+  a->bound = a->have_fwd = false;
+  *out = a;
+  return MTVD_OK;
+}
+
+int mtvd_adj_bind(mtvd_adj* a, void* workspace) {
+  if (!a) return MTVD_EINVAL;
+  if (!workspace) return aerr(a, MTVD_ESIZE, "null workspace");
+  if ((uintptr_t)workspace % kAlign) return aerr(a, MTVD_ESIZE, "workspace must be 256-byte aligned");
+  a->ws = (unsigned char*)workspace;
+  adj_layout(a, a->ws);
+  AHIP(a, launch_fill((double*)a->sh, sizeof(Shared) / sizeof(double), 0.0, a->stream));
+  zrow_kernel<<<(a->c.nz + 255) / 256, 256, 0, a->stream>>>(a->c.nz, a->zr);
+  AHIP(a, hipGetLastError());
+  a->bound = true;
+  a->have_fwd = false;
+  return MTVD_OK;
+}
+
+int mtvd_adj_forward(mtvd_adj* a, const double* theta, double dt, double* J, double* dt_used) {
+  if (!a) return MTVD_EINVAL;
+  if (!a->bound) return aerr(a, MTVD_ESTATE, "mtvd_adj_bind first");
+  if (!(dt >= 0.0) || !isfinite(dt)) return aerr(a, MTVD_EINVAL, "dt must be finite and >= 0");
+  a->have_fwd = false;
+  const size_t S = 4 * (size_t)a->c.cnt;
+  AHIP(a, launch_init_theta(a->c, a->zr, theta, a->ckpt, a->stream));
+  if (dt > 0.0) {
+    AHIP(a, launch_fill(&a->sh->dt_frozen, 1, dt, a->stream));
+  } else {
+    clear_slot_kernel<<<1, 64, 0, a->stream>>>(a->sh, 0);
+    AHIP(a, hipGetLastError());
+    long long blocks = (a->c.cnt + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    dt_kernel<<<(int)blocks, 256, 0, a->stream>>>(a->c, a->sh, a->zr, 0, a->ckpt);
+    AHIP(a, hipGetLastError());
+    freeze_dt_kernel<<<1, 64, 0, a->stream>>>(a->c, a->sh, 0);
+    AHIP(a, hipGetLastError());
+  }
+  AHIP(a, launch_fill(a->acc, 8, 0.0, a->stream));
+  const double w = 1.0 / (double)a->nsteps;
+  const double* in = a->ckpt;
+  for (int n = 0; n < a->nsteps; ++n) {
+    const int nn = n + 1;
+    double* out = (nn % a->every == 0 && nn / a->every < a->nseg) ? a->ckpt + S * (nn / a->every)
+                                                                   : a->tmp[1];
+    AHIP(a, adj_fwd_step(a, in, out));
+    AHIP(a, launch_nu_obj(a->c, a->zr, out, w, a->acc, a->stream));
+    in = out;
+  }
+  double host[2];
+  AHIP(a, hipMemcpyAsync(&host[0], a->acc, sizeof(double), hipMemcpyDeviceToHost, a->stream));
+  AHIP(a, hipMemcpyAsync(&host[1], &a->sh->dt_frozen, sizeof(double), hipMemcpyDeviceToHost,
+                         a->stream));
+  AHIP(a, hipStreamSynchronize(a->stream));
+  if (J) *J = host[0];
+  if (dt_used) *dt_used = host[1];
+  if (!isfinite(host[0])) return aerr(a, MTVD_ENONFINITE, "non-finite objective");
+  a->have_fwd = true;
+  return MTVD_OK;
+}
+
+int mtvd_adj_backward(mtvd_adj* a, double Jbar, double* grad_x0, double* grad_theta,
+                      double* grad_ra) {
+  if (!a) return MTVD_EINVAL;
+  if (!a->have_fwd) return aerr(a, MTVD_ESTATE, "mtvd_adj_forward first");
+  if (!isfinite(Jbar)) return aerr(a, MTVD_EINVAL, "non-finite cotangent");
+  const long long cnt = a->c.cnt;
+  const size_t S = 4 * (size_t)cnt;
+  const int* o = kOrder2[a->p.sweep_order];
+  const double w = Jbar / (double)a->nsteps;
+  AHIP(a, launch_fill(a->A.MU, cnt, 0.0, a->stream));
+  AHIP(a, launch_fill(a->A.KB, cnt, 0.0, a->stream));
+  AHIP(a, launch_fill(a->acc + 1, 1, 0.0, a->stream));
+  int cur = 0;   // cot[cur] holds the running cotangent
+  for (int seg = a->nseg - 1; seg >= 0; --seg) {
+    const int s0 = seg * a->every;
+    const int m = (a->nsteps - s0 < a->every) ? a->nsteps - s0 : a->every;
+    double* base = a->ckpt + S * seg;
+    auto state = [&](int q) -> double* { return q == 0 ? base : a->segs + S * (size_t)(q - 1); };
+    for (int j = 0; j < m; ++j)
+      for (int s = 0; s < 4; ++s) {
+        hipError_t e = launch_sweep_2d(o[s], a->c, a->sh, a->zr, 0, 0, false, state(4 * j + s),
+                                       state(4 * j + s + 1), a->kc, a->stream);
+        AHIP(a, e);
+      }
+    for (int j = m - 1; j >= 0; --j) {
+      const int n = s0 + j + 1;   // the step maps X_{n-1} to X_n
+      if (n == a->nsteps) {
+        AHIP(a, launch_fill(a->cot[cur], (long long)S, 0.0, a->stream));
+        AHIP(a, launch_nu_vjp(a->ac, a->c, a->zr, state(4 * m), w, a->cot[cur], a->stream));
+      }
+      for (int s = 3; s >= 0; --s) {
+        adj::Arr A = a->A;
+        A.X = state(4 * j + s);
+        A.Yb = a->cot[cur];
+        A.Xb = a->cot[cur ^ 1];
+        AHIP(a, launch_adj_sweep(o[s], a->ac, A, a->sh, a->stream));
+        cur ^= 1;
+      }
+      if (n - 1 >= 1)
+        AHIP(a, launch_nu_vjp(a->ac, a->c, a->zr, state(4 * j), w, a->cot[cur], a->stream));
+    }
+  }
+  if (grad_x0)
+    AHIP(a, hipMemcpyAsync(grad_x0, a->cot[cur], sizeof(double) * S, hipMemcpyDeviceToDevice,
+                           a->stream));
+  if (grad_theta) AHIP(a, launch_grad_theta(a->c, a->ckpt, a->cot[cur], grad_theta, a->stream));
+  // mu = sqrt(Pr/Ra), K = 1/(eps D sqrt(Ra Pr)): d/dRa = -mu/(2 Ra), -K/(2 Ra)
+  const double Ra = a->p.Ra;
+  AHIP(a, launch_ra_reduce(cnt, a->A.MU, a->A.KB, -a->c.mu / (2.0 * Ra), -a->c.K / (2.0 * Ra),
+                           a->acc + 1, a->stream));
+  double gr = 0.0;
+  AHIP(a, hipMemcpyAsync(&gr, a->acc + 1, sizeof(double), hipMemcpyDeviceToHost, a->stream));
+  AHIP(a, hipStreamSynchronize(a->stream));
+  if (grad_ra) *grad_ra = gr;
+  if (!isfinite(gr)) return aerr(a, MTVD_ENONFINITE, "non-finite gradient");
+  return MTVD_OK;
+}
+
+int mtvd_adj_destroy(mtvd_adj* a) {
+  delete a;
+  return MTVD_OK;
+}
+
+const char* mtvd_adj_last_error(const mtvd_adj* a) { return a ? a->err.c_str() : ""; }
+
+}  // extern "C"

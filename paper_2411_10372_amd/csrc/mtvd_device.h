@@ -40,7 +40,19 @@ struct Shared {
   double dt_last;                 // dt used by the latest step
   double dt_frozen;               // dt when dt_mode = 1
   unsigned int flags;             // bit 0: non-finite / non-positive seen
-  unsigned int pad[7];
+  unsigned int pad[9];            // 128 bytes per box in a batch
+};
+
+// One box of a batch: its constants, the offset of its state in the state
+// arenas (field stride c.cnt from there), of its plate table in the z
+// arena, and its rows per wave for each operator.
+struct BoxDesc {
+  Coef c;
+  long long off;
+  int zoff;
+  int kc_x, kc_z;
+  int nstrips;
+  int pad[2];
 };
 
 __device__ __forceinline__ double u2d(unsigned long long b) {
@@ -72,9 +84,49 @@ __device__ __forceinline__ N2 operator-(const N2& a, const N2& b) {
   return N2{a.r - b.r, a.mx - b.mx, a.mz - b.mz, a.E - b.E};
 }
 
+// 1/x from the hardware estimate and two Newton steps (error within an ulp
+// for the normal, finite, positive arguments the kernels pass)
+__device__ __forceinline__ double frcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// sqrt(y) for normal positive y: reciprocal square-root estimate, one
+// coupled Newton step on (s, h) = (y r, r/2) and a final residual
+// correction (Goldschmidt); within an ulp.  Non-positive or non-finite y
+// gives a non-finite or zero result, which the positivity checks flag.
+__device__ __forceinline__ double fsqrt(double y) {
+  double r = __builtin_amdgcn_rsq(y);
+  double s = y * r;
+  double h = 0.5 * r;
+  double e = fma(-s, h, 0.5);
+  s = fma(s, e, s);
+  h = fma(h, e, h);
+  double d = fma(-s, s, y);
+  return fma(d, h, s);
+}
+
+// lane i <- lane i-1 (wave_shr:1) and lane i <- lane i+1 (wave_shl:1) for a
+// double; the lane without a source gets 0 (it is always a halo lane)
+__device__ __forceinline__ double lane_from_below(double v) {
+  long long b = __double_as_longlong(v);
+  int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x138, 0xf, 0xf, false);
+  int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double lane_from_above(double v) {
+  long long b = __double_as_longlong(v);
+  int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x130, 0xf, 0xf, false);
+  int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // primitives (Sec. 2): u = m/rho, T = (E/rho - |u|^2/2 - g z)/c_v, p = a rho T
 __device__ __forceinline__ P2 prim2(const Coef& c, const N2& x, double z) {
-  double ri = 1.0 / x.r;
+  double ri = frcp(x.r);
   P2 q;
   q.ux = x.mx * ri;
   q.uz = x.mz * ri;
@@ -86,7 +138,7 @@ __device__ __forceinline__ P2 prim2(const Coef& c, const N2& x, double z) {
 
 // sound speed c = sqrt(gamma p / rho) = sqrt(gamma a T)
 __device__ __forceinline__ double sound(const Coef& c, double T) {
-  return sqrt(c.gam_a * T);
+  return fsqrt(c.gam_a * T);
 }
 
 // Flux along z (Sec. 3.1 F_3; tau_zz, tau_xz of Sec. 2) given the inner
@@ -132,7 +184,7 @@ __device__ __forceinline__ double tvd_G(const Coef& c, double a_m, double a_p,
                                         double den, double Co) {
   if (den == 0.0) return 0.0;
   double C = (Co <= 0.5) ? Co * (1.0 - Co) : 0.25;
-  double id = 1.0 / den;
+  double id = frcp(den);
   if (c.limiter_form == 0) {
     return 0.5 * C * (1.0 - phi(a_m * id + a_p * id));
   }

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "mtvd_adjoint.h"
 #include "mtvd_device.h"
 
 namespace mtvd {
@@ -13,9 +14,32 @@ hipError_t launch_sweep_2d(int axis, const Coef& c, Shared* sh, const double* zr
                            hipStream_t s);
 int strips_2d(int nx);
 
+// all boxes of a batch, one directional operator (2D), one launch
+hipError_t launch_batch_2d(int axis, const BoxDesc* boxes, const int4* items, int nitems,
+                           Shared* shs, const double* zarena, int slot, int first, bool fuse,
+                           const double* X, double* Y, hipStream_t s);
+
 // one directional operator L_axis(tau) in 3D (axis 0 = x, 1 = y, 2 = z)
 hipError_t launch_sweep_3d(int axis, const Coef& c, Shared* sh, const double* zr, int slot,
                            int first, bool fuse, const double* X, double* Y, int kc,
                            hipStream_t s);
+
+// reverse of one 2D operator L_axis(dt_frozen/2) at A.X: A.Xb = J^T A.Yb,
+// A.MU and A.KB accumulate the mu and K cotangents
+hipError_t launch_adj_sweep(int axis, const adj::AC& c, const adj::Arr& A, const Shared* sh,
+                            hipStream_t s);
+hipError_t launch_fill(double* a, long long n, double v, hipStream_t s);
+hipError_t launch_ra_reduce(long long cnt, const double* MU, const double* KB, double s_mu,
+                            double s_K, double* out, hipStream_t s);
+// acc[0] += w Nu_mean(X) (2D)
+hipError_t launch_nu_obj(const Coef& c, const double* zr, const double* X, double w, double* acc,
+                         hipStream_t s);
+// xb += w dNu_mean/dX (2D)
+hipError_t launch_nu_vjp(const adj::AC& ac, const Coef& c, const double* zr, const double* X,
+                         double w, double* xb, hipStream_t s);
+hipError_t launch_init_theta(const Coef& c, const double* zr, const double* theta, double* X,
+                             hipStream_t s);
+hipError_t launch_grad_theta(const Coef& c, const double* X0, const double* xb, double* gt,
+                             hipStream_t s);
 
 }  // namespace mtvd

@@ -1,0 +1,100 @@
+"""Summaries of rocprofv3 output for the files under ``profiles/``.
+
+``trace``: per-kernel call counts and average durations from a
+``rocprofv3 --kernel-trace --stats --output-format csv`` run.
+
+``pmc``: HBM bytes per launch of one kernel from two ``rocprofv3 --pmc``
+runs (``FETCH_SIZE``, then ``WRITE_SIZE``; KiB per dispatch), each scaled by
+what the same counter reads for a plain device copy of known size (the
+largest ``__amd_rocclr_copyBuffer`` dispatch of the run: ``bench.py
+--copy-ref`` copies 256 MiB).
+
+Usage (paths are the rocprofv3 output directories):
+    python -m paper_2411_10372_amd.profiling trace DIR OUT.md "COMMAND"
+    python -m paper_2411_10372_amd.profiling pmc FETCH_DIR WRITE_DIR KERNEL \
+        WORKLOAD SOURCE_HASH COPY_BYTES OUT.json "COMMANDS"
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import json
+import os
+import sys
+
+
+def _one(pattern: str) -> str:
+    hits = sorted(glob.glob(pattern))
+    if not hits:
+        raise FileNotFoundError(pattern)
+    return hits[0]
+
+
+def trace_summary(trace_dir: str, out_md: str, command: str, top: int = 12) -> list:
+    rows = list(csv.DictReader(open(_one(os.path.join(trace_dir, "*kernel_stats.csv")))))
+    lines = ["# Kernel trace summary", "", "Command:", "", "```", command, "```", "",
+             "| kernel | calls | avg (us) | min (us) | max (us) | share of GPU time |",
+             "|---|---|---|---|---|---|"]
+    out = []
+    for r in rows[:top]:
+        name = r["Name"].split("(")[0].replace("void ", "")
+        avg, mn, mx = (float(r[k]) / 1e3 for k in ("AverageNs", "MinNs", "MaxNs"))
+        lines.append(f"| `{name}` | {r['Calls']} | {avg:.1f} | {mn:.1f} | {mx:.1f} | "
+                     f"{float(r['Percentage']):.2f} % |")
+        out.append({"kernel": name, "calls": int(r["Calls"]), "avg_us": avg})
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return out
+
+
+def _counter(dir_: str):
+    return list(csv.DictReader(open(_one(os.path.join(dir_, "*counter_collection.csv")))))
+
+
+def _mean_for(rows, pred):
+    v = [float(r["Counter_Value"]) for r in rows if pred(r)]
+    return (sum(v) / len(v), len(v)) if v else (None, 0)
+
+
+def pmc_summary(fetch_dir: str, write_dir: str, kernel: str, workload: str, shash: str,
+                copy_bytes: int, out_json: str, commands: str) -> dict:
+    fr, wr = _counter(fetch_dir), _counter(write_dir)
+
+    def is_kernel(r):
+        return kernel in r["Kernel_Name"]
+
+    def big_copy(rows):
+        copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        gmax = max(int(r["Grid_Size"]) for r in copies)
+        return lambda r: "copyBuffer" in r["Kernel_Name"] and int(r["Grid_Size"]) == gmax
+
+    fetch_kib, nf = _mean_for(fr, is_kernel)
+    write_kib, nw = _mean_for(wr, is_kernel)
+    cf, _ = _mean_for(fr, big_copy(fr))
+    cw, _ = _mean_for(wr, big_copy(wr))
+    half_kib = copy_bytes / 2 / 1024          # the copy reads and writes this much
+    fs, ws = half_kib / cf, half_kib / cw
+    d = {
+        "kernel": kernel, "workload": workload, "source_hash": shash,
+        "fetch_kib_per_dispatch": fetch_kib, "write_kib_per_dispatch": write_kib,
+        "dispatches": [nf, nw],
+        "copy_ref": {"bytes_read": copy_bytes // 2, "bytes_written": copy_bytes // 2,
+                     "fetch_kib": cf, "write_kib": cw, "fetch_scale": fs, "write_scale": ws},
+        "hbm_bytes_per_launch": (fetch_kib * fs + write_kib * ws) * 1024.0,
+        "commands": commands,
+    }
+    with open(out_json, "w") as f:
+        json.dump(d, f, indent=1)
+    return d
+
+
+if __name__ == "__main__":
+    a = sys.argv[1:]
+    if a and a[0] == "trace":
+        print(json.dumps(trace_summary(a[1], a[2], a[3]), indent=1))
+    elif a and a[0] == "pmc":
+        print(json.dumps(pmc_summary(a[1], a[2], a[3], a[4], a[5], int(a[6]), a[7], a[8]),
+                         indent=1))
+    else:
+        print(__doc__)
+        sys.exit(2)

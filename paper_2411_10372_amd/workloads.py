@@ -31,3 +31,59 @@ def params_dict(name: str, **overrides) -> dict:
     w = dict(WORKLOADS[name])
     w.update(overrides)
     return {k: w[k] for k in PARAM_KEYS if k in w}
+
+
+# ---------------------------------------------------------------------------
+# 64 independent 2D boxes advanced together
+
+BATCH_SIZES = ((128, 32), (256, 64), (512, 128), (1024, 256))
+
+
+def _splitmix64(seed: int, n: int) -> int:
+    """n-th output of SplitMix64 from `seed` (Steele, Lea & Flood 2014);
+    used here only to draw the batch layout."""
+    m = (1 << 64) - 1
+    z = (seed + n * 0x9E3779B97F4A7C15) & m
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & m
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & m
+    return z ^ (z >> 31)
+
+
+def _u01(seed: int, n: int) -> float:
+    return (_splitmix64(seed, n) >> 11) * 2.0 ** -53
+
+
+def _diffusion_ok(nx: int, nz: int, Ra: float, Pr: float = 1.0) -> bool:
+    """The explicit-diffusion limit the library enforces, for the batch
+    layout (same inequality, evaluated here so every drawn box is legal)."""
+    eps, D, gamma, aspect, cfl, amp = 0.1, 0.4, 1.4, 4.0, 0.5, 1e-3
+    h = min(aspect / nx, 1.0 / (nz - 1))
+    Delta = eps + D
+    m = gamma * D / ((gamma - 1.0) * Delta)
+    rho_min = min(1.0, (1.0 - Delta) ** (m - 1.0))
+    a = (gamma - 1.0) / (gamma * eps * D)
+    tau = 0.5 * cfl * h / (gamma * a * (1.0 + amp)) ** 0.5
+    mu = (Pr / Ra) ** 0.5
+    K = 1.0 / (eps * D * (Ra * Pr) ** 0.5)
+    cv = 1.0 / (gamma * eps * D)
+    return max(mu * (2.0 + 2.0 / 3.0), K / cv) * tau / (rho_min * h * h) <= 0.5
+
+
+def batch_boxes(nbox: int = 64, seed: int = 3):
+    """Parameter sets of the batch: box b takes size option floor(4 U) of
+    BATCH_SIZES with U the draw 2b+1 of stream `seed`, Ra = 10^(5 + 4 U')
+    with U' the draw 2b+2, noise seed 1000 + b.  A size whose explicit
+    diffusion limit that Ra would break is replaced by the largest smaller
+    size that keeps it."""
+    out = []
+    for b in range(nbox):
+        k = min(3, int(4 * _u01(seed, 2 * b + 1)))
+        Ra = 10.0 ** (5.0 + 4.0 * _u01(seed, 2 * b + 2))
+        while k > 0 and not _diffusion_ok(*BATCH_SIZES[k], Ra):
+            k -= 1
+        nx, nz = BATCH_SIZES[k]
+        out.append(dict(COMMON, ndim=2, nx=nx, ny=1, nz=nz, Ra=Ra, seed=1000 + b))
+    return out
+
+
+WORKLOADS["batch_64_mixed_2d"] = dict(COMMON, ndim=2, boxes=64, layout_seed=3, steps=500)

@@ -30,3 +30,19 @@ def perturb(X: np.ndarray, seed: int, amp: float = 0.02, mom_scale: float = 1.0)
 def roll_x(X: np.ndarray, s: int) -> np.ndarray:
     """Periodic shift by s columns along x (the last axis)."""
     return np.roll(X, s, axis=-1)
+
+
+def theta_field(nz: int, nx: int, seed: int, amp: float = 1e-3) -> np.ndarray:
+    """(nz, nx) temperature perturbation, amp*U with U uniform in [-1, 1)."""
+    rng = np.random.default_rng(seed)
+    return amp * rng.uniform(-1.0, 1.0, size=(nz, nx))
+
+
+def unit_directions(nz: int, nx: int, count: int, seed: int) -> np.ndarray:
+    """(count, nz, nx) Gaussian directions on the interior rows (plate rows
+    zero), each scaled to unit Euclidean norm."""
+    rng = np.random.default_rng(seed)
+    V = np.zeros((count, nz, nx))
+    V[:, 1:nz - 1, :] = rng.standard_normal((count, nz - 2, nx))
+    V /= np.sqrt(np.sum(V * V, axis=(1, 2)))[:, None, None]
+    return V

@@ -64,3 +64,28 @@ def test_strerror_covers_every_code(L):
     for code in range(0, -7, -1):
         s = L.mtvd_strerror(code).decode()
         assert s and s != "unknown status"
+
+
+def test_adjoint_sizes_and_restrictions(L):
+    # workspace: checkpoints (ceil(N/E) states), one interval's operator
+    # inputs (4E states), and per-node stage arrays; 2D and the printed
+    # limiter only
+    import paper_2411_10372_amd as mtvd
+    wb = ctypes.c_size_t()
+    p = mtvd.Params(nx=512, nz=128, Ra=1e7)._c()
+    assert L.mtvd_adj_bytes(ctypes.byref(p), 500, 50, ctypes.byref(wb)) == 0
+    state = 4 * 512 * 128 * 8
+    assert wb.value >= (10 + 200) * state
+    assert wb.value <= (10 + 200) * state + 80 * 512 * 128 * 8 + (1 << 20)
+    small = wb.value
+    assert L.mtvd_adj_bytes(ctypes.byref(p), 500, 10, ctypes.byref(wb)) == 0
+    assert wb.value < small                      # fewer recomputed states
+    assert L.mtvd_adj_bytes(ctypes.byref(p), 0, 50, ctypes.byref(wb)) == -1
+    assert L.mtvd_adj_bytes(ctypes.byref(p), 10, 0, ctypes.byref(wb)) == -1
+    for bad in (dict(limiter_form=1), dict(ndim=3, ny=8, nx=16, nz=9)):
+        q = mtvd.Params(**bad)._c()
+        assert L.mtvd_adj_bytes(ctypes.byref(q), 10, 5, ctypes.byref(wb)) == -1
+    ctx = ctypes.c_void_p()
+    q = mtvd.Params(limiter_form=1)._c()
+    assert L.mtvd_adj_create(ctypes.byref(q), 10, 5, None, ctypes.byref(ctx)) == -1
+    assert not ctx.value
