@@ -34,13 +34,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def source_hash() -> str:
+KERNEL_SOURCES = {2: ("mtvd_2d.hip", "mtvd_device.h"), 3: ("mtvd_3d.hip", "mtvd_device.h")}
+
+
+def source_hash(files=None) -> str:
+    """Hash of the kernel sources (all of them, or the named files)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2411_10372_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            h.update(f.encode())
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    names = sorted(files) if files else sorted(
+        f for f in os.listdir(csrc) if f.endswith((".hip", ".h")))
+    for f in names:
+        h.update(f.encode())
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -147,6 +152,74 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_adjoint(args):
+    """Cost of the gradient of the time-averaged Nu-bar (checkpointed forward
+    pass + backward pass) as a multiple of the plain forward run of the same
+    steps on the same GPU.  --steps counts gradient evaluations here (at most
+    10); each covers the workload's 500 steps."""
+    import numpy as np
+    import torch
+    import paper_2411_10372_amd as mtvd
+    from paper_2411_10372_amd.workloads import WORKLOADS, params_dict
+
+    wl = WORKLOADS[args.workload]
+    p = mtvd.Params(**params_dict(args.workload))
+    N, E = wl["steps"], wl["adjoint_every"]
+    reps = max(1, min(args.steps, 10))
+    torch.cuda.set_device(0)
+    rng = np.random.default_rng(wl["theta_seed"])
+    theta = torch.tensor(wl["theta_amp"] * rng.uniform(-1.0, 1.0, size=(p.nz, p.nx)),
+                         device="cuda:0")
+    a = mtvd.Adjoint(p, N, E, device="cuda:0")
+    J, dt = a.forward(theta, 0.0)
+    a.backward(1.0)
+    # the plain step of the same box with the same frozen dt, N steps
+    s = mtvd.Solver(p, device="cuda:0")
+    s.init_state()
+    s.step(max(1, args.warmup))
+    s.sync()
+    tf, tb, tp = [], [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(N)
+        s.sync()
+        t1 = time.perf_counter()
+        a.forward(theta, dt)
+        t2 = time.perf_counter()
+        a.backward(1.0)
+        t3 = time.perf_counter()
+        tp.append(t1 - t0)
+        tf.append(t2 - t1)
+        tb.append(t3 - t2)
+    t_plain, t_fwd, t_bwd = (float(np.median(v)) for v in (tp, tf, tb))
+    nodes = p.nodes
+    # algorithmic bytes of the backward pass per node and step: every
+    # operator's input recomputed once (read + write the state, 64 B) and
+    # reversed once (read X and the output cotangent, write the input
+    # cotangent, 96 B)
+    bwd_bytes = nodes * N * 4 * (64 + 96)
+    achieved = bwd_bytes / t_bwd / 1e9
+    out = {
+        "metric": "adjoint cost/forward", "value": (t_fwd + t_bwd) / t_plain, "unit": "x",
+        "n_gpus": 1, "steps": reps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * (t_fwd + t_bwd) / N, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded temperature perturbation)",
+        "config": {"workload": args.workload, "nx": p.nx, "nz": p.nz, "Ra": p.Ra,
+                   "steps_per_gradient": N, "checkpoint_every": E, "dt": dt},
+        "plain_forward_ms": 1e3 * t_plain, "adjoint_forward_ms": 1e3 * t_fwd,
+        "adjoint_backward_ms": 1e3 * t_bwd, "backward_over_plain": t_bwd / t_plain,
+        "roofline": {"bound": "hbm", "kernel": "backward pass (all stage kernels)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_gradient": bwd_bytes},
+        "J": J, "workspace_MiB": a.workspace_bytes / 2 ** 20,
+        "source_hash": source_hash(),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,6 +246,8 @@ def main():
     wl = WORKLOADS[args.workload]
     if "boxes" in wl:
         return bench_batch(args)
+    if "adjoint_every" in wl:
+        return bench_adjoint(args)
     kw = params_dict(args.workload)
     p = mtvd.Params(**kw)
     diag_every = wl.get("diag_every", 0)
@@ -224,7 +299,7 @@ def main():
     per_launch_bytes = nodes * 2 * p.nf * 8      # read + write every field once
     avg_s = 1e-3 * ms[dom] / cnt[dom]
     achieved = per_launch_bytes / avg_s / 1e9
-    shash = source_hash()
+    shash = source_hash(KERNEL_SOURCES[p.ndim])
     traffic = load_traffic(args.workload, AXES[dom], shash)
 
     value = nodes * K / t_all

@@ -205,7 +205,7 @@ int mtvd_batch_set_tiling(mtvd_batch* b, int32_t box, int32_t rows_x, int32_t ro
  * wave {4, 8, 16, 32, 64} for L_z and then L_x, keep the fastest for every
  * box of that size, and restore the state, time and dt afterwards.
  * `scratch` is caller-owned device memory of at least state_bytes +
- * 128 * nbox bytes.  Synchronises. */
+ * 2048 * nbox bytes.  Synchronises. */
 int mtvd_batch_autotune(mtvd_batch* b, void* scratch, int32_t trial_steps);
 int mtvd_batch_get_tiling(const mtvd_batch* b, int32_t box, int32_t* rows_x,
                           int32_t* rows_z);
@@ -258,6 +258,11 @@ int mtvd_adj_forward(mtvd_adj* a, const double* theta, double dt, double* J, dou
  * Synchronises. */
 int mtvd_adj_backward(mtvd_adj* a, double Jbar, double* grad_x0, double* grad_theta,
                       double* grad_ra);
+/* Jbar dJ/d(mu) and Jbar dJ/d(K) of the latest backward pass (host), mu and
+ * K the viscosity and conductivity coefficients; d/dRa is made of these two
+ * parts, d(mu)/dRa = -mu/(2 Ra) and d(K)/dRa = -K/(2 Ra).  MTVD_ESTATE before
+ * a backward pass. */
+int mtvd_adj_coef_grads(const mtvd_adj* a, double* grad_mu, double* grad_K);
 int mtvd_adj_destroy(mtvd_adj* a);
 const char* mtvd_adj_last_error(const mtvd_adj* a);
 

@@ -142,7 +142,7 @@ def lib():
         L.ora_step.argtypes = [P, dp, ctypes.c_int, dp, dp]
         L.ora_diag.argtypes = [P, dp, ctypes.POINTER(_Diag)]
         L.ora_time_avg_nu_cs.argtypes = [P, dp, dp, ctypes.c_double, ctypes.c_double,
-                                         ctypes.c_int, ctypes.c_double, dp, dp]
+                                         ctypes.c_double, ctypes.c_int, ctypes.c_double, dp, dp]
         for fn in ("ora_init", "ora_init_box", "ora_sweep", "ora_sweep_box",
                    "ora_step", "ora_diag", "ora_time_avg_nu_cs"):
             getattr(L, fn).restype = ctypes.c_int
@@ -268,11 +268,24 @@ def time_avg_nu(p: Params, X0: np.ndarray, nsteps: int, dt: float) -> float:
     return acc / nsteps
 
 
+def mu_K(p: Params):
+    """The viscosity and conductivity coefficients of Sec. 2 (mu* = sqrt(Pr/Ra),
+    K* = 1/(eps D sqrt(Ra Pr))) and their derivatives with respect to Ra."""
+    mu = np.sqrt(p.Pr / p.Ra)
+    K = 1.0 / (p.eps * p.D * np.sqrt(p.Ra * p.Pr))
+    return mu, K, -mu / (2.0 * p.Ra), -K / (2.0 * p.Ra)
+
+
 def time_avg_nu_cs(p: Params, X0: np.ndarray, V, nsteps: int, dt: float,
-                   dRa: float = 0.0, h: float = 1e-20):
+                   dRa: float = 0.0, h: float = 1e-20, dmu: float = 0.0, dK: float = 0.0):
     """Complex-step mode of :func:`time_avg_nu`: (J, dJ) with dJ the
-    derivative of J along the state direction V (None: no state direction)
-    plus dRa times d/dRa, on the branches the run takes."""
+    derivative of J along the state direction V (None: no state direction),
+    plus dmu times d/dmu* and dK times d/dK*, plus dRa times d/dRa (through
+    mu* and K*), on the branches the run takes."""
+    if dRa:
+        _, _, dmu_dRa, dK_dRa = mu_K(p)
+        dmu = dmu + dRa * dmu_dRa
+        dK = dK + dRa * dK_dRa
     X0 = np.ascontiguousarray(X0, dtype=np.float64)
     Vp = None
     if V is not None:
@@ -282,7 +295,7 @@ def time_avg_nu_cs(p: Params, X0: np.ndarray, V, nsteps: int, dt: float,
         Vp = _ptr(V)
     J, dJ = ctypes.c_double(), ctypes.c_double()
     pc = p._c()
-    _ok(lib().ora_time_avg_nu_cs(ctypes.byref(pc), _ptr(X0), Vp, h, dRa, nsteps, dt,
+    _ok(lib().ora_time_avg_nu_cs(ctypes.byref(pc), _ptr(X0), Vp, h, dmu, dK, nsteps, dt,
                                  ctypes.byref(J), ctypes.byref(dJ)), "time_avg_nu_cs")
     return J.value, dJ.value
 

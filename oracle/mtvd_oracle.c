@@ -510,16 +510,14 @@ static double complex nu_mean_cs(const coefs* c, const double complex* X) {
 }
 
 int ora_time_avg_nu_cs(const ora_params* p, const double* X0, const double* V, double h,
-                       double dRa, int nsteps, double dt, double* J, double* dJ) {
+                       double dmu, double dK, int nsteps, double dt, double* J, double* dJ) {
   if (check_params(p)) return -1;
   if (nsteps < 1 || !(dt > 0.0) || !(h > 0.0)) return -1;
   coefs c;
   make_coefs(p, &c);
   set_threads(p);
-  /* Ra + i h dRa enters through mu = sqrt(Pr/Ra) and K = 1/(eps D sqrt(Ra Pr)):
-   * d mu/dRa = -mu/(2 Ra), dK/dRa = -K/(2 Ra) */
-  c.mu_cs = c.mu + (h * dRa * (-c.mu / (2.0 * p->Ra))) * I;
-  c.K_cs = c.K + (h * dRa * (-c.K / (2.0 * p->Ra))) * I;
+  c.mu_cs = c.mu + (h * dmu) * I;
+  c.K_cs = c.K + (h * dK) * I;
   size_t len = ora_state_len(p);
   double complex* X = (double complex*)malloc(sizeof(double complex) * len);
   double complex* Y = (double complex*)malloc(sizeof(double complex) * len);

@@ -97,12 +97,14 @@ int ora_step(const ora_params* p, double* X, int nsteps, double* time,
 int ora_diag(const ora_params* p, const double* X, ora_diag_t* d);
 
 /* Complex-step mode (checks of the adjoint): N = nsteps steps with the fixed
- * dt from X0 + i h V (V may be NULL) and Ra + i h dRa, every branch decided
- * on real parts.  *J = (1/N) sum_{n=1..N} Nu_mean(X_n) of the real part and
- * *dJ = Im(...)/h, the derivative of J along (V, dRa) on the branches taken
- * (Squire & Trapp, SIAM Review 40, 1998).  Returns -1 on bad arguments. */
+ * dt from X0 + i h V (V may be NULL), mu + i h dmu and K + i h dK (mu and K
+ * the viscosity and conductivity coefficients of the parameters), every
+ * branch decided on real parts.  *J = (1/N) sum_{n=1..N} Nu_mean(X_n) of the
+ * real part and *dJ = Im(...)/h, the derivative of J along (V, dmu, dK) on
+ * the branches taken (Squire & Trapp, SIAM Review 40, 1998).  Returns -1 on
+ * bad arguments. */
 int ora_time_avg_nu_cs(const ora_params* p, const double* X0, const double* V, double h,
-                       double dRa, int nsteps, double dt, double* J, double* dJ);
+                       double dmu, double dK, int nsteps, double dt, double* J, double* dJ);
 
 #ifdef __cplusplus
 }

@@ -162,11 +162,12 @@ def lib() -> ctypes.CDLL:
         L.mtvd_adj_bind.argtypes = [vp, vp]
         L.mtvd_adj_forward.argtypes = [vp, vp, ctypes.c_double, dp, dp]
         L.mtvd_adj_backward.argtypes = [vp, ctypes.c_double, vp, vp, dp]
+        L.mtvd_adj_coef_grads.argtypes = [vp, dp, dp]
         L.mtvd_adj_destroy.argtypes = [vp]
         L.mtvd_adj_last_error.argtypes = [vp]
         L.mtvd_adj_last_error.restype = ctypes.c_char_p
         for fn in ("mtvd_adj_bytes", "mtvd_adj_create", "mtvd_adj_bind", "mtvd_adj_forward",
-                   "mtvd_adj_backward", "mtvd_adj_destroy"):
+                   "mtvd_adj_backward", "mtvd_adj_coef_grads", "mtvd_adj_destroy"):
             getattr(L, fn).restype = ctypes.c_int
         for fn in ("mtvd_batch_bytes", "mtvd_batch_create", "mtvd_batch_bind",
                    "mtvd_batch_offset", "mtvd_batch_init_state", "mtvd_batch_step",
@@ -391,7 +392,7 @@ class Batch:
     def autotune(self, trial_steps: int = 4):
         """Pick rows per wave per box size by timing (state restored)."""
         import torch
-        scratch = torch.empty((self.state_bytes + 128 * self.n + 7) // 8 + 32,
+        scratch = torch.empty((self.state_bytes + 2048 * self.n + 7) // 8 + 32,
                               dtype=torch.float64, device=self.device)
         self._check(lib().mtvd_batch_autotune(self.ctx, ctypes.c_void_p(scratch.data_ptr()),
                                               int(trial_steps)))
@@ -478,6 +479,12 @@ class Adjoint:
         self._check(lib().mtvd_adj_backward(self.ctx, float(Jbar), ctypes.c_void_p(gx.data_ptr() if gx is not None else 0),
                                             ctypes.c_void_p(gt.data_ptr()), ctypes.byref(gr)))
         return gt, gx, gr.value
+
+    def coef_grads(self):
+        """(dJ/dmu*, dJ/dK*) of the latest backward pass, times its Jbar."""
+        gm, gk = ctypes.c_double(), ctypes.c_double()
+        self._check(lib().mtvd_adj_coef_grads(self.ctx, ctypes.byref(gm), ctypes.byref(gk)))
+        return gm.value, gk.value
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -65,10 +65,12 @@ __device__ __forceinline__ N2 dn(const N2& v) { return N2{dn(v.r), dn(v.mx), dn(
 // into that slot.
 __device__ __forceinline__ void step_head(const Coef& c, Shared* sh, int slot, int first,
                                           double dt) {
-  if (first && blockIdx.x == 0 && threadIdx.x == 0) {
-    sh->time += dt;
-    sh->dt_last = dt;
-    for (int a = 0; a < 4; ++a) sh->smax[slot ^ 1][a] = 0ull;
+  if (first && blockIdx.x == 0 && threadIdx.x < kMaxParts * 4) {
+    if (threadIdx.x == 0) {
+      sh->time += dt;
+      sh->dt_last = dt;
+    }
+    sh->smax[slot ^ 1][threadIdx.x >> 2][threadIdx.x & 3] = 0ull;
   }
 }
 
@@ -78,8 +80,8 @@ __device__ __forceinline__ void fold_max(Shared* sh, int slot, double mx, double
   mz = wave_max(mz);
   unsigned long long anybad = __ballot(bad);
   if ((threadIdx.x & 63) == 0) {
-    atomicMax(&sh->smax[slot ^ 1][0], d2u(mx));
-    atomicMax(&sh->smax[slot ^ 1][2], d2u(mz));
+    atomicMax(&sh->smax[slot ^ 1][max_part()][0], d2u(mx));
+    atomicMax(&sh->smax[slot ^ 1][max_part()][2], d2u(mz));
     if (anybad) atomicOr(&sh->flags, 1u);
   }
 }
@@ -115,140 +117,174 @@ struct Z2 {
   bool bad;
 };
 
+// The stages of one march step f of L_z.  Ring slots: row f in S & 3,
+// f-1 in (S+3) & 3, f-2 in (S+2) & 3, f-3 in (S+1) & 3; period-2 rings: row
+// f (and f-2) in S & 1, f-1 in (S+1) & 1.
+template <int S>
+struct ZS {
+  static constexpr int c0 = S & 3, c1 = (S + 3) & 3, c2 = (S + 2) & 3, c3 = (S + 1) & 3;
+  static constexpr int c4 = S & 3;   // row f-4 (its slot is reused by row f)
+  static constexpr int e0 = S & 1, e1 = (S + 1) & 1;
+};
+
+// A: row f (prefetched) and its primitives; prefetch row f+2 when `pre`
+template <int S>
+__device__ __forceinline__ void z2_load(const Coef& c, Z2& st, int f, bool pre, const Cols& L,
+                                        const double* __restrict__ zr,
+                                        const double* __restrict__ X) {
+  using Z = ZS<S>;
+  st.x[Z::c0] = st.pf[Z::e0];
+  if (pre) st.pf[Z::e0] = load2(c, X, f + 2, L.col);
+  st.pn[Z::c0] = prim2(c, st.x[Z::c0], zr[f]);
+  st.s[Z::c0] = fabs(st.pn[Z::c0].uz) + sound(c, st.pn[Z::c0].T);
+}
+
+// B: predictor flux F_r of row r = f-2 (inner z forward; second-order
+//    forward at the bottom plate when `wall`), central x cross-derivatives
+template <int S>
+__device__ __forceinline__ void z2_pflux(const Coef& c, Z2& st, bool wall) {
+  using Z = ZS<S>;
+  const P2& q0 = st.pn[Z::c2];
+  const P2& q1 = st.pn[Z::c1];
+  double dzux, dzuz, dzT;
+  if (wall) {
+    const P2& q2 = st.pn[Z::c0];
+    double h2 = 0.5 * c.ihz;
+    dzux = ((-3.0 * q0.ux + 4.0 * q1.ux) - q2.ux) * h2;
+    dzuz = ((-3.0 * q0.uz + 4.0 * q1.uz) - q2.uz) * h2;
+    dzT = ((-3.0 * q0.T + 4.0 * q1.T) - q2.T) * h2;
+  } else {
+    dzux = (q1.ux - q0.ux) * c.ihz;
+    dzuz = (q1.uz - q0.uz) * c.ihz;
+    dzT = (q1.T - q0.T) * c.ihz;
+  }
+  double dxux = (up(q0.ux) - dn(q0.ux)) * (0.5 * c.ihx);
+  double dxuz = (up(q0.uz) - dn(q0.uz)) * (0.5 * c.ihx);
+  P2 q = q0;
+  q.p = c.a * st.x[Z::c2].r * q0.T;
+  st.F[Z::e0] = flux_z2(c, st.x[Z::c2], q, dzux, dzuz, dzT, dxux, dxuz);
+}
+
+// C (interior rows): X^P_r = X_r - (tau/dz)(F_r - F_{r-1}) + tau S(X_r)
+template <int S>
+__device__ __forceinline__ void z2_pred(const Coef& c, Z2& st, double z, double tau, double lz) {
+  using Z = ZS<S>;
+  const N2& Fa = st.F[Z::e0];
+  const N2& Fb = st.F[Z::e1];
+  N2 v = st.x[Z::c2] - N2{lz * (Fa.r - Fb.r), lz * (Fa.mx - Fb.mx), lz * (Fa.mz - Fb.mz),
+                          lz * (Fa.E - Fb.E)};
+  v.mz = v.mz + tau * (-c.g * st.x[Z::c2].r);
+  st.xp[Z::c2] = v;
+  st.pp[Z::c2] = prim2(c, v, z);
+}
+
+// D: corrector flux F^P_r (inner z backward; second-order backward at the
+//    top plate when `wall`), central x cross-derivatives of X^P
+template <int S>
+__device__ __forceinline__ void z2_cflux(const Coef& c, Z2& st, bool wall) {
+  using Z = ZS<S>;
+  const P2& q0 = st.pp[Z::c2];
+  const P2& qm = st.pp[Z::c3];
+  double dzux, dzuz, dzT;
+  if (wall) {
+    const P2& qmm = st.pp[Z::c4];
+    double h2 = 0.5 * c.ihz;
+    dzux = ((3.0 * q0.ux - 4.0 * qm.ux) + qmm.ux) * h2;
+    dzuz = ((3.0 * q0.uz - 4.0 * qm.uz) + qmm.uz) * h2;
+    dzT = ((3.0 * q0.T - 4.0 * qm.T) + qmm.T) * h2;
+  } else {
+    dzux = (q0.ux - qm.ux) * c.ihz;
+    dzuz = (q0.uz - qm.uz) * c.ihz;
+    dzT = (q0.T - qm.T) * c.ihz;
+  }
+  double dxux = (up(q0.ux) - dn(q0.ux)) * (0.5 * c.ihx);
+  double dxuz = (up(q0.uz) - dn(q0.uz)) * (0.5 * c.ihx);
+  st.FP[Z::e0] = flux_z2(c, st.xp[Z::c2], q0, dzux, dzuz, dzT, dxux, dxuz);
+}
+
+// E (faces away from the plates): TVD coefficient of face r+1/2 from the
+//    X^n ring
+template <int S>
+__device__ __forceinline__ double z2_tvd(const Coef& c, const Z2& st, double lz) {
+  using Z = ZS<S>;
+  N2 dm = st.x[Z::c2] - st.x[Z::c3];
+  N2 d0 = st.x[Z::c1] - st.x[Z::c2];
+  N2 dp = st.x[Z::c0] - st.x[Z::c1];
+  double Co = lz * fmax(st.s[Z::c2], st.s[Z::c1]);
+  return tvd_G(c, dot2(dm, d0), dot2(d0, dp), dot2(d0, d0), Co);
+}
+
+// F: corrector, average and TVD term of row o = f-3 (when `emit`); the face
+//    o+1/2 term G dX is carried to the next row as its o-1/2 term
+template <int S, bool FUSE>
+__device__ __forceinline__ void z2_out(const Coef& c, Z2& st, bool emit, int o, const Cols& L,
+                                       const double* __restrict__ zr, double* __restrict__ Y,
+                                       double tau, double lz) {
+  using Z = ZS<S>;
+  N2 d0 = st.x[Z::c2] - st.x[Z::c3];
+  double G = st.G[Z::e1];
+  N2 Dc{G * d0.r, G * d0.mx, G * d0.mz, G * d0.E};
+  if (emit) {
+    const N2& fp1 = st.FP[Z::e0];
+    const N2& fp0 = st.FP[Z::e1];
+    N2 xc = st.x[Z::c3] - N2{lz * (fp1.r - fp0.r), lz * (fp1.mx - fp0.mx),
+                             lz * (fp1.mz - fp0.mz), lz * (fp1.E - fp0.E)};
+    xc.mz = xc.mz + tau * (-c.g * st.xp[Z::c3].r);
+    const N2& xp = st.xp[Z::c3];
+    const N2& Dm = st.Dp;
+    N2 out;
+    out.r = 0.5 * (xp.r + xc.r) + (Dc.r - Dm.r);
+    out.mx = 0.5 * (xp.mx + xc.mx) + (Dc.mx - Dm.mx);
+    out.mz = 0.5 * (xp.mz + xc.mz) + (Dc.mz - Dm.mz);
+    out.E = 0.5 * (xp.E + xc.E) + (Dc.E - Dm.E);
+    if (FUSE) out_max(c, out, zr[o], st.mx, st.mz, st.bad, L.out);
+    if (L.out) store2(c, Y, o, L.col, out);
+  }
+  st.Dp = Dc;
+}
+
+// One march step: plates, chunk edges and the end of the grid are guarded.
 template <int S, bool FUSE>
 __device__ __forceinline__ void z2_iter(const Coef& c, Z2& st, int f, int fs, int fe,
                                         int k0, int k1, const Cols& L,
                                         const double* __restrict__ zr,
                                         const double* __restrict__ X,
                                         double* __restrict__ Y, double tau, double lz) {
+  using Z = ZS<S>;
   if (f < fs || f > fe) return;
   const int M = c.M;
-  constexpr int c0 = S & 3;          // row f
-  constexpr int c1 = (S + 3) & 3;    // row f-1
-  constexpr int c2 = (S + 2) & 3;    // row f-2
-  constexpr int c3 = (S + 1) & 3;    // row f-3
-  constexpr int c4 = S & 3;          // row f-4 (its slot is reused by row f)
-  constexpr int e0 = S & 1;          // row f (and f-2) in period-2 rings
-  constexpr int e1 = (S + 1) & 1;    // row f-1 (and f-3)
-
-  // A: row f (prefetched) and its primitives; prefetch row f+2
-  if (f <= M) {
-    st.x[c0] = st.pf[e0];
-    if (f + 2 <= M) st.pf[e0] = load2(c, X, f + 2, L.col);
-    st.pn[c0] = prim2(c, st.x[c0], zr[f]);
-    st.s[c0] = fabs(st.pn[c0].uz) + sound(c, st.pn[c0].T);
-  }
+  if (f <= M) z2_load<S>(c, st, f, f + 2 <= M, L, zr, X);
   const int r = f - 2;
-  // B: predictor flux F_r (inner z forward; second-order forward at the
-  //    bottom plate when wall_order = 2), central x cross-derivatives
-  if (r >= k0 - 2 && r >= 0 && r <= M - 1) {
-    const P2& q0 = st.pn[c2];
-    const P2& q1 = st.pn[c1];
-    double dzux, dzuz, dzT;
-    if (r == 0 && c.wall_order == 2) {
-      const P2& q2 = st.pn[c0];
-      double h2 = 0.5 * c.ihz;
-      dzux = ((-3.0 * q0.ux + 4.0 * q1.ux) - q2.ux) * h2;
-      dzuz = ((-3.0 * q0.uz + 4.0 * q1.uz) - q2.uz) * h2;
-      dzT = ((-3.0 * q0.T + 4.0 * q1.T) - q2.T) * h2;
-    } else {
-      dzux = (q1.ux - q0.ux) * c.ihz;
-      dzuz = (q1.uz - q0.uz) * c.ihz;
-      dzT = (q1.T - q0.T) * c.ihz;
-    }
-    double dxux = (up(q0.ux) - dn(q0.ux)) * (0.5 * c.ihx);
-    double dxuz = (up(q0.uz) - dn(q0.uz)) * (0.5 * c.ihx);
-    P2 q = q0;
-    q.p = c.a * st.x[c2].r * q0.T;
-    st.F[e0] = flux_z2(c, st.x[c2], q, dzux, dzuz, dzT, dxux, dxuz);
-  }
-  // C: predictor X^P_r = X_r - (tau/dz)(F_r - F_{r-1}) + tau S(X_r); plates:
-  //    u = 0, T = T_plate, top density from the backward mass-flux difference
+  if (r >= k0 - 2 && r >= 0 && r <= M - 1) z2_pflux<S>(c, st, r == 0 && c.wall_order == 2);
+  // C: plates: u = 0, T = T_plate, top density from the backward mass-flux
+  //    difference
   if (r >= k0 - 1 && r >= 0 && r <= M) {
     if (r == 0) {
-      double rho = st.x[c2].r;
-      st.xp[c2] = N2{rho, 0.0, 0.0, rho * (c.cv * c.Tb + c.g * zr[0])};
-      st.pp[c2] = P2{0.0, 0.0, c.Tb, c.a * rho * c.Tb};
+      double rho = st.x[Z::c2].r;
+      st.xp[Z::c2] = N2{rho, 0.0, 0.0, rho * (c.cv * c.Tb + c.g * zr[0])};
+      st.pp[Z::c2] = P2{0.0, 0.0, c.Tb, c.a * rho * c.Tb};
     } else if (r == M) {
-      double rho = st.x[c2].r - lz * (st.x[c2].mz - st.x[c3].mz);
-      st.xp[c2] = N2{rho, 0.0, 0.0, rho * (c.cv * c.Tt + c.g * zr[M])};
-      st.pp[c2] = P2{0.0, 0.0, c.Tt, c.a * rho * c.Tt};
+      double rho = st.x[Z::c2].r - lz * (st.x[Z::c2].mz - st.x[Z::c3].mz);
+      st.xp[Z::c2] = N2{rho, 0.0, 0.0, rho * (c.cv * c.Tt + c.g * zr[M])};
+      st.pp[Z::c2] = P2{0.0, 0.0, c.Tt, c.a * rho * c.Tt};
     } else {
-      const N2& Fa = st.F[e0];
-      const N2& Fb = st.F[e1];
-      N2 v = st.x[c2] - N2{lz * (Fa.r - Fb.r), lz * (Fa.mx - Fb.mx), lz * (Fa.mz - Fb.mz),
-                           lz * (Fa.E - Fb.E)};
-      v.mz = v.mz + tau * (-c.g * st.x[c2].r);
-      st.xp[c2] = v;
-      st.pp[c2] = prim2(c, v, zr[r]);
+      z2_pred<S>(c, st, zr[r], tau, lz);
     }
   }
-  // D: corrector flux F^P_r (inner z backward; second-order backward at the
-  //    top plate when wall_order = 2), central x cross-derivatives of X^P
-  if (r >= k0 && r >= 1 && r <= M) {
-    const P2& q0 = st.pp[c2];
-    const P2& qm = st.pp[c3];
-    double dzux, dzuz, dzT;
-    if (r == M && c.wall_order == 2) {
-      const P2& qmm = st.pp[c4];
-      double h2 = 0.5 * c.ihz;
-      dzux = ((3.0 * q0.ux - 4.0 * qm.ux) + qmm.ux) * h2;
-      dzuz = ((3.0 * q0.uz - 4.0 * qm.uz) + qmm.uz) * h2;
-      dzT = ((3.0 * q0.T - 4.0 * qm.T) + qmm.T) * h2;
-    } else {
-      dzux = (q0.ux - qm.ux) * c.ihz;
-      dzuz = (q0.uz - qm.uz) * c.ihz;
-      dzT = (q0.T - qm.T) * c.ihz;
-    }
-    double dxux = (up(q0.ux) - dn(q0.ux)) * (0.5 * c.ihx);
-    double dxuz = (up(q0.uz) - dn(q0.uz)) * (0.5 * c.ihx);
-    st.FP[e0] = flux_z2(c, st.xp[c2], q0, dzux, dzuz, dzT, dxux, dxuz);
-  }
-  // E: TVD coefficient of face q+1/2, q = f-2 (zero on the two faces next
-  //    to the plates); the jumps come from the X^n ring
-  if (r >= k0 - 1 && r >= 0 && r <= M - 1) {
-    double G = 0.0;
-    if (c.tvd_on && r >= 1 && r <= M - 2) {
-      N2 dm = st.x[c2] - st.x[c3];
-      N2 d0 = st.x[c1] - st.x[c2];
-      N2 dp = st.x[c0] - st.x[c1];
-      double Co = lz * fmax(st.s[c2], st.s[c1]);
-      G = tvd_G(c, dot2(dm, d0), dot2(d0, dp), dot2(d0, d0), Co);
-    }
-    st.G[e0] = G;
-  }
-  // F: corrector, average, TVD term and plate closure of row o = f-3; the
-  //    face o+1/2 term G dX is carried to the next row as its o-1/2 term
+  if (r >= k0 && r >= 1 && r <= M) z2_cflux<S>(c, st, r == M && c.wall_order == 2);
+  // E: zero on the two faces next to the plates
+  if (r >= k0 - 1 && r >= 0 && r <= M - 1)
+    st.G[Z::e0] = (c.tvd_on && r >= 1 && r <= M - 2) ? z2_tvd<S>(c, st, lz) : 0.0;
   const int o = f - 3;
-  if (o >= k0 - 1 && o >= 0 && o < k1 && o <= M - 1) {
-    N2 d0 = st.x[c2] - st.x[c3];
-    double G = st.G[e1];
-    N2 Dc{G * d0.r, G * d0.mx, G * d0.mz, G * d0.E};
-    if (o >= k0 && o >= 1) {
-      const N2& fp1 = st.FP[e0];
-      const N2& fp0 = st.FP[e1];
-      N2 xc = st.x[c3] - N2{lz * (fp1.r - fp0.r), lz * (fp1.mx - fp0.mx),
-                            lz * (fp1.mz - fp0.mz), lz * (fp1.E - fp0.E)};
-      xc.mz = xc.mz + tau * (-c.g * st.xp[c3].r);
-      const N2& xp = st.xp[c3];
-      const N2& Dm = st.Dp;
-      N2 out;
-      out.r = 0.5 * (xp.r + xc.r) + (Dc.r - Dm.r);
-      out.mx = 0.5 * (xp.mx + xc.mx) + (Dc.mx - Dm.mx);
-      out.mz = 0.5 * (xp.mz + xc.mz) + (Dc.mz - Dm.mz);
-      out.E = 0.5 * (xp.E + xc.E) + (Dc.E - Dm.E);
-      if (FUSE) out_max(c, out, zr[o], st.mx, st.mz, st.bad, L.out);
-      if (L.out) store2(c, Y, o, L.col, out);
-    }
-    st.Dp = Dc;
-  }
+  if (o >= k0 - 1 && o >= 0 && o < k1 && o <= M - 1)
+    z2_out<S, FUSE>(c, st, o >= k0 && o >= 1, o, L, zr, Y, tau, lz);
   if (o >= k0 && o < k1 && (o == 0 || o == M)) {
     N2 out;
     if (o == 0) {
-      double rho = st.x[c3].r - lz * (st.xp[c2].mz - 0.0);
+      double rho = st.x[Z::c3].r - lz * (st.xp[Z::c2].mz - 0.0);
       out = N2{rho, 0.0, 0.0, rho * (c.cv * c.Tb + c.g * zr[0])};
     } else {
-      double rho = st.xp[c3].r;
+      double rho = st.xp[Z::c3].r;
       out = N2{rho, 0.0, 0.0, rho * (c.cv * c.Tt + c.g * zr[M])};
     }
     if (FUSE) out_max(c, out, zr[o], st.mx, st.mz, st.bad, L.out);
@@ -325,83 +361,96 @@ struct X2 {
   bool bad;
 };
 
+// The stages of one march step f of L_x (ring slots as for L_z).
+template <int S>
+__device__ __forceinline__ void x2_load(const Coef& c, X2& st, int f, bool pre, const Cols& L,
+                                        const double* __restrict__ zr,
+                                        const double* __restrict__ X) {
+  using Z = ZS<S>;
+  st.x[Z::c0] = st.pf[Z::e0];
+  if (pre) st.pf[Z::e0] = load2(c, X, f + 2, L.col);
+  st.pn[Z::c0] = prim2(c, st.x[Z::c0], zr[f]);
+}
+
+// predictor on interior row f-1: X^P_i = X_i - (tau/dx)(F_i - F_{i-1})
+template <int S>
+__device__ __forceinline__ void x2_pred(const Coef& c, X2& st, double z, double lx) {
+  using Z = ZS<S>;
+  P2 q = st.pn[Z::c1];
+  q.p = c.a * st.x[Z::c1].r * q.T;
+  double dxux = (up(q.ux) - q.ux) * c.ihx;
+  double dxuz = (up(q.uz) - q.uz) * c.ihx;
+  double dxT = (up(q.T) - q.T) * c.ihx;
+  double dzux = (st.pn[Z::c0].ux - st.pn[Z::c2].ux) * (0.5 * c.ihz);
+  double dzuz = (st.pn[Z::c0].uz - st.pn[Z::c2].uz) * (0.5 * c.ihz);
+  N2 Fi = flux_x2(c, st.x[Z::c1], q, dxux, dxuz, dxT, dzux, dzuz);
+  N2 Fm = dn(Fi);
+  N2 v = st.x[Z::c1] - N2{lx * (Fi.r - Fm.r), lx * (Fi.mx - Fm.mx), lx * (Fi.mz - Fm.mz),
+                          lx * (Fi.E - Fm.E)};
+  st.xp[Z::c1] = v;
+  st.pp[Z::c1] = prim2(c, v, z);
+}
+
+// corrector, average and TVD term on interior row f-2
+template <int S>
+__device__ __forceinline__ N2 x2_corr(const Coef& c, const X2& st, double lx) {
+  using Z = ZS<S>;
+  const P2& q = st.pp[Z::c2];
+  double dxux = (q.ux - dn(q.ux)) * c.ihx;
+  double dxuz = (q.uz - dn(q.uz)) * c.ihx;
+  double dxT = (q.T - dn(q.T)) * c.ihx;
+  double dzux = (st.pp[Z::c1].ux - st.pp[Z::c3].ux) * (0.5 * c.ihz);
+  double dzuz = (st.pp[Z::c1].uz - st.pp[Z::c3].uz) * (0.5 * c.ihz);
+  N2 Fi = flux_x2(c, st.xp[Z::c2], q, dxux, dxuz, dxT, dzux, dzuz);
+  N2 Fp = up(Fi);
+  const N2& x0 = st.x[Z::c2];
+  N2 xc = x0 - N2{lx * (Fp.r - Fi.r), lx * (Fp.mx - Fi.mx), lx * (Fp.mz - Fi.mz),
+                  lx * (Fp.E - Fi.E)};
+  // TVD: face i+1/2 belongs to lane i; its dX_{+3/2}.dX_{+1/2} product is
+  // the dX_{-1/2}.dX_{+1/2} product of face i+3/2, one lane up
+  N2 d0 = up(x0) - x0;
+  double G = 0.0;
+  if (c.tvd_on) {
+    N2 dm = dn(d0);
+    double a_m = dot2(dm, d0);
+    double s0 = fabs(st.pn[Z::c2].ux) + sound(c, st.pn[Z::c2].T);
+    double Co = lx * fmax(s0, up(s0));
+    G = tvd_G(c, a_m, up(a_m), dot2(d0, d0), Co);
+  }
+  N2 D{G * d0.r, G * d0.mx, G * d0.mz, G * d0.E};
+  N2 Dm = dn(D);
+  const N2& xp = st.xp[Z::c2];
+  N2 out;
+  out.r = 0.5 * (xp.r + xc.r) + (D.r - Dm.r);
+  out.mx = 0.5 * (xp.mx + xc.mx) + (D.mx - Dm.mx);
+  out.mz = 0.5 * (xp.mz + xc.mz) + (D.mz - Dm.mz);
+  out.E = 0.5 * (xp.E + xc.E) + (D.E - Dm.E);
+  return out;
+}
+
+// One march step (plate rows are copied through).
 template <int S, bool FUSE>
 __device__ __forceinline__ void x2_iter(const Coef& c, X2& st, int f, int fs, int fe,
                                         int k0, int k1, const Cols& L,
                                         const double* __restrict__ zr,
                                         const double* __restrict__ X,
                                         double* __restrict__ Y, double lx) {
+  using Z = ZS<S>;
   if (f < fs || f > fe) return;
   const int M = c.M;
-  constexpr int c0 = S & 3;          // row f
-  constexpr int c1 = (S + 3) & 3;    // row f-1
-  constexpr int c2 = (S + 2) & 3;    // row f-2
-  constexpr int c3 = (S + 1) & 3;    // row f-3
-  constexpr int e0 = S & 1;
-
-  if (f <= M) {
-    st.x[c0] = st.pf[e0];
-    if (f + 2 <= M) st.pf[e0] = load2(c, X, f + 2, L.col);
-    st.pn[c0] = prim2(c, st.x[c0], zr[f]);
-  }
-  // predictor on row f-1: X^P_i = X_i - (tau/dx)(F_i - F_{i-1})
+  if (f <= M) x2_load<S>(c, st, f, f + 2 <= M, L, zr, X);
   const int r1 = f - 1;
   if (r1 >= k0 - 1 && r1 >= 0 && r1 <= M) {
     if (r1 == 0 || r1 == M) {
-      st.xp[c1] = st.x[c1];
-      st.pp[c1] = st.pn[c1];
+      st.xp[Z::c1] = st.x[Z::c1];
+      st.pp[Z::c1] = st.pn[Z::c1];
     } else {
-      P2 q = st.pn[c1];
-      q.p = c.a * st.x[c1].r * q.T;
-      double dxux = (up(q.ux) - q.ux) * c.ihx;
-      double dxuz = (up(q.uz) - q.uz) * c.ihx;
-      double dxT = (up(q.T) - q.T) * c.ihx;
-      double dzux = (st.pn[c0].ux - st.pn[c2].ux) * (0.5 * c.ihz);
-      double dzuz = (st.pn[c0].uz - st.pn[c2].uz) * (0.5 * c.ihz);
-      N2 Fi = flux_x2(c, st.x[c1], q, dxux, dxuz, dxT, dzux, dzuz);
-      N2 Fm = dn(Fi);
-      N2 v = st.x[c1] - N2{lx * (Fi.r - Fm.r), lx * (Fi.mx - Fm.mx), lx * (Fi.mz - Fm.mz),
-                           lx * (Fi.E - Fm.E)};
-      st.xp[c1] = v;
-      st.pp[c1] = prim2(c, v, zr[r1]);
+      x2_pred<S>(c, st, zr[r1], lx);
     }
   }
-  // corrector, average and TVD term on row f-2
   const int r = f - 2;
   if (r >= k0 && r < k1) {
-    N2 out;
-    if (r == 0 || r == M) {
-      out = st.x[c2];
-    } else {
-      const P2& q = st.pp[c2];
-      double dxux = (q.ux - dn(q.ux)) * c.ihx;
-      double dxuz = (q.uz - dn(q.uz)) * c.ihx;
-      double dxT = (q.T - dn(q.T)) * c.ihx;
-      double dzux = (st.pp[c1].ux - st.pp[c3].ux) * (0.5 * c.ihz);
-      double dzuz = (st.pp[c1].uz - st.pp[c3].uz) * (0.5 * c.ihz);
-      N2 Fi = flux_x2(c, st.xp[c2], q, dxux, dxuz, dxT, dzux, dzuz);
-      N2 Fp = up(Fi);
-      const N2& x0 = st.x[c2];
-      N2 xc = x0 - N2{lx * (Fp.r - Fi.r), lx * (Fp.mx - Fi.mx), lx * (Fp.mz - Fi.mz),
-                      lx * (Fp.E - Fi.E)};
-      // TVD: face i+1/2 belongs to lane i
-      N2 d0 = up(x0) - x0;
-      double G = 0.0;
-      if (c.tvd_on) {
-        N2 dm = dn(d0);
-        N2 dp = up(d0);
-        double s0 = fabs(st.pn[c2].ux) + sound(c, st.pn[c2].T);
-        double Co = lx * fmax(s0, up(s0));
-        G = tvd_G(c, dot2(dm, d0), dot2(d0, dp), dot2(d0, d0), Co);
-      }
-      N2 D{G * d0.r, G * d0.mx, G * d0.mz, G * d0.E};
-      N2 Dm = dn(D);
-      const N2& xp = st.xp[c2];
-      out.r = 0.5 * (xp.r + xc.r) + (D.r - Dm.r);
-      out.mx = 0.5 * (xp.mx + xc.mx) + (D.mx - Dm.mx);
-      out.mz = 0.5 * (xp.mz + xc.mz) + (D.mz - Dm.mz);
-      out.E = 0.5 * (xp.E + xc.E) + (D.E - Dm.E);
-    }
+    N2 out = (r == 0 || r == M) ? st.x[Z::c2] : x2_corr<S>(c, st, lx);
     if (FUSE) out_max(c, out, zr[r], st.mx, st.mz, st.bad, L.out);
     if (L.out) store2(c, Y, r, L.col, out);
   }
@@ -482,10 +531,12 @@ __global__ __launch_bounds__(256) void sweep_batch2d(const BoxDesc* __restrict__
   const Coef c = bd->c;
   Shared* sh = shs + it.x;
   const double dt = step_dt(c, sh, slot);
-  if (first && it.w && lane == 0) {
-    sh->time += dt;
-    sh->dt_last = dt;
-    for (int a = 0; a < 4; ++a) sh->smax[slot ^ 1][a] = 0ull;
+  if (first && it.w) {
+    if (lane == 0) {
+      sh->time += dt;
+      sh->dt_last = dt;
+    }
+    sh->smax[slot ^ 1][lane >> 2][lane & 3] = 0ull;   // 64 lanes, 16 x 4 entries
   }
   const double* zr = zarena + bd->zoff;
   if (AXIS == 2)
@@ -497,6 +548,20 @@ __global__ __launch_bounds__(256) void sweep_batch2d(const BoxDesc* __restrict__
 // ---------------------------------------------------------------------------
 
 int strips_2d(int nx) { return (nx + kStrip - 1) / kStrip; }
+
+int wave_slots_2d(int axis, bool fuse) {
+  int dev = 0, cus = 0, nb = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  const void* fn;
+  if (axis == 2)
+    fn = fuse ? (const void*)sweep_z2d<true> : (const void*)sweep_z2d<false>;
+  else
+    fn = fuse ? (const void*)sweep_x2d<true> : (const void*)sweep_x2d<false>;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, 0) != hipSuccess) return 0;
+  return nb * 4 * cus;
+}
 
 hipError_t launch_batch_2d(int axis, const BoxDesc* boxes, const int4* items, int nitems,
                            Shared* shs, const double* zarena, int slot, int first, bool fuse,

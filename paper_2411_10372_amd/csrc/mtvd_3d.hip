@@ -163,18 +163,20 @@ __device__ __forceinline__ void fold3(Shared* sh, int slot, Acc3& a) {
   double m0 = wave_max(a.s[0]), m1 = wave_max(a.s[1]), m2 = wave_max(a.s[2]);
   unsigned long long anybad = __ballot(a.bad);
   if ((threadIdx.x & 63) == 0) {
-    atomicMax(&sh->smax[slot ^ 1][0], d2u(m0));
-    atomicMax(&sh->smax[slot ^ 1][1], d2u(m1));
-    atomicMax(&sh->smax[slot ^ 1][2], d2u(m2));
+    atomicMax(&sh->smax[slot ^ 1][max_part()][0], d2u(m0));
+    atomicMax(&sh->smax[slot ^ 1][max_part()][1], d2u(m1));
+    atomicMax(&sh->smax[slot ^ 1][max_part()][2], d2u(m2));
     if (anybad) atomicOr(&sh->flags, 1u);
   }
 }
 
 __device__ __forceinline__ void head3(Shared* sh, int slot, int first, double dt) {
-  if (first && blockIdx.x == 0 && threadIdx.x == 0) {
-    sh->time += dt;
-    sh->dt_last = dt;
-    for (int a = 0; a < 4; ++a) sh->smax[slot ^ 1][a] = 0ull;
+  if (first && blockIdx.x == 0 && threadIdx.x < kMaxParts * 4) {
+    if (threadIdx.x == 0) {
+      sh->time += dt;
+      sh->dt_last = dt;
+    }
+    sh->smax[slot ^ 1][threadIdx.x >> 2][threadIdx.x & 3] = 0ull;
   }
 }
 

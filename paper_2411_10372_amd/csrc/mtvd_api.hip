@@ -103,7 +103,7 @@ __global__ void init_kernel(Coef c, const double* __restrict__ zr, double* __res
 }
 
 __global__ void clear_slot_kernel(Shared* sh, int slot) {
-  if (threadIdx.x < 4) sh->smax[slot][threadIdx.x] = 0ull;
+  if (threadIdx.x < kMaxParts * 4) sh->smax[slot][threadIdx.x >> 2][threadIdx.x & 3] = 0ull;
 }
 
 __global__ void set_scalars_kernel(Shared* sh, double time, int clear_flags) {
@@ -143,9 +143,9 @@ __global__ __launch_bounds__(256) void dt_kernel(Coef c, Shared* sh, const doubl
   for (int a = 0; a < 3; ++a) m[a] = wave_max(m[a]);
   unsigned long long anybad = __ballot(bad);
   if ((threadIdx.x & 63) == 0) {
-    atomicMax(&sh->smax[slot][0], d2u(m[0]));
-    if (c.ndim == 3) atomicMax(&sh->smax[slot][1], d2u(m[1]));
-    atomicMax(&sh->smax[slot][2], d2u(m[2]));
+    atomicMax(&sh->smax[slot][max_part()][0], d2u(m[0]));
+    if (c.ndim == 3) atomicMax(&sh->smax[slot][max_part()][1], d2u(m[1]));
+    atomicMax(&sh->smax[slot][max_part()][2], d2u(m[2]));
     if (anybad) atomicOr(&sh->flags, 1u);
   }
 }
@@ -271,6 +271,7 @@ struct mtvd_ctx {
   int64_t step;
   bool bound, have_state;
   int rows_x, rows_z;
+  int slots_x, slots_z;   // resident waves of the 2D sweep kernels
   bool timing;
   struct Rec { int axis; hipEvent_t a, b; };
   std::vector<Rec> recs;
@@ -391,12 +392,17 @@ Coef make_coef(const mtvd_params* p) {
 Shared* shared_of(mtvd_ctx* c) { return (Shared*)(c->ws + c->L.shared); }
 double* zrow_of(mtvd_ctx* c) { return (double*)(c->ws + c->L.zrow); }
 
-int default_rows(const mtvd_ctx* c) {
+int default_rows(const mtvd_ctx* c, int axis) {
   long long kc;
   if (c->c.ndim == 2) {
-    // about four waves per SIMD (1024 SIMDs) when the grid allows it
-    long long cols = (long long)strips_2d(c->c.nx);
-    kc = cols * c->c.nz / 4096;
+    // the fewest rows per wave that keep the whole launch in one round of
+    // the device's resident waves: long marches (less halo re-reading per
+    // row) and no partly filled last round
+    const long long cols = (long long)strips_2d(c->c.nx);
+    const int slots = axis == 2 ? c->slots_z : c->slots_x;
+    long long chunks = slots > 0 ? slots / cols : 1;
+    if (chunks < 1) chunks = 1;
+    kc = (c->c.nz + chunks - 1) / chunks;
   } else {
     // 3D: blocks of 8 waves; a quarter of the marched extent, 4..32 rows
     kc = c->c.nz / 4;
@@ -420,7 +426,7 @@ hipError_t sweep_launch(mtvd_ctx* c, int axis, int first, bool fuse) {
   const double* X = c->buf[c->cur];
   double* Y = c->buf[c->cur ^ 1];
   int kc = (axis == 2) ? c->rows_z : c->rows_x;
-  if (kc <= 0) kc = default_rows(c);
+  if (kc <= 0) kc = default_rows(c, axis);
   hipError_t e;
   mtvd_ctx::Rec rec{axis, nullptr, nullptr};
   if (c->timing) {
@@ -458,6 +464,15 @@ int refresh_dt(mtvd_ctx* c) {
     HIPCHK(c, hipGetLastError());
   }
   return MTVD_OK;
+}
+
+// max over the partial maxima of a slot, as step_dt takes it on the device
+void host_slot_max(const Shared& hs, int slot, double S[3]) {
+  for (int a = 0; a < 3; ++a) {
+    unsigned long long m = 0ull;
+    for (int q = 0; q < kMaxParts; ++q) m = hs.smax[slot][q][a] > m ? hs.smax[slot][q][a] : m;
+    memcpy(&S[a], &m, sizeof(double));
+  }
 }
 
 int read_flags(mtvd_ctx* c, unsigned int* flags) {
@@ -536,6 +551,11 @@ int mtvd_create(const mtvd_params* p, void* hip_stream, mtvd_ctx** out) {
   c->step = 0;
   c->bound = c->have_state = false;
   c->rows_x = c->rows_z = 0;
+  c->slots_x = c->slots_z = 0;
+  if (c->c.ndim == 2) {
+    c->slots_x = wave_slots_2d(0, false);
+    c->slots_z = wave_slots_2d(2, false);
+  }
   c->timing = false;
   *out = c;
   return MTVD_OK;
@@ -640,7 +660,7 @@ int mtvd_diagnostics(mtvd_ctx* c, mtvd_diag* out) {
   } else {
     // the same arithmetic as step_dt on the device
     double S[3];
-    for (int a = 0; a < 3; ++a) memcpy(&S[a], &hs.smax[c->slot][a], sizeof(double));
+    host_slot_max(hs, c->slot, S);
     double m = fmin(c->c.hx / S[0], c->c.hz / S[2]);
     if (c->c.ndim == 3) m = fmin(m, c->c.hy / S[1]);
     out->dt = c->c.cfl * m;
@@ -1133,7 +1153,7 @@ int mtvd_batch_diagnostics(mtvd_batch* b, int32_t box, mtvd_diag* out) {
     out->dt = hs.dt_frozen;
   } else {
     double S[3];
-    for (int a = 0; a < 3; ++a) memcpy(&S[a], &hs.smax[b->slot][a], sizeof(double));
+    host_slot_max(hs, b->slot, S);
     out->dt = c.cfl * fmin(c.hx / S[0], c.hz / S[2]);
   }
   out->mass = host[0];
@@ -1210,6 +1230,7 @@ int mtvd_batch_autotune(mtvd_batch* b, void* scratch, int32_t trial_steps) {
   if ((uintptr_t)scratch % kAlign) return berr(b, MTVD_ESIZE, "scratch must be 256-byte aligned");
   const size_t sbytes = b->state_doubles * sizeof(double);
   const size_t shbytes = sizeof(Shared) * (size_t)b->nbox;
+  static_assert(sizeof(Shared) <= 2048, "the documented scratch size per box");
   unsigned char* sc = (unsigned char*)scratch;
   // save the state (current buffer), the per-box scalars and the slot
   BHIP(b, hipMemcpyAsync(sc, b->buf[b->cur], sbytes, hipMemcpyDeviceToDevice, b->stream));
@@ -1316,7 +1337,8 @@ struct mtvd_adj {
   Shared* sh;
   adj::Arr A;
   size_t total;
-  bool bound, have_fwd;
+  bool bound, have_fwd, have_bwd;
+  double gmu, gK;         // Jbar dJ/dmu*, Jbar dJ/dK* of the latest backward pass
   std::string err;
 };
 
@@ -1464,7 +1486,8 @@ int mtvd_adj_create(const mtvd_params* p, int32_t nsteps, int32_t every, void* h
   a->total = adj_layout(a, nullptr);
   a->stream = (hipStream_t)hip_stream;
   a->ws = nullptr;
-  a->bound = a->have_fwd = false;
+  a->bound = a->have_fwd = a->have_bwd = false;
+  a->gmu = a->gK = 0.0;
   *out = a;
   return MTVD_OK;
 }
@@ -1479,7 +1502,7 @@ int mtvd_adj_bind(mtvd_adj* a, void* workspace) {
   zrow_kernel<<<(a->c.nz + 255) / 256, 256, 0, a->stream>>>(a->c.nz, a->zr);
   AHIP(a, hipGetLastError());
   a->bound = true;
-  a->have_fwd = false;
+  a->have_fwd = a->have_bwd = false;
   return MTVD_OK;
 }
 
@@ -1487,7 +1510,7 @@ int mtvd_adj_forward(mtvd_adj* a, const double* theta, double dt, double* J, dou
   if (!a) return MTVD_EINVAL;
   if (!a->bound) return aerr(a, MTVD_ESTATE, "mtvd_adj_bind first");
   if (!(dt >= 0.0) || !isfinite(dt)) return aerr(a, MTVD_EINVAL, "dt must be finite and >= 0");
-  a->have_fwd = false;
+  a->have_fwd = a->have_bwd = false;
   const size_t S = 4 * (size_t)a->c.cnt;
   AHIP(a, launch_init_theta(a->c, a->zr, theta, a->ckpt, a->stream));
   if (dt > 0.0) {
@@ -1573,13 +1596,27 @@ int mtvd_adj_backward(mtvd_adj* a, double Jbar, double* grad_x0, double* grad_th
   if (grad_theta) AHIP(a, launch_grad_theta(a->c, a->ckpt, a->cot[cur], grad_theta, a->stream));
   // mu = sqrt(Pr/Ra), K = 1/(eps D sqrt(Ra Pr)): d/dRa = -mu/(2 Ra), -K/(2 Ra)
   const double Ra = a->p.Ra;
+  AHIP(a, launch_fill(a->acc + 2, 2, 0.0, a->stream));
   AHIP(a, launch_ra_reduce(cnt, a->A.MU, a->A.KB, -a->c.mu / (2.0 * Ra), -a->c.K / (2.0 * Ra),
                            a->acc + 1, a->stream));
-  double gr = 0.0;
-  AHIP(a, hipMemcpyAsync(&gr, a->acc + 1, sizeof(double), hipMemcpyDeviceToHost, a->stream));
+  AHIP(a, launch_ra_reduce(cnt, a->A.MU, a->A.KB, 1.0, 0.0, a->acc + 2, a->stream));
+  AHIP(a, launch_ra_reduce(cnt, a->A.MU, a->A.KB, 0.0, 1.0, a->acc + 3, a->stream));
+  double g3[3] = {0.0, 0.0, 0.0};
+  AHIP(a, hipMemcpyAsync(g3, a->acc + 1, 3 * sizeof(double), hipMemcpyDeviceToHost, a->stream));
   AHIP(a, hipStreamSynchronize(a->stream));
-  if (grad_ra) *grad_ra = gr;
-  if (!isfinite(gr)) return aerr(a, MTVD_ENONFINITE, "non-finite gradient");
+  if (grad_ra) *grad_ra = g3[0];
+  a->gmu = g3[1];
+  a->gK = g3[2];
+  a->have_bwd = true;
+  if (!isfinite(g3[0])) return aerr(a, MTVD_ENONFINITE, "non-finite gradient");
+  return MTVD_OK;
+}
+
+int mtvd_adj_coef_grads(const mtvd_adj* a, double* grad_mu, double* grad_K) {
+  if (!a || !grad_mu || !grad_K) return MTVD_EINVAL;
+  if (!a->have_bwd) return MTVD_ESTATE;
+  *grad_mu = a->gmu;
+  *grad_K = a->gK;
   return MTVD_OK;
 }
 

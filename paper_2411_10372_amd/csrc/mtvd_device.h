@@ -32,16 +32,26 @@ struct Coef {
   int limiter_form, tvd_on, wall_order, dt_mode;
 };
 
+// Partial maxima per step slot: the blocks of a launch fold into
+// kMaxParts addresses (block index mod kMaxParts) instead of one, so the
+// device-scope atomics of thousands of waves do not queue on a single
+// address; readers take the max over the parts.
+constexpr int kMaxParts = 16;
+
 // Scalars the kernels share through the workspace.
 struct Shared {
-  unsigned long long smax[2][4];  // max over nodes of |u_a| + c (bit patterns
-                                  // of positive doubles), two step slots
+  unsigned long long smax[2][kMaxParts][4];  // max over nodes of |u_a| + c
+                                  // (bit patterns of positive doubles), two
+                                  // step slots of kMaxParts partial maxima
   double time;                    // simulated time of the current state
   double dt_last;                 // dt used by the latest step
   double dt_frozen;               // dt when dt_mode = 1
   unsigned int flags;             // bit 0: non-finite / non-positive seen
-  unsigned int pad[9];            // 128 bytes per box in a batch
+  unsigned int pad[9];            // 1088 bytes per box in a batch
 };
+
+// the part a block folds into
+__device__ __forceinline__ int max_part() { return (int)(blockIdx.x % kMaxParts); }
 
 // One box of a batch: its constants, the offset of its state in the state
 // arenas (field stride c.cnt from there), of its plate table in the z
@@ -66,12 +76,19 @@ __device__ __forceinline__ unsigned long long d2u(double d) {
 // dt = cfl * min_a h_a / max_nodes(|u_a| + c), the same number as the
 // minimum over nodes of h_a/(|u_a| + c) because division by a positive
 // number is monotone.
+__device__ __forceinline__ double slot_max(const Shared* sh, int slot, int a) {
+  // positive doubles order as their bit patterns
+  unsigned long long m = 0ull;
+  for (int q = 0; q < kMaxParts; ++q) m = max(m, sh->smax[slot][q][a]);
+  return u2d(m);
+}
+
 __device__ __forceinline__ double step_dt(const Coef& c, const Shared* sh, int slot) {
   if (c.dt_mode) return sh->dt_frozen;
-  double m = c.hx / u2d(sh->smax[slot][0]);
-  double mz = c.hz / u2d(sh->smax[slot][2]);
+  double m = c.hx / slot_max(sh, slot, 0);
+  double mz = c.hz / slot_max(sh, slot, 2);
   m = fmin(m, mz);
-  if (c.ndim == 3) m = fmin(m, c.hy / u2d(sh->smax[slot][1]));
+  if (c.ndim == 3) m = fmin(m, c.hy / slot_max(sh, slot, 1));
   return c.cfl * m;
 }
 
@@ -110,17 +127,18 @@ __device__ __forceinline__ double fsqrt(double y) {
 }
 
 // lane i <- lane i-1 (wave_shr:1) and lane i <- lane i+1 (wave_shl:1) for a
-// double; the lane without a source gets 0 (it is always a halo lane)
+// double; the lane without a source reads 0 (bound_ctrl; it is always a
+// halo lane), so no old value has to be set up first
 __device__ __forceinline__ double lane_from_below(double v) {
   long long b = __double_as_longlong(v);
-  int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x138, 0xf, 0xf, false);
-  int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xf, 0xf, false);
+  int lo = __builtin_amdgcn_mov_dpp((int)b, 0x138, 0xf, 0xf, true);
+  int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x138, 0xf, 0xf, true);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 __device__ __forceinline__ double lane_from_above(double v) {
   long long b = __double_as_longlong(v);
-  int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x130, 0xf, 0xf, false);
-  int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xf, 0xf, false);
+  int lo = __builtin_amdgcn_mov_dpp((int)b, 0x130, 0xf, 0xf, true);
+  int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x130, 0xf, 0xf, true);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 

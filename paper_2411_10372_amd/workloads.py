@@ -20,6 +20,11 @@ WORKLOADS = {
     # 2D 512 x 128, Ra 1e7, 500 steps, dt frozen: the adjoint case
     "2d_512x128_ra1e7": dict(COMMON, ndim=2, nx=512, ny=1, nz=128, Ra=1e7, seed=4, steps=500,
                              dt_mode=1),
+    # its gradient: time-averaged Nu-bar over 500 steps, checkpoints every 50,
+    # theta uniform +-1e-3 (seed 4) on interior T of the noise-free state
+    "adjoint_512x128_ra1e7": dict(COMMON, ndim=2, nx=512, ny=1, nz=128, Ra=1e7, seed=4,
+                                  steps=500, dt_mode=1, noise_amp=0.0, adjoint_every=50,
+                                  theta_seed=4, theta_amp=1e-3),
 }
 
 PARAM_KEYS = ("ndim", "nx", "ny", "nz", "aspect", "gamma", "Pr", "Ra", "eps", "D", "cfl",

@@ -1,7 +1,8 @@
 """Write tests/golden/adjoint_c4.txt: directional derivatives of the
 time-averaged mean Nusselt number of the adjoint workload (512 x 128, Ra 1e7,
 gamma 1.4, aspect 4, 500 steps with the dt of X_0 frozen; theta = seeded
-uniform +-1e-3, seed 4; 16 unit Gaussian directions, seed 5; and d/dRa),
+uniform +-1e-3, seed 4; 16 unit Gaussian directions, seed 5; d/dmu*, d/dK*
+and d/dRa),
 from the oracle's complex-step mode.  Calls only oracle/ and the seeded
 input generators.  Run from the repository root:
 
@@ -46,6 +47,11 @@ def main(out=os.path.join(HERE, "adjoint_c4.txt")):
         _, d = oracle.time_avg_nu_cs(p, X0, oracle.theta_direction(p, X0, v), NSTEPS, dt)
         lines.append(f"dir {i} {d!r}")
         print(f"direction {i}: {d!r} ({time.time() - t0:.0f} s)", flush=True)
+    # the diffusion coefficients mu* and K*, each alone, and Ra through both
+    _, dmu = oracle.time_avg_nu_cs(p, X0, None, NSTEPS, dt, dmu=1.0)
+    lines.append(f"mu {dmu!r}")
+    _, dK = oracle.time_avg_nu_cs(p, X0, None, NSTEPS, dt, dK=1.0)
+    lines.append(f"K {dK!r}")
     _, dra = oracle.time_avg_nu_cs(p, X0, None, NSTEPS, dt, dRa=1.0)
     lines.append(f"ra {dra!r}")
     with open(out, "w") as f:

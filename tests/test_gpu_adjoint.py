@@ -94,16 +94,28 @@ def test_gradient_matches_oracle_complex_step():
         assert abs((jp - jm) / (2 * H) - ad) <= 1e-6 * gn
 
 
-def test_ra_gradient_matches_oracle_complex_step():
+def _coef_bar(po, dmu, dK):
+    # d/dRa = dJ/dmu* dmu*/dRa + dJ/dK* dK*/dRa can cancel; its error is
+    # bounded by the same relative error on the scale of the two parts
+    _, _, mr, kr = oracle.mu_K(po)
+    return 1e-8 * (abs(dmu * mr) + abs(dK * kr))
+
+
+def test_coefficient_and_ra_gradients_match_oracle_complex_step():
     gpu_or_skip()
     import paper_2411_10372_amd as mtvd
-    _say("d/dRa small")
+    _say("d/dmu*, d/dK*, d/dRa small")
     po, pg, th, X0, dt = _setup(SMALL, 0.05)
     a = mtvd.Adjoint(pg, N_SMALL, EVERY_SMALL)
     a.forward(th, dt)
     _, _, gr = a.backward(1.0)
+    gm, gk = a.coef_grads()
+    _, dmu = oracle.time_avg_nu_cs(po, X0, None, N_SMALL, dt, dmu=1.0)
+    _, dK = oracle.time_avg_nu_cs(po, X0, None, N_SMALL, dt, dK=1.0)
     _, d = oracle.time_avg_nu_cs(po, X0, None, N_SMALL, dt, dRa=1.0)
-    assert abs(d - gr) <= 1e-8 * abs(d), (d, gr)
+    _say("mu", dmu, gm, "K", dK, gk, "Ra", d, gr)
+    assert abs(gm - dmu) <= 1e-8 * abs(dmu) and abs(gk - dK) <= 1e-8 * abs(dK)
+    assert abs(d - gr) <= _coef_bar(po, dmu, dK), (d, gr)
     hr = 1e-4
     pp = oracle.Params(**{**po.__dict__, "Ra": po.Ra * (1 + hr)})
     pm = oracle.Params(**{**po.__dict__, "Ra": po.Ra * (1 - hr)})
@@ -145,7 +157,7 @@ def test_autograd_wrapper():
     b = mtvd.Adjoint(pg, N_SMALL, EVERY_SMALL)
     Jb, _ = b.forward(th, dt)
     g, _, gr = b.backward(3.0)
-    assert float(J) == Jb
+    assert float(J.detach()) == Jb
     assert torch.equal(t.grad, g)
     assert float(ra.grad) == gr
     with pytest.raises(ValueError):
@@ -179,7 +191,8 @@ def _golden():
 
 
 def test_c4_gradient_against_complex_step_golden():
-    # the adjoint workload: 16 directional derivatives and d/dRa stored by
+    # the adjoint workload: 16 directional derivatives, d/dmu*, d/dK* and
+    # d/dRa stored by
     # tests/golden/make_adjoint_c4.py from the oracle's complex-step mode
     gpu_or_skip()
     import paper_2411_10372_amd as mtvd
@@ -198,7 +211,19 @@ def test_c4_gradient_against_complex_step_golden():
     errs = [abs(float(np.sum(g * v)) - gold["dir"][i]) / gn for i, v in enumerate(V)]
     _say("C4 max |adjoint - complex step| / |g|", max(errs))
     assert max(errs) <= _cs_bar(gn) / gn, errs
-    assert abs(gr - gold["ra"]) <= 1e-8 * abs(gold["ra"]), (gr, gold["ra"])
+    gm, gk = a.coef_grads()
+    _say("C4 mu", gm, gold["mu"], "K", gk, gold["K"], "Ra", gr, gold["ra"])
+    # dJ/dmu* and dJ/dK* integrate over the whole 500-step trajectory: the
+    # oracle's own values move by 1.03e-8 and 3.5e-9 (relative) when its
+    # input moves by one ulp, and two FP64 codes differ by rounding at every
+    # step, so the bar is N times that one-ulp sensitivity (linear growth,
+    # no cancellation assumed)
+    rm, rk = N_C4 * 1.03e-8, N_C4 * 3.5e-9
+    assert abs(gm - gold["mu"]) <= rm * abs(gold["mu"]), (gm, gold["mu"])
+    assert abs(gk - gold["K"]) <= rk * abs(gold["K"]), (gk, gold["K"])
+    _, _, mr, kr = oracle.mu_K(po)
+    assert abs(gr - gold["ra"]) <= rm * abs(gold["mu"] * mr) + rk * abs(gold["K"] * kr), (
+        gr, gold["ra"])
 
 
 def test_c4_central_differences_within_the_kink_bound():
