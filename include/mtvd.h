@@ -227,7 +227,7 @@ const char* mtvd_batch_last_error(const mtvd_batch* b);
  * The reverse of each directional operator is hand-written stage by stage;
  * at a kink of max/min/abs/phi it takes the branch the forward pass took.
  * Memory: checkpoints every `every` steps, and one interval's operator
- * inputs (4 every states) recomputed during the backward pass, plus about 76
+ * inputs (4 every states) recomputed during the backward pass, plus about 54
  * doubles per node of stage arrays (mtvd_adj_bytes gives the total).
  * Restrictions: ndim = 2 and limiter_form = 0 (MTVD_EINVAL otherwise);
  * dt_mode is ignored (dt is always frozen).

@@ -1,15 +1,18 @@
 // mtvd_adjoint.h -- reverse mode (vector-Jacobian products) of one 2D
 // directional operator L_a(tau) with tau fixed (frozen dt), stage by stage.
 //
-// The forward operator (Sec. 3.1 of arXiv:2411.10372) is split into stages
+// The forward operator (Sec. 3.1 of arXiv:2411.10372) is taken as stages
 // over whole arrays (primitives P of X; predictor fluxes F; X^P and its
 // primitives P^P; corrector fluxes F^P; X^C; the TVD coefficient G of every
-// face; the output).  The reverse stages below take the cotangent of the
-// output back to the cotangent of X, and accumulate the cotangents of the
-// diffusion coefficients mu and K (from which d/dRa follows).  Every stage is
-// a function of one node (or face) that gathers what its neighbours
-// contribute, so each stage is one kernel without atomics.  Limiter kinks
-// take the branch the forward pass took.
+// face; the output).  Five passes take the cotangent of the output back to
+// the cotangent of X and accumulate the cotangents of the diffusion
+// coefficients mu and K (from which d/dRa follows): fw_all (P, |u|+c, X^P,
+// P^P), rv_tc (output, TVD faces and corrector), rv_pred (P^P -> X^P and
+// the predictor) and rv_prim (P -> X).  Every pass is a function of one
+// node that gathers what its neighbours contribute, recomputing the cheap
+// neighbour values it needs instead of storing them, so each pass is one
+// kernel without atomics.  Limiter kinks take the branch the forward pass
+// took.
 //
 // Layout: arrays of nf = 4 fields (or 4 primitive slots ux, uz, T, p) over
 // nz x nx nodes, field-major, node n = k nx + i.
@@ -239,52 +242,86 @@ MTVD_HD inline void face_vjp(const AC& c, const Face& f, const double dm[4], con
 
 // ---- the stages ---------------------------------------------------------------
 // Arrays of one operator's reverse pass (4 x cnt unless noted):
-//   X, P (primitives of X), S (1: |u_a| + c of X), F, XP, PP   forward values
+//   X, P (primitives of X), S (1: |u_a| + c of X), XP, PP   forward values
 //   Yb (output cotangent), Xb (input cotangent, the result)
-//   XCb, XPb, PPb, PB (primitive cotangents), DPb, DB (5: derivative
-//   cotangents), FAm, FA0, FAp (4: jump cotangents a face sends to the
-//   faces below / itself / above), SB0, SB1 (1: |u|+c cotangent a face
-//   sends to its lower / upper node), SB (1), RPb (1 per column: top-plate
-//   predicted density), MU, KB (1: per-node mu and K cotangents, accumulated
-//   over every operator reversed until the caller clears them)
+//   XPb (X^P cotangent from the corrector), PPb, PB (primitive
+//   cotangents), DPb, DB (5: derivative cotangents), SB (1: |u_a| + c
+//   cotangent), MU, KB (1: per-node mu and K cotangents, accumulated over
+//   every operator reversed until the caller clears them)
+// The predictor fluxes, the X^C cotangent, the cotangents the TVD faces
+// send to their jumps and the final X^P cotangent are not stored: the
+// stages that need them recompute them for the few neighbours involved,
+// with the same arithmetic.
 struct Arr {
   const double *X, *zr;
-  double *P, *S, *F, *XP, *PP;
+  double *P, *S, *XP, *PP;
   const double* Yb;
-  double *Xb, *XCb, *XPb, *PPb, *PB, *DPb, *DB, *FAm, *FA0, *FAp, *SB0, *SB1, *SB, *RPb, *MU, *KB;
+  double *Xb, *XPb, *PPb, *PB, *DPb, *DB, *SB, *MU, *KB;
 };
 
-// forward 1: primitives and |u_a| + c of X
-MTVD_HD inline void fw_prim(const AC& c, const Arr& A, int i, int k) {
+// primitives of X at a node
+MTVD_HD inline void prim_node(const AC& c, const Arr& A, int i, int k, double q[4]) {
+  double x[4];
+  ld4(A.X, c.cnt, nid(c, i, k), x);
+  prim(c, x, A.zr[k], q);
+}
+
+// derivative inputs of the predictor flux at (i, k) (forward inner
+// differences, the bottom-plate rule of the z operator) from primitives
+// recomputed from X: the same values derivs() takes from the stored P
+MTVD_HD inline void derivs_x(const AC& c, const Arr& A, int i, int k, double d[5]) {
+  const int ia = c.axis == 0 ? 0 : 1, ic = 1 - ia;
+  const int slots[3] = {ia, ic, 2};
+  double q0[4], qa[3];
+  prim_node(c, A, i, k, q0);
+  if (c.axis == 2 && k == 0 && c.wall_order == 2) {
+    double q1[4], q2[4];
+    prim_node(c, A, i, 1, q1);
+    prim_node(c, A, i, 2, q2);
+    for (int s = 0; s < 3; ++s)
+      qa[s] = ((-3.0 * q0[slots[s]] + 4.0 * q1[slots[s]]) - q2[slots[s]]) * (0.5 * c.iha);
+  } else {
+    double qm[4];
+    if (c.axis == 0) prim_node(c, A, i + 1, k, qm); else prim_node(c, A, i, k + 1, qm);
+    for (int s = 0; s < 3; ++s) qa[s] = (qm[slots[s]] - q0[slots[s]]) * c.iha;
+  }
+  const double ihc2 = 0.5 * (c.axis == 0 ? c.ihz : c.ihx);
+  double qp[4], qn[4];
+  if (c.axis == 0) {
+    prim_node(c, A, i, k + 1, qp);
+    prim_node(c, A, i, k - 1, qn);
+  } else {
+    prim_node(c, A, i + 1, k, qp);
+    prim_node(c, A, i - 1, k, qn);
+  }
+  d[0] = qa[0];
+  d[1] = qa[1];
+  d[2] = qa[2];
+  d[3] = (qp[ia] - qn[ia]) * ihc2;
+  d[4] = (qp[ic] - qn[ic]) * ihc2;
+}
+
+// predictor flux at (i, k) from X
+MTVD_HD inline void flux_node(const AC& c, const Arr& A, int i, int k, double F[4]) {
+  double x[4], q[4], d[5];
+  ld4(A.X, c.cnt, nid(c, i, k), x);
+  prim(c, x, A.zr[k], q);
+  derivs_x(c, A, i, k, d);
+  flux(c, x, q, d, F);
+}
+
+// forward: primitives and |u_a| + c of X; X^P and its primitives (plate
+// rows as in the fused kernels), with the two predictor fluxes it needs
+MTVD_HD inline void fw_all(const AC& c, const Arr& A, int i, int k) {
   long long n = nid(c, i, k);
-  double x[4], q[4];
+  double x[4], v[4], q[4];
   ld4(A.X, c.cnt, n, x);
   prim(c, x, A.zr[k], q);
   st4(A.P, c.cnt, n, q);
   double ua = c.axis == 0 ? q[0] : q[1];
   A.S[n] = fabs(ua) + sqrt(c.gam_a * q[2]);
-}
-
-// forward 2: predictor flux (forward inner differences)
-MTVD_HD inline void fw_flux(const AC& c, const Arr& A, int i, int k) {
-  if (!has_F(c, i, k)) return;
-  long long n = nid(c, i, k);
-  double x[4], q[4], d[5], F[4];
-  ld4(A.X, c.cnt, n, x);
-  ld4(A.P, c.cnt, n, q);
-  derivs(c, A.P, i, k, 1, d);
-  flux(c, x, q, d, F);
-  st4(A.F, c.cnt, n, F);
-}
-
-// forward 3: X^P and its primitives (plate rows as in the fused kernels)
-MTVD_HD inline void fw_pred(const AC& c, const Arr& A, int i, int k) {
-  long long n = nid(c, i, k);
-  double x[4], v[4], q[4];
-  ld4(A.X, c.cnt, n, x);
   if (c.axis == 0 && !interior(c, k)) {
     st4(A.XP, c.cnt, n, x);
-    ld4(A.P, c.cnt, n, q);
     st4(A.PP, c.cnt, n, q);
     return;
   }
@@ -298,9 +335,10 @@ MTVD_HD inline void fw_pred(const AC& c, const Arr& A, int i, int k) {
     st4(A.PP, c.cnt, n, q);
     return;
   }
-  long long m = along(c, i, k, -1);
-  for (int f = 0; f < 4; ++f)
-    v[f] = x[f] - c.lm * (A.F[f * c.cnt + n] - A.F[f * c.cnt + m]);
+  double Fn[4], Fm[4];
+  flux_node(c, A, i, k, Fn);
+  if (c.axis == 0) flux_node(c, A, i - 1, k, Fm); else flux_node(c, A, i, k - 1, Fm);
+  for (int f = 0; f < 4; ++f) v[f] = x[f] - c.lm * (Fn[f] - Fm[f]);
   if (c.axis == 2) v[2] = v[2] + c.tau * (-c.g * x[0]);
   prim(c, v, A.zr[k], q);
   st4(A.XP, c.cnt, n, v);
@@ -313,55 +351,44 @@ MTVD_HD inline void jump(const AC& c, const double* X, int i, int k, double d[4]
   for (int f = 0; f < 4; ++f) d[f] = X[f * c.cnt + m] - X[f * c.cnt + n];
 }
 
-// reverse 1: output -> X^C, X^P; plate outputs
-MTVD_HD inline void rv_out(const AC& c, const Arr& A, int i, int k) {
+// the output's cotangents at (i, k): the share of the input (plates that
+// copy or close), of X^C and of X^P
+MTVD_HD inline void out_cots(const AC& c, const Arr& A, int i, int k, double xb[4],
+                             double xcb[4], double xpb[4]) {
   long long n = nid(c, i, k);
-  double yb[4], z4[4] = {0, 0, 0, 0};
+  double yb[4];
   ld4(A.Yb, c.cnt, n, yb);
-  st4(A.Xb, c.cnt, n, z4);
-  st4(A.XCb, c.cnt, n, z4);
-  st4(A.XPb, c.cnt, n, z4);
+  for (int q = 0; q < 4; ++q) xb[q] = xcb[q] = xpb[q] = 0.0;
   if (c.axis == 0) {
     if (interior(c, k)) {
-      double h[4] = {0.5 * yb[0], 0.5 * yb[1], 0.5 * yb[2], 0.5 * yb[3]};
-      st4(A.XCb, c.cnt, n, h);
-      st4(A.XPb, c.cnt, n, h);
+      for (int q = 0; q < 4; ++q) xcb[q] = xpb[q] = 0.5 * yb[q];
     } else {
-      st4(A.Xb, c.cnt, n, yb);       // plate rows are copied through
+      for (int q = 0; q < 4; ++q) xb[q] = yb[q];    // plate rows are copied through
     }
     return;
   }
   if (k == 0) {                        // rho'_0 = rho_0 - lm m^P_z,1
-    A.Xb[n] = yb[0] + yb[3] * (c.cv * c.Tb + c.g * A.zr[0]);
+    xb[0] = yb[0] + yb[3] * (c.cv * c.Tb + c.g * A.zr[0]);
   } else if (k == c.M) {               // rho'_M = rho^P_M
-    A.XPb[n] = yb[0] + yb[3] * (c.cv * c.Tt + c.g * A.zr[c.M]);
+    xpb[0] = yb[0] + yb[3] * (c.cv * c.Tt + c.g * A.zr[c.M]);
   } else {
-    double h[4] = {0.5 * yb[0], 0.5 * yb[1], 0.5 * yb[2], 0.5 * yb[3]};
-    if (k == 1) {
+    for (int q = 0; q < 4; ++q) xcb[q] = xpb[q] = 0.5 * yb[q];
+    if (k == 1) {                      // X^P_1 carries the bottom closure's m^P_z,1
       long long n0 = nid(c, i, 0);
       double r0b = A.Yb[n0] + A.Yb[3 * c.cnt + n0] * (c.cv * c.Tb + c.g * A.zr[0]);
-      h[2] += -c.lm * r0b;
-      // h is the X^P cotangent; X^C gets the plain half
-      st4(A.XPb, c.cnt, n, h);
-      double g2[4] = {0.5 * yb[0], 0.5 * yb[1], 0.5 * yb[2], 0.5 * yb[3]};
-      st4(A.XCb, c.cnt, n, g2);
-    } else {
-      st4(A.XCb, c.cnt, n, h);
-      st4(A.XPb, c.cnt, n, h);
+      xpb[2] += -c.lm * r0b;
     }
   }
 }
 
-// reverse 2a: one TVD face: D = G dX with G from (dX_-, dX_0, dX_+, s_0, s_1)
-MTVD_HD inline void rv_face(const AC& c, const Arr& A, int i, int k) {
-  long long n = nid(c, i, k);
-  double z4[4] = {0, 0, 0, 0};
-  st4(A.FAm, c.cnt, n, z4);
-  st4(A.FA0, c.cnt, n, z4);
-  st4(A.FAp, c.cnt, n, z4);
-  A.SB0[n] = 0.0;
-  A.SB1[n] = 0.0;
+// the reverse of one TVD face (i, k)-(i, k)+1: the cotangents it sends to
+// its three jumps and to |u|+c of its two nodes (zero where there is no face)
+MTVD_HD inline void face_cot(const AC& c, const Arr& A, int i, int k, double dmb[4],
+                             double d0b[4], double dpb[4], double* s0b, double* s1b) {
+  for (int q = 0; q < 4; ++q) dmb[q] = d0b[q] = dpb[q] = 0.0;
+  *s0b = *s1b = 0.0;
   if (!has_D(c, i, k)) return;
+  long long n = nid(c, i, k);
   int im = c.axis == 0 ? i - 1 : i, km = c.axis == 0 ? k : k - 1;
   int ip = c.axis == 0 ? i + 1 : i, kp = c.axis == 0 ? k : k + 1;
   double dm[4], d0[4], dp[4];
@@ -374,60 +401,63 @@ MTVD_HD inline void rv_face(const AC& c, const Arr& A, int i, int k) {
   double Db[4];
   for (int q = 0; q < 4; ++q) Db[q] = A.Yb[q * c.cnt + n] - A.Yb[q * c.cnt + m1];
   double Gb = dot4(Db, d0);
-  double dmb[4] = {0, 0, 0, 0}, d0b[4], dpb[4] = {0, 0, 0, 0};
   for (int q = 0; q < 4; ++q) d0b[q] = f.G * Db[q];
-  double s0b = 0.0, s1b = 0.0;
-  face_vjp(c, f, dm, d0, dp, Gb, dmb, d0b, dpb, &s0b, &s1b);
-  st4(A.FAm, c.cnt, n, dmb);
-  st4(A.FA0, c.cnt, n, d0b);
-  st4(A.FAp, c.cnt, n, dpb);
-  A.SB0[n] = s0b;
-  A.SB1[n] = s1b;
+  face_vjp(c, f, dm, d0, dp, Gb, dmb, d0b, dpb, s0b, s1b);
 }
 
-// reverse 2b: jump cotangents -> X; |u|+c cotangent per node; X^C -> X,
-// and the corrector flux cotangent -> its inputs
-MTVD_HD inline void rv_tvd_corr(const AC& c, const Arr& A, int i, int k) {
+// reverse of the output, the TVD faces and the corrector: the jump
+// cotangents of the faces around (i, k) -> X; |u|+c cotangent of the node;
+// X^C -> X; the corrector flux cotangent -> its inputs
+MTVD_HD inline void rv_tc(const AC& c, const Arr& A, int i, int k) {
   long long n = nid(c, i, k);
   const bool lo_ok = c.axis == 0 || k >= 1;        // a face below exists
   const bool hi_ok = c.axis == 0 || k <= c.M - 1;  // a face above exists
-  long long nm = lo_ok ? along(c, i, k, -1) : n;
-  long long np = hi_ok ? along(c, i, k, 1) : n;
-  long long nmm = (c.axis == 0 || k >= 2) ? along(c, i, k, -2) : n;
-  // cotangent of dX of face n (between n, n+1) and of face n-1
-  double xb[4];
-  ld4(A.Xb, c.cnt, n, xb);
+  // faces (by lower node) n-2, n-1, n, n+1 along the axis
+  const int di = c.axis == 0 ? 1 : 0, dk = c.axis == 0 ? 0 : 1;
+  double am[4][4], a0[4][4], ap[4][4], s0[4], s1[4];   // index f+2 for face n+f
+  for (int f = -2; f <= 1; ++f) {
+    const int kk = k + f * dk;
+    if (c.axis == 2 && (kk < 0 || kk > c.M)) {
+      for (int q = 0; q < 4; ++q) am[f + 2][q] = a0[f + 2][q] = ap[f + 2][q] = 0.0;
+      s0[f + 2] = s1[f + 2] = 0.0;
+      continue;
+    }
+    face_cot(c, A, i + f * di, kk, am[f + 2], a0[f + 2], ap[f + 2], &s0[f + 2], &s1[f + 2]);
+  }
+  double xb[4], xcb[4], xpb[4];
+  out_cots(c, A, i, k, xb, xcb, xpb);
   for (int q = 0; q < 4; ++q) {
     double own = 0.0, below = 0.0;
     if (hi_ok) {
-      own = A.FA0[q * c.cnt + n];
-      if (c.axis == 0 || k + 1 <= c.M - 1) own += A.FAm[q * c.cnt + np];
-      if (lo_ok) own += A.FAp[q * c.cnt + nm];
+      own = a0[2][q];                                                // face n
+      if (c.axis == 0 || k + 1 <= c.M - 1) own += am[3][q];          // face n+1
+      if (lo_ok) own += ap[1][q];                                    // face n-1
     }
     if (lo_ok) {
-      below = A.FA0[q * c.cnt + nm];
-      below += A.FAm[q * c.cnt + n];
-      if (c.axis == 0 || k - 2 >= 0) below += A.FAp[q * c.cnt + nmm];
+      below = a0[1][q];                                              // face n-1
+      below += am[2][q];                                             // face n
+      if (c.axis == 0 || k - 2 >= 0) below += ap[0][q];              // face n-2
     }
     xb[q] += below - own;
   }
-  A.SB[n] = A.SB0[n] + (lo_ok ? A.SB1[nm] : 0.0);
+  A.SB[n] = s0[2] + (lo_ok ? s1[1] : 0.0);
   // X^C = X - lm (F^P_{n+1} - F^P_n) + tau S(X^P)
-  double xcb[4];
-  ld4(A.XCb, c.cnt, n, xcb);
   for (int q = 0; q < 4; ++q) xb[q] += xcb[q];
   st4(A.Xb, c.cnt, n, xb);
-  double xpb[4];
-  ld4(A.XPb, c.cnt, n, xpb);
   if (c.axis == 2 && interior(c, k)) xpb[0] += c.tau * (-c.g) * xcb[2];
   double qb[4] = {0, 0, 0, 0}, db[5] = {0, 0, 0, 0, 0};
   double mub = 0.0, Kb = 0.0;
   if (has_FP(c, i, k)) {
+    double xcbm[4] = {0, 0, 0, 0};
+    if (c.axis == 0 || k - 1 >= 1) {
+      double t0[4], t1[4];
+      if (c.axis == 0) out_cots(c, A, i - 1, k, t0, xcbm, t1);
+      else out_cots(c, A, i, k - 1, t0, xcbm, t1);
+    }
     double Fb[4];
     for (int q = 0; q < 4; ++q) {
-      double here = (c.axis == 0 || k <= c.M - 1) ? A.XCb[q * c.cnt + n] : 0.0;
-      double prev = (c.axis == 0 || k - 1 >= 1) ? A.XCb[q * c.cnt + nm] : 0.0;
-      Fb[q] = c.lm * (here - prev);
+      double here = (c.axis == 0 || k <= c.M - 1) ? xcb[q] : 0.0;
+      Fb[q] = c.lm * (here - xcbm[q]);
     }
     double x[4], p4[4], d[5];
     ld4(A.XP, c.cnt, n, x);
@@ -495,63 +525,74 @@ MTVD_HD inline void gather_prim(const AC& c, const double* D, bool (*hasf)(const
   }
 }
 
-// reverse 3: P^P cotangent (direct + gathered) -> X^P (or X on copied
-// plate rows, or the top plate's predicted density)
-MTVD_HD inline void rv_pp(const AC& c, const Arr& A, int i, int k) {
+// The P^P cotangent of (i, k) (direct + gathered from the corrector fluxes
+// that read it) taken back through the primitives.  Returns the kind of
+// result in v: 0 the final X^P cotangent (v = 0 where X^P and P^P are
+// constants, the bottom plate of L_z); 1 an addition to the X cotangent
+// (plate rows that a horizontal operator copies: X^P = X, P^P = P); 2 the
+// cotangent of the top plate's predicted density in v[0] (L_z, k = M).
+MTVD_HD inline int pp_back(const AC& c, const Arr& A, int i, int k, double v[4]) {
   long long n = nid(c, i, k);
   double qb[4];
   ld4(A.PPb, c.cnt, n, qb);
   gather_prim(c, A.DPb, has_FP, 0, i, k, qb);
+  for (int q = 0; q < 4; ++q) v[q] = 0.0;
   if (c.axis == 0 && !interior(c, k)) {
-    // plate rows: X^P = X, P^P = P
-    double xb[4];
-    ld4(A.Xb, c.cnt, n, xb);
     double x[4];
     ld4(A.X, c.cnt, n, x);
-    prim_vjp(c, x, A.zr[k], qb, xb);
-    st4(A.Xb, c.cnt, n, xb);
-    return;
+    prim_vjp(c, x, A.zr[k], qb, v);
+    return 1;
   }
-  if (c.axis == 2 && k == 0) return;     // X^P_0 and P^P_0 are constants here
-  double xpb[4];
-  ld4(A.XPb, c.cnt, n, xpb);
+  if (c.axis == 2 && k == 0) return 0;
+  ld4(A.XPb, c.cnt, n, v);
   if (c.axis == 2 && k == c.M) {
     // X^P_M = (r, 0, 0, r(cv Tt + g)), P^P_M = (0, 0, Tt, a r Tt)
-    A.RPb[i] = xpb[0] + xpb[3] * (c.cv * c.Tt + c.g * A.zr[c.M]) + qb[3] * c.a * c.Tt;
-    return;
+    double r = v[0] + v[3] * (c.cv * c.Tt + c.g * A.zr[c.M]) + qb[3] * c.a * c.Tt;
+    v[0] = r;
+    v[1] = v[2] = v[3] = 0.0;
+    return 2;
   }
   double x[4];
   ld4(A.XP, c.cnt, n, x);
-  prim_vjp(c, x, A.zr[k], qb, xpb);
-  st4(A.XPb, c.cnt, n, xpb);
+  prim_vjp(c, x, A.zr[k], qb, v);
+  return 0;
 }
 
-// reverse 4: X^P -> X and the predictor flux cotangent -> its inputs
+// reverse of the predictor: P^P and X^P cotangents of (i, k) and of the
+// node above along the axis (pp_back), X^P -> X, and the predictor flux
+// cotangent -> its inputs
 MTVD_HD inline void rv_pred(const AC& c, const Arr& A, int i, int k) {
   long long n = nid(c, i, k);
-  double xb[4];
+  double xb[4], v[4];
   ld4(A.Xb, c.cnt, n, xb);
+  const int kind = pp_back(c, A, i, k, v);
+  if (kind == 1)
+    for (int q = 0; q < 4; ++q) xb[q] += v[q];
   const bool in = interior(c, k);
   if (in) {
-    double xpb[4];
-    ld4(A.XPb, c.cnt, n, xpb);
-    for (int q = 0; q < 4; ++q) xb[q] += xpb[q];
-    if (c.axis == 2) xb[0] += c.tau * (-c.g) * xpb[2];
+    for (int q = 0; q < 4; ++q) xb[q] += v[q];
+    if (c.axis == 2) xb[0] += c.tau * (-c.g) * v[2];
   }
   if (c.axis == 2 && k == c.M) {           // r^P_M = rho_M - lm (m_z,M - m_z,M-1)
-    xb[0] += A.RPb[i];
-    xb[2] += -c.lm * A.RPb[i];
+    xb[0] += v[0];
+    xb[2] += -c.lm * v[0];
   }
-  if (c.axis == 2 && k == c.M - 1) xb[2] += c.lm * A.RPb[i];
+  if (c.axis == 2 && k == c.M - 1) {
+    double t[4];
+    pp_back(c, A, i, c.M, t);
+    xb[2] += c.lm * t[0];
+  }
   double qb[4] = {0, 0, 0, 0}, db[5] = {0, 0, 0, 0, 0};
   double mub = 0.0, Kb = 0.0;
   if (has_F(c, i, k)) {
-    long long np = along(c, i, k, 1);
+    double vu[4] = {0, 0, 0, 0};
+    if (c.axis == 0 || k + 1 <= c.M - 1) {
+      if (c.axis == 0) pp_back(c, A, i + 1, k, vu); else pp_back(c, A, i, k + 1, vu);
+    }
     double Fb[4];
     for (int q = 0; q < 4; ++q) {
-      double up = (c.axis == 0 || k + 1 <= c.M - 1) ? A.XPb[q * c.cnt + np] : 0.0;
-      double here = in ? A.XPb[q * c.cnt + n] : 0.0;
-      Fb[q] = c.lm * (up - here);
+      double here = in ? v[q] : 0.0;
+      Fb[q] = c.lm * (vu[q] - here);
     }
     double x[4], p4[4], d[5];
     ld4(A.X, c.cnt, n, x);

@@ -1,6 +1,6 @@
 // mtvd_adjoint.hip -- kernels of the reverse pass of a 2D time step with a
-// frozen dt: the stages of each directional operator's reverse (functions of
-// mtvd_adjoint.h, one kernel per stage), the objective (the mean plate
+// frozen dt: the four stages of each directional operator's reverse
+// (functions of mtvd_adjoint.h, one kernel per stage), the objective (the mean plate
 // Nusselt number, accumulated over steps), its cotangent, the initial state
 // from a temperature perturbation and the perturbation's cotangent.
 //
@@ -17,7 +17,7 @@ using adj::Arr;
 
 namespace {
 
-enum Stage { kFwPrim, kFwFlux, kFwPred, kRvOut, kRvFace, kRvTvdCorr, kRvPP, kRvPred, kRvPrim };
+enum Stage { kFwAll, kRvTc, kRvPred, kRvPrim };
 
 constexpr int kBlk = 256;
 constexpr int kObjBlk = 256;
@@ -30,13 +30,8 @@ __global__ __launch_bounds__(kBlk) void adj_stage(AC c, Arr A, const Shared* sh)
   c.lm = c.tau * c.iha;
   const int i = (int)(t % c.nx), k = (int)(t / c.nx);
   switch (ST) {
-    case kFwPrim: adj::fw_prim(c, A, i, k); break;
-    case kFwFlux: adj::fw_flux(c, A, i, k); break;
-    case kFwPred: adj::fw_pred(c, A, i, k); break;
-    case kRvOut: adj::rv_out(c, A, i, k); break;
-    case kRvFace: adj::rv_face(c, A, i, k); break;
-    case kRvTvdCorr: adj::rv_tvd_corr(c, A, i, k); break;
-    case kRvPP: adj::rv_pp(c, A, i, k); break;
+    case kFwAll: adj::fw_all(c, A, i, k); break;
+    case kRvTc: adj::rv_tc(c, A, i, k); break;
     case kRvPred: adj::rv_pred(c, A, i, k); break;
     default: adj::rv_prim(c, A, i, k); break;
   }
@@ -188,13 +183,8 @@ hipError_t launch_adj_sweep(int axis, const AC& c0, const Arr& A, const Shared* 
   c.axis = axis;
   c.iha = axis == 0 ? c.ihx : c.ihz;
   const unsigned g = blocks_for(c.cnt, kBlk);
-  adj_stage<kFwPrim><<<g, kBlk, 0, s>>>(c, A, sh);
-  adj_stage<kFwFlux><<<g, kBlk, 0, s>>>(c, A, sh);
-  adj_stage<kFwPred><<<g, kBlk, 0, s>>>(c, A, sh);
-  adj_stage<kRvOut><<<g, kBlk, 0, s>>>(c, A, sh);
-  adj_stage<kRvFace><<<g, kBlk, 0, s>>>(c, A, sh);
-  adj_stage<kRvTvdCorr><<<g, kBlk, 0, s>>>(c, A, sh);
-  adj_stage<kRvPP><<<g, kBlk, 0, s>>>(c, A, sh);
+  adj_stage<kFwAll><<<g, kBlk, 0, s>>>(c, A, sh);
+  adj_stage<kRvTc><<<g, kBlk, 0, s>>>(c, A, sh);
   adj_stage<kRvPred><<<g, kBlk, 0, s>>>(c, A, sh);
   adj_stage<kRvPrim><<<g, kBlk, 0, s>>>(c, A, sh);
   return hipGetLastError();

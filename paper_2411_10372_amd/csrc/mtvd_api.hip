@@ -1375,25 +1375,17 @@ size_t adj_layout(mtvd_adj* a, unsigned char* base) {
   for (int q = 0; q < 2; ++q) a->cot[q] = (double*)take(S);
   adj::Arr& A = a->A;
   A.P = (double*)take(S);
-  A.F = (double*)take(S);
   A.XP = (double*)take(S);
   A.PP = (double*)take(S);
-  A.XCb = (double*)take(S);
   A.XPb = (double*)take(S);
   A.PPb = (double*)take(S);
   A.PB = (double*)take(S);
-  A.FAm = (double*)take(S);
-  A.FA0 = (double*)take(S);
-  A.FAp = (double*)take(S);
   A.DPb = (double*)take(5 * one);
   A.DB = (double*)take(5 * one);
   A.S = (double*)take(one);
-  A.SB0 = (double*)take(one);
-  A.SB1 = (double*)take(one);
   A.SB = (double*)take(one);
   A.MU = (double*)take(one);
   A.KB = (double*)take(one);
-  A.RPb = (double*)take(sizeof(double) * a->c.nx);
   A.zr = a->zr;
   return off;
 }
