@@ -9,9 +9,9 @@
 // stay in registers in rings of period 4 (the march is unrolled by 4 so
 // every ring index is a compile-time constant); values along x move between
 // neighbouring lanes with DPP wave shifts.  Rows are prefetched two
-// iterations ahead so a wave's loads overlap its own arithmetic.  Each sweep
-// reads and writes the state once: 4 fields x 8 B in, 4 x 8 B out per node,
-// plus halo re-reads that hit in L2.
+// iterations ahead, with their heights z_k, so a wave's loads overlap its own
+// arithmetic.  Each sweep reads and writes the state once: 4 fields x 8 B in,
+// 4 x 8 B out per node, plus halo re-reads that hit in L2.
 #include "mtvd_device.h"
 #include "mtvd_launch.h"
 
@@ -104,7 +104,10 @@ __device__ __forceinline__ void out_max(const Coef& c, const N2& o, double z, do
 
 struct Z2 {
   N2 pf[2];     // prefetched rows f+1, f+2, slot row & 1
+  double pz[2]; // their heights z_k, prefetched with them (a height loaded
+                // on use would make the wave wait for every load in flight)
   N2 x[4];      // X^n rows f-3..f, slot row & 3
+  double zz[4]; // their heights
   P2 pn[4];     // primitives of X^n (p filled on use)
   double s[4];  // |u_z| + c of X^n
   double G[2];  // TVD coefficient of face row+1/2
@@ -127,15 +130,23 @@ struct ZS {
   static constexpr int e0 = S & 1, e1 = (S + 1) & 1;
 };
 
-// A: row f (prefetched) and its primitives; prefetch row f+2 when `pre`
+// A: row f (prefetched) and its primitives; prefetch row f+2 (`pre`, else
+//    the top row again)
 template <int S>
 __device__ __forceinline__ void z2_load(const Coef& c, Z2& st, int f, bool pre, const Cols& L,
                                         const double* __restrict__ zr,
                                         const double* __restrict__ X) {
   using Z = ZS<S>;
   st.x[Z::c0] = st.pf[Z::e0];
-  if (pre) st.pf[Z::e0] = load2(c, X, f + 2, L.col);
-  st.pn[Z::c0] = prim2(c, st.x[Z::c0], zr[f]);
+  st.zz[Z::c0] = st.pz[Z::e0];
+  {
+    // always prefetch (the row index clamped to the top plate), so the ring
+    // registers carry no conditional merge
+    const int fp = pre ? f + 2 : c.M;
+    st.pf[Z::e0] = load2(c, X, fp, L.col);
+    st.pz[Z::e0] = zr[fp];
+  }
+  st.pn[Z::c0] = prim2(c, st.x[Z::c0], st.zz[Z::c0]);
   st.s[Z::c0] = fabs(st.pn[Z::c0].uz) + sound(c, st.pn[Z::c0].T);
 }
 
@@ -218,8 +229,7 @@ __device__ __forceinline__ double z2_tvd(const Coef& c, const Z2& st, double lz)
 //    o+1/2 term G dX is carried to the next row as its o-1/2 term
 template <int S, bool FUSE>
 __device__ __forceinline__ void z2_out(const Coef& c, Z2& st, bool emit, int o, const Cols& L,
-                                       const double* __restrict__ zr, double* __restrict__ Y,
-                                       double tau, double lz) {
+                                       double* __restrict__ Y, double tau, double lz) {
   using Z = ZS<S>;
   N2 d0 = st.x[Z::c2] - st.x[Z::c3];
   double G = st.G[Z::e1];
@@ -237,7 +247,7 @@ __device__ __forceinline__ void z2_out(const Coef& c, Z2& st, bool emit, int o, 
     out.mx = 0.5 * (xp.mx + xc.mx) + (Dc.mx - Dm.mx);
     out.mz = 0.5 * (xp.mz + xc.mz) + (Dc.mz - Dm.mz);
     out.E = 0.5 * (xp.E + xc.E) + (Dc.E - Dm.E);
-    if (FUSE) out_max(c, out, zr[o], st.mx, st.mz, st.bad, L.out);
+    if (FUSE) out_max(c, out, st.zz[Z::c3], st.mx, st.mz, st.bad, L.out);
     if (L.out) store2(c, Y, o, L.col, out);
   }
   st.Dp = Dc;
@@ -261,14 +271,14 @@ __device__ __forceinline__ void z2_iter(const Coef& c, Z2& st, int f, int fs, in
   if (r >= k0 - 1 && r >= 0 && r <= M) {
     if (r == 0) {
       double rho = st.x[Z::c2].r;
-      st.xp[Z::c2] = N2{rho, 0.0, 0.0, rho * (c.cv * c.Tb + c.g * zr[0])};
+      st.xp[Z::c2] = N2{rho, 0.0, 0.0, rho * (c.cv * c.Tb + c.g * st.zz[Z::c2])};
       st.pp[Z::c2] = P2{0.0, 0.0, c.Tb, c.a * rho * c.Tb};
     } else if (r == M) {
       double rho = st.x[Z::c2].r - lz * (st.x[Z::c2].mz - st.x[Z::c3].mz);
-      st.xp[Z::c2] = N2{rho, 0.0, 0.0, rho * (c.cv * c.Tt + c.g * zr[M])};
+      st.xp[Z::c2] = N2{rho, 0.0, 0.0, rho * (c.cv * c.Tt + c.g * st.zz[Z::c2])};
       st.pp[Z::c2] = P2{0.0, 0.0, c.Tt, c.a * rho * c.Tt};
     } else {
-      z2_pred<S>(c, st, zr[r], tau, lz);
+      z2_pred<S>(c, st, st.zz[Z::c2], tau, lz);
     }
   }
   if (r >= k0 && r >= 1 && r <= M) z2_cflux<S>(c, st, r == M && c.wall_order == 2);
@@ -277,17 +287,17 @@ __device__ __forceinline__ void z2_iter(const Coef& c, Z2& st, int f, int fs, in
     st.G[Z::e0] = (c.tvd_on && r >= 1 && r <= M - 2) ? z2_tvd<S>(c, st, lz) : 0.0;
   const int o = f - 3;
   if (o >= k0 - 1 && o >= 0 && o < k1 && o <= M - 1)
-    z2_out<S, FUSE>(c, st, o >= k0 && o >= 1, o, L, zr, Y, tau, lz);
+    z2_out<S, FUSE>(c, st, o >= k0 && o >= 1, o, L, Y, tau, lz);
   if (o >= k0 && o < k1 && (o == 0 || o == M)) {
     N2 out;
     if (o == 0) {
       double rho = st.x[Z::c3].r - lz * (st.xp[Z::c2].mz - 0.0);
-      out = N2{rho, 0.0, 0.0, rho * (c.cv * c.Tb + c.g * zr[0])};
+      out = N2{rho, 0.0, 0.0, rho * (c.cv * c.Tb + c.g * st.zz[Z::c3])};
     } else {
       double rho = st.xp[Z::c3].r;
-      out = N2{rho, 0.0, 0.0, rho * (c.cv * c.Tt + c.g * zr[M])};
+      out = N2{rho, 0.0, 0.0, rho * (c.cv * c.Tt + c.g * st.zz[Z::c3])};
     }
-    if (FUSE) out_max(c, out, zr[o], st.mx, st.mz, st.bad, L.out);
+    if (FUSE) out_max(c, out, st.zz[Z::c3], st.mx, st.mz, st.bad, L.out);
     if (L.out) store2(c, Y, o, L.col, out);
   }
 }
@@ -315,12 +325,17 @@ __device__ __forceinline__ void z2_wave(const Coef& c, Shared* sh, const double*
   {
     N2 a = load2(c, X, fs, L.col);
     N2 b = (fs + 1 <= c.M) ? load2(c, X, fs + 1, L.col) : a;
+    double za = zr[fs], zb = (fs + 1 <= c.M) ? zr[fs + 1] : za;
     if (fs & 1) {
       st.pf[1] = a;
       st.pf[0] = b;
+      st.pz[1] = za;
+      st.pz[0] = zb;
     } else {
       st.pf[0] = a;
       st.pf[1] = b;
+      st.pz[0] = za;
+      st.pz[1] = zb;
     }
   }
   for (int fb = fs & ~3; fb <= fe; fb += 4) {
@@ -352,8 +367,10 @@ __global__ __launch_bounds__(256) void sweep_z2d(Coef c, Shared* sh, const doubl
 // march.  Plate rows are copied through.
 
 struct X2 {
-  N2 pf[2];
+  N2 pf[2];      // as in Z2
+  double pz[2];
   N2 x[4];
+  double zz[4];
   P2 pn[4];      // p filled on use
   N2 xp[4];
   P2 pp[4];
@@ -368,8 +385,15 @@ __device__ __forceinline__ void x2_load(const Coef& c, X2& st, int f, bool pre, 
                                         const double* __restrict__ X) {
   using Z = ZS<S>;
   st.x[Z::c0] = st.pf[Z::e0];
-  if (pre) st.pf[Z::e0] = load2(c, X, f + 2, L.col);
-  st.pn[Z::c0] = prim2(c, st.x[Z::c0], zr[f]);
+  st.zz[Z::c0] = st.pz[Z::e0];
+  {
+    // always prefetch (the row index clamped to the top plate), so the ring
+    // registers carry no conditional merge
+    const int fp = pre ? f + 2 : c.M;
+    st.pf[Z::e0] = load2(c, X, fp, L.col);
+    st.pz[Z::e0] = zr[fp];
+  }
+  st.pn[Z::c0] = prim2(c, st.x[Z::c0], st.zz[Z::c0]);
 }
 
 // predictor on interior row f-1: X^P_i = X_i - (tau/dx)(F_i - F_{i-1})
@@ -445,13 +469,13 @@ __device__ __forceinline__ void x2_iter(const Coef& c, X2& st, int f, int fs, in
       st.xp[Z::c1] = st.x[Z::c1];
       st.pp[Z::c1] = st.pn[Z::c1];
     } else {
-      x2_pred<S>(c, st, zr[r1], lx);
+      x2_pred<S>(c, st, st.zz[Z::c1], lx);
     }
   }
   const int r = f - 2;
   if (r >= k0 && r < k1) {
     N2 out = (r == 0 || r == M) ? st.x[Z::c2] : x2_corr<S>(c, st, lx);
-    if (FUSE) out_max(c, out, zr[r], st.mx, st.mz, st.bad, L.out);
+    if (FUSE) out_max(c, out, st.zz[Z::c2], st.mx, st.mz, st.bad, L.out);
     if (L.out) store2(c, Y, r, L.col, out);
   }
 }
@@ -477,12 +501,17 @@ __device__ __forceinline__ void x2_wave(const Coef& c, Shared* sh, const double*
   {
     N2 a = load2(c, X, fs, L.col);
     N2 b = (fs + 1 <= c.M) ? load2(c, X, fs + 1, L.col) : a;
+    double za = zr[fs], zb = (fs + 1 <= c.M) ? zr[fs + 1] : za;
     if (fs & 1) {
       st.pf[1] = a;
       st.pf[0] = b;
+      st.pz[1] = za;
+      st.pz[0] = zb;
     } else {
       st.pf[0] = a;
       st.pf[1] = b;
+      st.pz[0] = za;
+      st.pz[1] = zb;
     }
   }
   for (int fb = fs & ~3; fb <= fe; fb += 4) {
