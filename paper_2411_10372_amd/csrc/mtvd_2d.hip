@@ -130,22 +130,22 @@ struct ZS {
   static constexpr int e0 = S & 1, e1 = (S + 1) & 1;
 };
 
-// A: row f (prefetched) and its primitives; prefetch row f+2 (`pre`, else
-//    the top row again)
+// A: row f (prefetched two steps ago) and its primitives; prefetch row f+2.
+//    Every step of the march runs this head, whether or not it computes:
+//    the row index is clamped into [0, M], and no guard surrounds the
+//    loads, because a guarded load has to be copied into the loop-carried
+//    ring registers at the guard's end and the copy waits for the load.
+//    Rows outside [first row, M] land in ring slots no stage reads.
 template <int S>
-__device__ __forceinline__ void z2_load(const Coef& c, Z2& st, int f, bool pre, const Cols& L,
+__device__ __forceinline__ void z2_load(const Coef& c, Z2& st, int f, const Cols& L,
                                         const double* __restrict__ zr,
                                         const double* __restrict__ X) {
   using Z = ZS<S>;
   st.x[Z::c0] = st.pf[Z::e0];
   st.zz[Z::c0] = st.pz[Z::e0];
-  {
-    // always prefetch (the row index clamped to the top plate), so the ring
-    // registers carry no conditional merge
-    const int fp = pre ? f + 2 : c.M;
-    st.pf[Z::e0] = load2(c, X, fp, L.col);
-    st.pz[Z::e0] = zr[fp];
-  }
+  const int fp = min(max(f + 2, 0), c.M);
+  st.pf[Z::e0] = load2(c, X, fp, L.col);
+  st.pz[Z::e0] = zr[fp];
   st.pn[Z::c0] = prim2(c, st.x[Z::c0], st.zz[Z::c0]);
   st.s[Z::c0] = fabs(st.pn[Z::c0].uz) + sound(c, st.pn[Z::c0].T);
 }
@@ -261,9 +261,9 @@ __device__ __forceinline__ void z2_iter(const Coef& c, Z2& st, int f, int fs, in
                                         const double* __restrict__ X,
                                         double* __restrict__ Y, double tau, double lz) {
   using Z = ZS<S>;
+  z2_load<S>(c, st, f, L, zr, X);
   if (f < fs || f > fe) return;
   const int M = c.M;
-  if (f <= M) z2_load<S>(c, st, f, f + 2 <= M, L, zr, X);
   const int r = f - 2;
   if (r >= k0 - 2 && r >= 0 && r <= M - 1) z2_pflux<S>(c, st, r == 0 && c.wall_order == 2);
   // C: plates: u = 0, T = T_plate, top density from the backward mass-flux
@@ -320,25 +320,11 @@ __device__ __forceinline__ void z2_wave(const Coef& c, Shared* sh, const double*
   st.Dp = N2{0.0, 0.0, 0.0, 0.0};
   const int fs = max(0, k0 - 2);
   const int fe = k1 + 2;
-  // prologue: rows fs and fs+1 into their prefetch slots (slot = row & 1,
-  // written with constant indices so the ring stays in registers)
-  {
-    N2 a = load2(c, X, fs, L.col);
-    N2 b = (fs + 1 <= c.M) ? load2(c, X, fs + 1, L.col) : a;
-    double za = zr[fs], zb = (fs + 1 <= c.M) ? zr[fs + 1] : za;
-    if (fs & 1) {
-      st.pf[1] = a;
-      st.pf[0] = b;
-      st.pz[1] = za;
-      st.pz[0] = zb;
-    } else {
-      st.pf[0] = a;
-      st.pf[1] = b;
-      st.pz[0] = za;
-      st.pz[1] = zb;
-    }
-  }
-  for (int fb = fs & ~3; fb <= fe; fb += 4) {
+  // the steps fs-2 and fs-1 only load rows fs and fs+1 (their heads); the
+  // heads before them copy this defined, unused row
+  st.pf[0] = st.pf[1] = N2{1.0, 0.0, 0.0, 1.0};
+  st.pz[0] = st.pz[1] = 0.0;
+  for (int fb = (fs - 2) & ~3; fb <= fe; fb += 4) {
     z2_iter<0, FUSE>(c, st, fb + 0, fs, fe, k0, k1, L, zr, X, Y, tau, lz);
     z2_iter<1, FUSE>(c, st, fb + 1, fs, fe, k0, k1, L, zr, X, Y, tau, lz);
     z2_iter<2, FUSE>(c, st, fb + 2, fs, fe, k0, k1, L, zr, X, Y, tau, lz);
@@ -379,20 +365,17 @@ struct X2 {
 };
 
 // The stages of one march step f of L_x (ring slots as for L_z).
+// the head of every step, as z2_load
 template <int S>
-__device__ __forceinline__ void x2_load(const Coef& c, X2& st, int f, bool pre, const Cols& L,
+__device__ __forceinline__ void x2_load(const Coef& c, X2& st, int f, const Cols& L,
                                         const double* __restrict__ zr,
                                         const double* __restrict__ X) {
   using Z = ZS<S>;
   st.x[Z::c0] = st.pf[Z::e0];
   st.zz[Z::c0] = st.pz[Z::e0];
-  {
-    // always prefetch (the row index clamped to the top plate), so the ring
-    // registers carry no conditional merge
-    const int fp = pre ? f + 2 : c.M;
-    st.pf[Z::e0] = load2(c, X, fp, L.col);
-    st.pz[Z::e0] = zr[fp];
-  }
+  const int fp = min(max(f + 2, 0), c.M);
+  st.pf[Z::e0] = load2(c, X, fp, L.col);
+  st.pz[Z::e0] = zr[fp];
   st.pn[Z::c0] = prim2(c, st.x[Z::c0], st.zz[Z::c0]);
 }
 
@@ -460,9 +443,9 @@ __device__ __forceinline__ void x2_iter(const Coef& c, X2& st, int f, int fs, in
                                         const double* __restrict__ X,
                                         double* __restrict__ Y, double lx) {
   using Z = ZS<S>;
+  x2_load<S>(c, st, f, L, zr, X);
   if (f < fs || f > fe) return;
   const int M = c.M;
-  if (f <= M) x2_load<S>(c, st, f, f + 2 <= M, L, zr, X);
   const int r1 = f - 1;
   if (r1 >= k0 - 1 && r1 >= 0 && r1 <= M) {
     if (r1 == 0 || r1 == M) {
@@ -496,25 +479,11 @@ __device__ __forceinline__ void x2_wave(const Coef& c, Shared* sh, const double*
   st.bad = false;
   const int fs = max(0, k0 - 2);
   const int fe = k1 + 1;
-  // prologue: rows fs and fs+1 into their prefetch slots (slot = row & 1,
-  // written with constant indices so the ring stays in registers)
-  {
-    N2 a = load2(c, X, fs, L.col);
-    N2 b = (fs + 1 <= c.M) ? load2(c, X, fs + 1, L.col) : a;
-    double za = zr[fs], zb = (fs + 1 <= c.M) ? zr[fs + 1] : za;
-    if (fs & 1) {
-      st.pf[1] = a;
-      st.pf[0] = b;
-      st.pz[1] = za;
-      st.pz[0] = zb;
-    } else {
-      st.pf[0] = a;
-      st.pf[1] = b;
-      st.pz[0] = za;
-      st.pz[1] = zb;
-    }
-  }
-  for (int fb = fs & ~3; fb <= fe; fb += 4) {
+  // the steps fs-2 and fs-1 only load rows fs and fs+1 (their heads); the
+  // heads before them copy this defined, unused row
+  st.pf[0] = st.pf[1] = N2{1.0, 0.0, 0.0, 1.0};
+  st.pz[0] = st.pz[1] = 0.0;
+  for (int fb = (fs - 2) & ~3; fb <= fe; fb += 4) {
     x2_iter<0, FUSE>(c, st, fb + 0, fs, fe, k0, k1, L, zr, X, Y, lx);
     x2_iter<1, FUSE>(c, st, fb + 1, fs, fe, k0, k1, L, zr, X, Y, lx);
     x2_iter<2, FUSE>(c, st, fb + 2, fs, fe, k0, k1, L, zr, X, Y, lx);
@@ -589,7 +558,9 @@ int wave_slots_2d(int axis, bool fuse) {
   else
     fn = fuse ? (const void*)sweep_x2d<true> : (const void*)sweep_x2d<false>;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, 0) != hipSuccess) return 0;
-  return nb * 4 * cus;
+  // at most two waves per SIMD (two 4-wave blocks per CU): where a third
+  // fits, longer marches for two still measured faster (fewer halo rows)
+  return min(nb, 2) * 4 * cus;
 }
 
 hipError_t launch_batch_2d(int axis, const BoxDesc* boxes, const int4* items, int nitems,

@@ -13,8 +13,8 @@ hipError_t launch_sweep_2d(int axis, const Coef& c, Shared* sh, const double* zr
                            int first, bool fuse, const double* X, double* Y, int kc,
                            hipStream_t s);
 int strips_2d(int nx);
-// waves of the 2D sweep kernel of `axis` that the device runs at once (0 if
-// the runtime cannot say)
+// waves of the 2D sweep kernel of `axis` to fill the device with: those it
+// keeps resident at once, at most two per SIMD (0 if the runtime cannot say)
 int wave_slots_2d(int axis, bool fuse);
 
 // all boxes of a batch, one directional operator (2D), one launch
