@@ -186,7 +186,9 @@ __device__ __forceinline__ void head3(Shared* sh, int slot, int first, double dt
 
 struct MF {
   N3 pf[2];                // prefetched rows f+1, f+2 (slot row & 1)
+  double pz[2];            // their heights (L_z), prefetched with them
   N3 x[4];                 // X^n rows f-3..f (slot row & 3)
+  double zz[4];            // their heights (L_z)
   P3 pn[4];                // primitives of X^n (p filled on use)
   double s[4];             // |u_AX| + c of X^n
   double bb[4], bm[4];     // d_B u_B and d_B u_AX of X^n (across waves)
@@ -207,8 +209,7 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
                                         double (&xa)[2][kNW][64], double (&xb)[2][kNW][64],
                                         const double* __restrict__ zr,
                                         const double* __restrict__ X, double* __restrict__ Y,
-                                        double tau, double lm) {
-  if (f < fs || f > fe) return;
+                                        double tau, double lm, int bload, double zb) {
   constexpr int B = (AX == 2) ? 1 : 2;   // axis of the waves
   const int M = c.M;
   const double ihm = (AX == 2) ? c.ihz : c.ihy;
@@ -221,21 +222,29 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
     if (AX == 2) return ((long long)row * c.ny + bidx) * c.nx + L.col;
     return ((long long)bidx * c.ny + wrap(row, c.ny)) * c.nx + L.col;
   };
-  auto zof = [&](int row) -> double { return (AX == 2) ? zr[row] : zr[bidx]; };
-
-  // A: row f of X^n (prefetched), its primitives; prefetch row f+2;
-  //    exchange across waves
-  const bool have_f = (AX == 2) ? (f <= M) : true;
-  if (have_f) {
-    if (bval) {
-      st.x[c0] = st.pf[e0];
-      if (AX == 1 || f + 2 <= M) st.pf[e0] = load3(c, X, node(f + 2));
-      st.pn[c0] = prim3(c, st.x[c0], zof(f));
-      st.s[c0] = fabs(st.pn[c0].u[AX]) + sound(c, st.pn[c0].T);
-    }
+  // A (every step of the march, guarded by nothing): row f of X^n
+  //    (prefetched two steps ago) and its primitives; prefetch row f+2 with
+  //    its height; exchange across waves.  A guarded load would have to be
+  //    copied into the loop-carried ring at the guard's end, and the copy
+  //    waits for the load.  Row (L_z) and plane (waves outside the plates of
+  //    L_y) indices are clamped into the grid; what such loads bring lands in
+  //    ring slots no stage reads, and their exchanged values are zeroed.
+  {
+    st.x[c0] = st.pf[e0];
+    st.zz[c0] = st.pz[e0];
+    const int fp = (AX == 2) ? min(max(f + 2, 0), M) : f + 2;
+    const long long np = (AX == 2) ? ((long long)fp * c.ny + bidx) * c.nx + L.col
+                                   : ((long long)bload * c.ny + wrap(fp, c.ny)) * c.nx + L.col;
+    st.pf[e0] = load3(c, X, np);
+    st.pz[e0] = (AX == 2) ? zr[fp] : zb;
+    st.pn[c0] = prim3(c, st.x[c0], (AX == 2) ? st.zz[c0] : zb);
+    st.s[c0] = fabs(st.pn[c0].u[AX]) + sound(c, st.pn[c0].T);
     double ub = bval ? st.pn[c0].u[B] : 0.0, um = bval ? st.pn[c0].u[AX] : 0.0;
     exchange(xa, w, lane, ub, um, ihb2, st.bb[c0], st.bm[c0]);
   }
+  if (f < fs || f > fe) return;
+  // heights of rows f-2 and f-3 (L_z) or of the wave's plane (L_y)
+  const double z_r = (AX == 2) ? st.zz[c2] : zb, z_o = (AX == 2) ? st.zz[c3] : zb;
   const int r = f - 2;
   const bool rin_F = (AX == 2) ? (r >= 0 && r <= M - 1) : true;
   // B: predictor flux F_r (inner derivatives forward along the march)
@@ -272,11 +281,11 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
         st.pp[c2].p = c.a * st.x[c2].r * st.pn[c2].T;
       } else if (AX == 2 && r == 0) {
         double rho = st.x[c2].r;
-        st.xp[c2] = N3{rho, {0.0, 0.0, 0.0}, rho * (c.cv * c.Tb + c.g * zr[0])};
+        st.xp[c2] = N3{rho, {0.0, 0.0, 0.0}, rho * (c.cv * c.Tb + c.g * z_r)};
         st.pp[c2] = P3{{0.0, 0.0, 0.0}, c.Tb, c.a * rho * c.Tb};
       } else if (AX == 2 && r == M) {
         double rho = st.x[c2].r - lm * (st.x[c2].m[2] - st.x[c3].m[2]);
-        st.xp[c2] = N3{rho, {0.0, 0.0, 0.0}, rho * (c.cv * c.Tt + c.g * zr[M])};
+        st.xp[c2] = N3{rho, {0.0, 0.0, 0.0}, rho * (c.cv * c.Tt + c.g * z_r)};
         st.pp[c2] = P3{{0.0, 0.0, 0.0}, c.Tt, c.a * rho * c.Tt};
       } else {
         const N3& Fa = st.F[e0];
@@ -289,7 +298,7 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
         v.E = x0.E - lm * (Fa.E - Fb.E);
         if (AX == 2) v.m[2] = v.m[2] + tau * (-c.g * x0.r);
         st.xp[c2] = v;
-        st.pp[c2] = prim3(c, v, zof(r));
+        st.pp[c2] = prim3(c, v, z_r);
       }
     }
     double ub = (role >= 1 && bval) ? st.pp[c2].u[B] : 0.0;
@@ -359,7 +368,7 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
 #pragma unroll
       for (int g = 0; g < 3; ++g) out.m[g] = 0.5 * (xp.m[g] + xc.m[g]) + (Dc.m[g] - Dm.m[g]);
       out.E = 0.5 * (xp.E + xc.E) + (Dc.E - Dm.E);
-      if (FUSE) acc_out(c, out, zof(o), st.acc, L.out);
+      if (FUSE) acc_out(c, out, z_o, st.acc, L.out);
       if (L.out) store3(c, Y, node(o), out);
     }
     st.Dp = Dc;
@@ -370,12 +379,12 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
       out = st.x[c3];
     } else if (o == 0) {
       double rho = st.x[c3].r - lm * (st.xp[c2].m[2] - 0.0);
-      out = N3{rho, {0.0, 0.0, 0.0}, rho * (c.cv * c.Tb + c.g * zr[0])};
+      out = N3{rho, {0.0, 0.0, 0.0}, rho * (c.cv * c.Tb + c.g * z_o)};
     } else {
       double rho = st.xp[c3].r;
-      out = N3{rho, {0.0, 0.0, 0.0}, rho * (c.cv * c.Tt + c.g * zr[M])};
+      out = N3{rho, {0.0, 0.0, 0.0}, rho * (c.cv * c.Tt + c.g * z_o)};
     }
-    if (FUSE) acc_out(c, out, zof(o), st.acc, L.out);
+    if (FUSE) acc_out(c, out, z_o, st.acc, L.out);
     if (L.out) store3(c, Y, node(o), out);
   }
 }
@@ -424,26 +433,19 @@ __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const
   st.Dp = N3{0.0, {0.0, 0.0, 0.0}, 0.0};
   const int fs = (AX == 2) ? max(0, m0 - 2) : m0 - 2;
   const int fe = m1 + 2;
-  if (bval) {
-    auto node0 = [&](int row) -> long long {
-      if (AX == 2) return ((long long)row * c.ny + bidx) * c.nx + L.col;
-      return ((long long)bidx * c.ny + wrap(row, c.ny)) * c.nx + L.col;
-    };
-    N3 a = load3(c, X, node0(fs));
-    N3 b = (AX == 1 || fs + 1 <= c.M) ? load3(c, X, node0(fs + 1)) : a;
-    if (fs & 1) {
-      st.pf[1] = a;
-      st.pf[0] = b;
-    } else {
-      st.pf[0] = a;
-      st.pf[1] = b;
-    }
-  }
-  for (int fb = fs & ~3; fb <= fe; fb += 4) {
-    mf_iter<AX, 0, FUSE>(c, st, fb + 0, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm);
-    mf_iter<AX, 1, FUSE>(c, st, fb + 1, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm);
-    mf_iter<AX, 2, FUSE>(c, st, fb + 2, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm);
-    mf_iter<AX, 3, FUSE>(c, st, fb + 3, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm);
+  // the plane this wave loads from (L_y: clamped into the plates) and its
+  // height
+  const int bload = (AX == 1) ? min(max(bidx, 0), c.M) : bidx;
+  const double zb = (AX == 1) ? zr[bload] : 0.0;
+  // the steps fs-2 and fs-1 only load rows fs and fs+1 (their heads); the
+  // heads before them copy this defined, unused row
+  st.pf[0] = st.pf[1] = N3{1.0, {0.0, 0.0, 0.0}, 1.0};
+  st.pz[0] = st.pz[1] = 0.0;
+  for (int fb = (fs - 2) & ~3; fb <= fe; fb += 4) {
+    mf_iter<AX, 0, FUSE>(c, st, fb + 0, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, bload, zb);
+    mf_iter<AX, 1, FUSE>(c, st, fb + 1, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, bload, zb);
+    mf_iter<AX, 2, FUSE>(c, st, fb + 2, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, bload, zb);
+    mf_iter<AX, 3, FUSE>(c, st, fb + 3, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, bload, zb);
   }
   if (FUSE) fold3(sh, slot, st.acc);
 }
@@ -453,7 +455,9 @@ __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const
 
 struct LF {
   N3 pf[2];                // prefetched rows f+1, f+2
+  double pz[2];            // their heights
   N3 x[4];
+  double zz[4];
   P3 pn[4];
   double s[4];             // |u_x| + c of X^n
   double yx[4], yy[4];     // d_y u_x, d_y u_y of X^n
@@ -471,7 +475,6 @@ __device__ __forceinline__ void lf_iter(const Coef& c, LF& st, int f, int fs, in
                                         const double* __restrict__ zr,
                                         const double* __restrict__ X, double* __restrict__ Y,
                                         double lx) {
-  if (f < fs || f > fe) return;
   const int M = c.M;
   constexpr int c0 = S & 3, c1 = (S + 3) & 3, c2 = (S + 2) & 3, c3 = (S + 1) & 3;
   const int role = (w == 0 || w == kNW - 1) ? 0 : ((w == 1 || w == kNW - 2) ? 1 : 2);
@@ -479,13 +482,18 @@ __device__ __forceinline__ void lf_iter(const Coef& c, LF& st, int f, int fs, in
   auto node = [&](int k) -> long long { return ((long long)k * c.ny + j) * c.nx + L.col; };
 
   constexpr int e0 = S & 1;
-  if (f <= M) {
+  // every step, guarded by nothing (as in the march kernels of L_z, L_y)
+  {
     st.x[c0] = st.pf[e0];
-    if (f + 2 <= M) st.pf[e0] = load3(c, X, node(f + 2));
-    st.pn[c0] = prim3(c, st.x[c0], zr[f]);
+    st.zz[c0] = st.pz[e0];
+    const int fp = min(max(f + 2, 0), M);
+    st.pf[e0] = load3(c, X, node(fp));
+    st.pz[e0] = zr[fp];
+    st.pn[c0] = prim3(c, st.x[c0], st.zz[c0]);
     st.s[c0] = fabs(st.pn[c0].u[0]) + sound(c, st.pn[c0].T);
     exchange(xa, w, lane, st.pn[c0].u[0], st.pn[c0].u[1], ihy2, st.yx[c0], st.yy[c0]);
   }
+  if (f < fs || f > fe) return;
   // predictor on row f-1
   const int r1 = f - 1;
   if (r1 >= k0 - 1 && r1 >= 0 && r1 <= M) {
@@ -513,7 +521,7 @@ __device__ __forceinline__ void lf_iter(const Coef& c, LF& st, int f, int fs, in
         for (int g = 0; g < 3; ++g) v.m[g] = x0.m[g] - lx * (Fi.m[g] - Fm.m[g]);
         v.E = x0.E - lx * (Fi.E - Fm.E);
         st.xp[c1] = v;
-        st.pp[c1] = prim3(c, v, zr[r1]);
+        st.pp[c1] = prim3(c, v, st.zz[c1]);
       }
     }
     double a = (role >= 1) ? st.pp[c1].u[0] : 0.0;
@@ -560,7 +568,7 @@ __device__ __forceinline__ void lf_iter(const Coef& c, LF& st, int f, int fs, in
       for (int g = 0; g < 3; ++g) out.m[g] = 0.5 * (xp.m[g] + xc.m[g]) + (D.m[g] - Dm.m[g]);
       out.E = 0.5 * (xp.E + xc.E) + (D.E - Dm.E);
     }
-    if (FUSE) acc_out(c, out, zr[r], st.acc, L.out);
+    if (FUSE) acc_out(c, out, st.zz[c2], st.acc, L.out);
     if (L.out) store3(c, Y, node(r), out);
   }
 }
@@ -594,19 +602,9 @@ __global__ __launch_bounds__(64 * kNW) void sweep_lf3d(Coef c, Shared* sh, const
   st.acc.bad = false;
   const int fs = max(0, k0 - 2);
   const int fe = k1 + 1;
-  {
-    auto node0 = [&](int k) -> long long { return ((long long)k * c.ny + j) * c.nx + L.col; };
-    N3 a = load3(c, X, node0(fs));
-    N3 b = (fs + 1 <= c.M) ? load3(c, X, node0(fs + 1)) : a;
-    if (fs & 1) {
-      st.pf[1] = a;
-      st.pf[0] = b;
-    } else {
-      st.pf[0] = a;
-      st.pf[1] = b;
-    }
-  }
-  for (int fb = fs & ~3; fb <= fe; fb += 4) {
+  st.pf[0] = st.pf[1] = N3{1.0, {0.0, 0.0, 0.0}, 1.0};
+  st.pz[0] = st.pz[1] = 0.0;
+  for (int fb = (fs - 2) & ~3; fb <= fe; fb += 4) {
     lf_iter<0, FUSE>(c, st, fb + 0, fs, fe, k0, k1, w, lane, L, j, owave, xa, xb, zr, X, Y, lx);
     lf_iter<1, FUSE>(c, st, fb + 1, fs, fe, k0, k1, w, lane, L, j, owave, xa, xb, zr, X, Y, lx);
     lf_iter<2, FUSE>(c, st, fb + 2, fs, fe, k0, k1, w, lane, L, j, owave, xa, xb, zr, X, Y, lx);
