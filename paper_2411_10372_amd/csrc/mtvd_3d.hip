@@ -191,13 +191,11 @@ struct MF {
   double zz[4];            // their heights (L_z)
   P3 pn[4];                // primitives of X^n (p filled on use)
   double s[4];             // |u_AX| + c of X^n
-  double bb[4], bm[4];     // d_B u_B and d_B u_AX of X^n (across waves)
   double G[2];             // TVD coefficient of face row+1/2
   N3 Dp;                   // G dX of the face below the next output row
   N3 F[2];
   N3 xp[4];
   P3 pp[4];
-  double pb[4], pm[4];     // d_B u_B and d_B u_AX of X^P
   N3 FP[2];
   Acc3 acc;
 };
@@ -239,15 +237,20 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
     st.pz[e0] = (AX == 2) ? zr[fp] : zb;
     st.pn[c0] = prim3(c, st.x[c0], (AX == 2) ? st.zz[c0] : zb);
     st.s[c0] = fabs(st.pn[c0].u[AX]) + sound(c, st.pn[c0].T);
-    double ub = bval ? st.pn[c0].u[B] : 0.0, um = bval ? st.pn[c0].u[AX] : 0.0;
-    exchange(xa, w, lane, ub, um, ihb2, st.bb[c0], st.bm[c0]);
   }
   if (f < fs || f > fe) return;
   // heights of rows f-2 and f-3 (L_z) or of the wave's plane (L_y)
   const double z_r = (AX == 2) ? st.zz[c2] : zb, z_o = (AX == 2) ? st.zz[c3] : zb;
   const int r = f - 2;
   const bool rin_F = (AX == 2) ? (r >= 0 && r <= M - 1) : true;
-  // B: predictor flux F_r (inner derivatives forward along the march)
+  // B: predictor flux F_r (inner derivatives forward along the march); the
+  //    cross-wave derivatives of row r first (every wave of the block takes
+  //    part in the exchange: its condition is the same for all of them)
+  double bb = 0.0, bm = 0.0;   // d_B u_B and d_B u_AX of X^n at row r
+  if (r >= m0 - 2 && rin_F) {
+    const double ub = bval ? st.pn[c2].u[B] : 0.0, um = bval ? st.pn[c2].u[AX] : 0.0;
+    exchange(xa, w, lane, ub, um, ihb2, bb, bm);
+  }
   if (r >= m0 - 2 && rin_F && role >= 1 && bval && !bwall) {
     P3 q0 = st.pn[c2];
     const P3& q1 = st.pn[c1];
@@ -266,13 +269,14 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
     }
     du[0][0] = (shd(q0.u[0]) - shu(q0.u[0])) * (0.5 * c.ihx);
     du[AX][0] = (shd(q0.u[AX]) - shu(q0.u[AX])) * (0.5 * c.ihx);
-    du[B][B] = st.bb[c2];
-    du[AX][B] = st.bm[c2];
+    du[B][B] = bb;
+    du[AX][B] = bm;
     q0.p = c.a * st.x[c2].r * q0.T;
     st.F[e0] = flux3<AX>(c, st.x[c2], q0, du, dT);
   }
   // C: predictor X^P_r; exchange its velocities across waves
   const bool rin_P = (AX == 2) ? (r >= 0 && r <= M) : true;
+  double pb = 0.0, pm = 0.0;   // d_B u_B and d_B u_AX of X^P at row r
   if (r >= m0 - 1 && rin_P) {
     if (role >= 1 && bval) {
       if (bwall) {
@@ -303,7 +307,7 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
     }
     double ub = (role >= 1 && bval) ? st.pp[c2].u[B] : 0.0;
     double um = (role >= 1 && bval) ? st.pp[c2].u[AX] : 0.0;
-    exchange(xb, w, lane, ub, um, ihb2, st.pb[c2], st.pm[c2]);
+    exchange(xb, w, lane, ub, um, ihb2, pb, pm);
   }
   // D: corrector flux F^P_r (inner derivatives backward along the march)
   const bool rin_FP = (AX == 2) ? (r >= 1 && r <= M) : true;
@@ -325,8 +329,8 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
     }
     du[0][0] = (shd(q0.u[0]) - shu(q0.u[0])) * (0.5 * c.ihx);
     du[AX][0] = (shd(q0.u[AX]) - shu(q0.u[AX])) * (0.5 * c.ihx);
-    du[B][B] = st.pb[c2];
-    du[AX][B] = st.pm[c2];
+    du[B][B] = pb;
+    du[AX][B] = pm;
     st.FP[e0] = flux3<AX>(c, st.xp[c2], q0, du, dT);
   }
   // E: TVD coefficient of face r+1/2 along the march, jumps from the X ring
