@@ -99,6 +99,11 @@ __device__ __forceinline__ Lane3 lane3(const Coef& c, int strip, int lane) {
   return r;
 }
 
+// height of row k, z_k = k / M: the correctly rounded IEEE quotient, the
+// same number as the plate table the library fills (and the oracle's), so
+// computing it on use costs a division and no registers
+__device__ __forceinline__ double zrow(int k, int M) { return (double)k / (double)M; }
+
 __device__ __forceinline__ int wrap(int v, int n) {
   int m = v % n;
   return m < 0 ? m + n : m;
@@ -186,9 +191,7 @@ __device__ __forceinline__ void head3(Shared* sh, int slot, int first, double dt
 
 struct MF {
   N3 pf[2];                // prefetched rows f+1, f+2 (slot row & 1)
-  double pz[2];            // their heights (L_z), prefetched with them
   N3 x[4];                 // X^n rows f-3..f (slot row & 3)
-  double zz[4];            // their heights (L_z)
   P3 pn[4];                // primitives of X^n (p filled on use)
   double s[4];             // |u_AX| + c of X^n
   double G[2];             // TVD coefficient of face row+1/2
@@ -200,7 +203,11 @@ struct MF {
   Acc3 acc;
 };
 
-template <int AX, int S, bool FUSE>
+// PL: the chunk may touch a plate (L_z).  Chunks that cannot (first row
+// >= 4, last row <= M-4: every stage then works on rows 2..M-4) run a copy
+// compiled without the plate and wall code, whose registers fit without
+// spilling.
+template <int AX, int S, bool FUSE, bool PL>
 __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, int fe, int m0,
                                         int m1, int w, int lane, const Lane3& L, int bidx,
                                         bool bval, bool bwall, bool owave,
@@ -209,6 +216,7 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
                                         const double* __restrict__ X, double* __restrict__ Y,
                                         double tau, double lm, int bload, double zb) {
   constexpr int B = (AX == 2) ? 1 : 2;   // axis of the waves
+  constexpr bool P = (AX == 2) && PL;    // plate rows possible in this chunk
   const int M = c.M;
   const double ihm = (AX == 2) ? c.ihz : c.ihy;
   const double ihb2 = 0.5 * ((B == 1) ? c.ihy : c.ihz);
@@ -229,20 +237,18 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
   //    ring slots no stage reads, and their exchanged values are zeroed.
   {
     st.x[c0] = st.pf[e0];
-    st.zz[c0] = st.pz[e0];
     const int fp = (AX == 2) ? min(max(f + 2, 0), M) : f + 2;
     const long long np = (AX == 2) ? ((long long)fp * c.ny + bidx) * c.nx + L.col
                                    : ((long long)bload * c.ny + wrap(fp, c.ny)) * c.nx + L.col;
     st.pf[e0] = load3(c, X, np);
-    st.pz[e0] = (AX == 2) ? zr[fp] : zb;
-    st.pn[c0] = prim3(c, st.x[c0], (AX == 2) ? st.zz[c0] : zb);
+    st.pn[c0] = prim3(c, st.x[c0], (AX == 2) ? zrow(f, M) : zb);
     st.s[c0] = fabs(st.pn[c0].u[AX]) + sound(c, st.pn[c0].T);
   }
   if (f < fs || f > fe) return;
   // heights of rows f-2 and f-3 (L_z) or of the wave's plane (L_y)
-  const double z_r = (AX == 2) ? st.zz[c2] : zb, z_o = (AX == 2) ? st.zz[c3] : zb;
+  const double z_r = (AX == 2) ? zrow(f - 2, M) : zb, z_o = (AX == 2) ? zrow(f - 3, M) : zb;
   const int r = f - 2;
-  const bool rin_F = (AX == 2) ? (r >= 0 && r <= M - 1) : true;
+  const bool rin_F = P ? (r >= 0 && r <= M - 1) : true;
   // B: predictor flux F_r (inner derivatives forward along the march); the
   //    cross-wave derivatives of row r first (every wave of the block takes
   //    part in the exchange: its condition is the same for all of them)
@@ -256,7 +262,7 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
     const P3& q1 = st.pn[c1];
     double du[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     double dT;
-    if (AX == 2 && r == 0 && c.wall_order == 2) {
+    if (P && r == 0 && c.wall_order == 2) {
       const P3& q2 = st.pn[c0];
       double h2 = 0.5 * ihm;
 #pragma unroll
@@ -275,7 +281,7 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
     st.F[e0] = flux3<AX>(c, st.x[c2], q0, du, dT);
   }
   // C: predictor X^P_r; exchange its velocities across waves
-  const bool rin_P = (AX == 2) ? (r >= 0 && r <= M) : true;
+  const bool rin_P = P ? (r >= 0 && r <= M) : true;
   double pb = 0.0, pm = 0.0;   // d_B u_B and d_B u_AX of X^P at row r
   if (r >= m0 - 1 && rin_P) {
     if (role >= 1 && bval) {
@@ -283,11 +289,11 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
         st.xp[c2] = st.x[c2];
         st.pp[c2] = st.pn[c2];
         st.pp[c2].p = c.a * st.x[c2].r * st.pn[c2].T;
-      } else if (AX == 2 && r == 0) {
+      } else if (P && r == 0) {
         double rho = st.x[c2].r;
         st.xp[c2] = N3{rho, {0.0, 0.0, 0.0}, rho * (c.cv * c.Tb + c.g * z_r)};
         st.pp[c2] = P3{{0.0, 0.0, 0.0}, c.Tb, c.a * rho * c.Tb};
-      } else if (AX == 2 && r == M) {
+      } else if (P && r == M) {
         double rho = st.x[c2].r - lm * (st.x[c2].m[2] - st.x[c3].m[2]);
         st.xp[c2] = N3{rho, {0.0, 0.0, 0.0}, rho * (c.cv * c.Tt + c.g * z_r)};
         st.pp[c2] = P3{{0.0, 0.0, 0.0}, c.Tt, c.a * rho * c.Tt};
@@ -310,13 +316,13 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
     exchange(xb, w, lane, ub, um, ihb2, pb, pm);
   }
   // D: corrector flux F^P_r (inner derivatives backward along the march)
-  const bool rin_FP = (AX == 2) ? (r >= 1 && r <= M) : true;
+  const bool rin_FP = P ? (r >= 1 && r <= M) : true;
   if (r >= m0 && rin_FP && role == 2 && bval && !bwall) {
     const P3& q0 = st.pp[c2];
     const P3& qm = st.pp[c3];
     double du[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     double dT;
-    if (AX == 2 && r == M && c.wall_order == 2) {
+    if (P && r == M && c.wall_order == 2) {
       const P3& qmm = st.pp[c4];
       double h2 = 0.5 * ihm;
 #pragma unroll
@@ -334,10 +340,10 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
     st.FP[e0] = flux3<AX>(c, st.xp[c2], q0, du, dT);
   }
   // E: TVD coefficient of face r+1/2 along the march, jumps from the X ring
-  const bool rin_G = (AX == 2) ? (r >= 0 && r <= M - 1) : true;
+  const bool rin_G = P ? (r >= 0 && r <= M - 1) : true;
   if (r >= m0 - 1 && rin_G && role == 2 && bval && !bwall) {
     double G = 0.0;
-    const bool active = (AX == 2) ? (r >= 1 && r <= M - 2) : true;
+    const bool active = P ? (r >= 1 && r <= M - 2) : true;
     if (c.tvd_on && active) {
       N3 dm = sub3(st.x[c2], st.x[c3]);
       N3 d0 = sub3(st.x[c1], st.x[c2]);
@@ -350,12 +356,12 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
   // F: output row o = f-3; the face o+1/2 term G dX is carried to the next
   //    row as its o-1/2 term
   const int o = f - 3;
-  const bool rin_O = (AX == 2) ? (o >= 0 && o <= M - 1) : true;
+  const bool rin_O = P ? (o >= 0 && o <= M - 1) : true;
   if (o >= m0 - 1 && o < m1 && rin_O && owave && !bwall) {
     N3 d0 = sub3(st.x[c2], st.x[c3]);
     const double G = st.G[e1];
     N3 Dc{G * d0.r, {G * d0.m[0], G * d0.m[1], G * d0.m[2]}, G * d0.E};
-    if (o >= m0 && (AX == 1 || o >= 1)) {
+    if (o >= m0 && (!P || o >= 1)) {
       const N3& fp1 = st.FP[e0];
       const N3& fp0 = st.FP[e1];
       const N3& x0 = st.x[c3];
@@ -377,7 +383,7 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
     }
     st.Dp = Dc;
   }
-  if (o >= m0 && o < m1 && owave && (bwall || (AX == 2 && (o == 0 || o == M)))) {
+  if (o >= m0 && o < m1 && owave && (bwall || (P && (o == 0 || o == M)))) {
     N3 out;
     if (bwall) {
       out = st.x[c3];
@@ -393,12 +399,12 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
   }
 }
 
-template <int AX, bool FUSE>
+template <int AX, bool FUSE, bool PL>
 __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const double* zr,
                                                        int slot, int first,
                                                        const double* __restrict__ X,
                                                        double* __restrict__ Y, int kc,
-                                                       int nstrips, int nbb) {
+                                                       int nstrips, int nbb, int chunk0) {
   __shared__ double xa[2][kNW][64];
   __shared__ double xb[2][kNW][64];
   constexpr int B = (AX == 2) ? 1 : 2;
@@ -410,7 +416,7 @@ __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const
   const int strip = bid % nstrips;
   bid /= nstrips;
   const int bb = bid % nbb;
-  const int chunk = bid / nbb;
+  const int chunk = chunk0 + bid / nbb;
   const Lane3 L = lane3(c, strip, lane);
   const int nb_len = (B == 1) ? c.ny : c.nz;
   const int braw = bb * (kNW - 4) - 2 + w;   // index of this wave along B
@@ -444,12 +450,11 @@ __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const
   // the steps fs-2 and fs-1 only load rows fs and fs+1 (their heads); the
   // heads before them copy this defined, unused row
   st.pf[0] = st.pf[1] = N3{1.0, {0.0, 0.0, 0.0}, 1.0};
-  st.pz[0] = st.pz[1] = 0.0;
   for (int fb = (fs - 2) & ~3; fb <= fe; fb += 4) {
-    mf_iter<AX, 0, FUSE>(c, st, fb + 0, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, bload, zb);
-    mf_iter<AX, 1, FUSE>(c, st, fb + 1, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, bload, zb);
-    mf_iter<AX, 2, FUSE>(c, st, fb + 2, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, bload, zb);
-    mf_iter<AX, 3, FUSE>(c, st, fb + 3, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, bload, zb);
+    mf_iter<AX, 0, FUSE, PL>(c, st, fb + 0, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, bload, zb);
+    mf_iter<AX, 1, FUSE, PL>(c, st, fb + 1, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, bload, zb);
+    mf_iter<AX, 2, FUSE, PL>(c, st, fb + 2, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, bload, zb);
+    mf_iter<AX, 3, FUSE, PL>(c, st, fb + 3, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, bload, zb);
   }
   if (FUSE) fold3(sh, slot, st.acc);
 }
@@ -459,9 +464,7 @@ __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const
 
 struct LF {
   N3 pf[2];                // prefetched rows f+1, f+2
-  double pz[2];            // their heights
   N3 x[4];
-  double zz[4];
   P3 pn[4];
   double s[4];             // |u_x| + c of X^n
   double yx[4], yy[4];     // d_y u_x, d_y u_y of X^n
@@ -489,11 +492,9 @@ __device__ __forceinline__ void lf_iter(const Coef& c, LF& st, int f, int fs, in
   // every step, guarded by nothing (as in the march kernels of L_z, L_y)
   {
     st.x[c0] = st.pf[e0];
-    st.zz[c0] = st.pz[e0];
     const int fp = min(max(f + 2, 0), M);
     st.pf[e0] = load3(c, X, node(fp));
-    st.pz[e0] = zr[fp];
-    st.pn[c0] = prim3(c, st.x[c0], st.zz[c0]);
+    st.pn[c0] = prim3(c, st.x[c0], zrow(f, M));
     st.s[c0] = fabs(st.pn[c0].u[0]) + sound(c, st.pn[c0].T);
     exchange(xa, w, lane, st.pn[c0].u[0], st.pn[c0].u[1], ihy2, st.yx[c0], st.yy[c0]);
   }
@@ -525,7 +526,7 @@ __device__ __forceinline__ void lf_iter(const Coef& c, LF& st, int f, int fs, in
         for (int g = 0; g < 3; ++g) v.m[g] = x0.m[g] - lx * (Fi.m[g] - Fm.m[g]);
         v.E = x0.E - lx * (Fi.E - Fm.E);
         st.xp[c1] = v;
-        st.pp[c1] = prim3(c, v, st.zz[c1]);
+        st.pp[c1] = prim3(c, v, zrow(r1, M));
       }
     }
     double a = (role >= 1) ? st.pp[c1].u[0] : 0.0;
@@ -572,7 +573,7 @@ __device__ __forceinline__ void lf_iter(const Coef& c, LF& st, int f, int fs, in
       for (int g = 0; g < 3; ++g) out.m[g] = 0.5 * (xp.m[g] + xc.m[g]) + (D.m[g] - Dm.m[g]);
       out.E = 0.5 * (xp.E + xc.E) + (D.E - Dm.E);
     }
-    if (FUSE) acc_out(c, out, st.zz[c2], st.acc, L.out);
+    if (FUSE) acc_out(c, out, zrow(r, M), st.acc, L.out);
     if (L.out) store3(c, Y, node(r), out);
   }
 }
@@ -607,7 +608,6 @@ __global__ __launch_bounds__(64 * kNW) void sweep_lf3d(Coef c, Shared* sh, const
   const int fs = max(0, k0 - 2);
   const int fe = k1 + 1;
   st.pf[0] = st.pf[1] = N3{1.0, {0.0, 0.0, 0.0}, 1.0};
-  st.pz[0] = st.pz[1] = 0.0;
   for (int fb = (fs - 2) & ~3; fb <= fe; fb += 4) {
     lf_iter<0, FUSE>(c, st, fb + 0, fs, fe, k0, k1, w, lane, L, j, owave, xa, xb, zr, X, Y, lx);
     lf_iter<1, FUSE>(c, st, fb + 1, fs, fe, k0, k1, w, lane, L, j, owave, xa, xb, zr, X, Y, lx);
@@ -636,8 +636,32 @@ hipError_t launch_sweep_3d(int axis, const Coef& c, Shared* sh, const double* zr
       if (fuse) sweep_lf3d<true><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nbb);
       else sweep_lf3d<false><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nbb);
     } else {
-      if (fuse) sweep_mf3d<2, true><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nbb);
-      else sweep_mf3d<2, false><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nbb);
+      // chunks [lo, hi] cannot touch a plate (first row >= 4, last row <=
+      // M-4): the copy without plate code; the others the general one.  The
+      // launches of one operator are independent (disjoint output rows); only
+      // the first one does the step's bookkeeping (time, dt, the next slot).
+      const int lo = (4 + kc - 1) / kc;
+      const int hi = (c.M - 4) / kc - 1;
+      int fst = first;
+      auto run = [&](int c0, int c1, bool pl) {
+        if (c1 < c0) return;
+        const dim3 g((unsigned)((long long)nstrips * nbb * (c1 - c0 + 1)));
+        if (pl) {
+          if (fuse) sweep_mf3d<2, true, true><<<g, block, 0, s>>>(c, sh, zr, slot, fst, X, Y, kc, nstrips, nbb, c0);
+          else sweep_mf3d<2, false, true><<<g, block, 0, s>>>(c, sh, zr, slot, fst, X, Y, kc, nstrips, nbb, c0);
+        } else {
+          if (fuse) sweep_mf3d<2, true, false><<<g, block, 0, s>>>(c, sh, zr, slot, fst, X, Y, kc, nstrips, nbb, c0);
+          else sweep_mf3d<2, false, false><<<g, block, 0, s>>>(c, sh, zr, slot, fst, X, Y, kc, nstrips, nbb, c0);
+        }
+        fst = 0;
+      };
+      if (lo > hi) {
+        run(0, nch - 1, true);
+      } else {
+        run(0, lo - 1, true);
+        run(lo, hi, false);
+        run(hi + 1, nch - 1, true);
+      }
     }
   } else {
     // march y, waves along z
@@ -646,8 +670,8 @@ hipError_t launch_sweep_3d(int axis, const Coef& c, Shared* sh, const double* zr
     const long long nblk = (long long)nstrips * nbb * nch;
     if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
     const dim3 grid((unsigned)nblk);
-    if (fuse) sweep_mf3d<1, true><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nbb);
-    else sweep_mf3d<1, false><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nbb);
+    if (fuse) sweep_mf3d<1, true, true><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nbb, 0);
+    else sweep_mf3d<1, false, true><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nbb, 0);
   }
   return hipGetLastError();
 }
