@@ -403,12 +403,20 @@ int default_rows(const mtvd_ctx* c, int axis) {
     long long chunks = slots > 0 ? slots / cols : 1;
     if (chunks < 1) chunks = 1;
     kc = (c->c.nz + chunks - 1) / chunks;
+    // small grids: at least 2 rows (more, shorter waves measured faster
+    // down to 2 at 512x128, where every launch is latency-bound)
+    if (kc < 2) kc = 2;
   } else {
-    // 3D: blocks of 8 waves; a quarter of the marched extent, 4..32 rows
-    kc = c->c.nz / 4;
-    if (kc > 32) kc = 32;
+    // 3D, blocks of 8 waves: a quarter of the marched extent (L_x and L_z
+    // march z, L_y marches y), at most 64 rows; L_z at most 48, so that
+    // most of its chunks stay clear of the plates and run the copy without
+    // plate code (measured at 1024x1024x256: L_x, L_y best at 64-128 rows,
+    // L_z at 24-48)
+    const long long len = (axis == 1) ? c->c.ny : c->c.nz;
+    kc = len / 4;
+    if (kc > ((axis == 2) ? 48 : 64)) kc = (axis == 2) ? 48 : 64;
+    if (kc < 4) kc = 4;
   }
-  if (kc < 4) kc = 4;
   if (kc > 64) kc = 64;
   return (int)kc;
 }
@@ -1407,8 +1415,14 @@ void adj_shape(mtvd_adj* a, const mtvd_params* p, int32_t nsteps, int32_t every)
   a->nsteps = nsteps;
   a->every = every > nsteps ? nsteps : every;
   a->nseg = (nsteps + a->every - 1) / a->every;
-  long long kc = (long long)strips_2d(a->c.nx) * a->c.nz / 4096;
-  a->kc = (int)(kc < 4 ? 4 : (kc > 64 ? 64 : kc));
+  // rows per wave of the forward sweeps as for a single box: fill the
+  // resident wave slots in one round, 2..64 rows
+  const long long cols = (long long)strips_2d(a->c.nx);
+  const int slots = wave_slots_2d(0, false);
+  long long chunks = slots > 0 ? slots / cols : 1;
+  if (chunks < 1) chunks = 1;
+  long long kc = (a->c.nz + chunks - 1) / chunks;
+  a->kc = (int)(kc < 2 ? 2 : (kc > 64 ? 64 : kc));
   adj::AC& ac = a->ac;
   memset(&ac, 0, sizeof(ac));
   const Coef& c = a->c;

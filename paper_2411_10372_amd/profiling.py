@@ -12,7 +12,7 @@ largest ``__amd_rocclr_copyBuffer`` dispatch of the run: ``bench.py
 Usage (paths are the rocprofv3 output directories):
     python -m paper_2411_10372_amd.profiling trace DIR OUT.md "COMMAND"
     python -m paper_2411_10372_amd.profiling pmc FETCH_DIR WRITE_DIR KERNEL \
-        WORKLOAD SOURCE_HASH COPY_BYTES OUT.json "COMMANDS"
+        WORKLOAD SOURCE_HASH COPY_BYTES OUT.json "COMMANDS" [DISPATCHES_PER_LAUNCH]
 """
 from __future__ import annotations
 
@@ -57,7 +57,10 @@ def _mean_for(rows, pred):
 
 
 def pmc_summary(fetch_dir: str, write_dir: str, kernel: str, workload: str, shash: str,
-                copy_bytes: int, out_json: str, commands: str) -> dict:
+                copy_bytes: int, out_json: str, commands: str, per_launch: int = 1) -> dict:
+    """HBM bytes of one launch of an operator: the mean over the dispatches
+    whose name contains `kernel`, times `per_launch` dispatches per
+    operator launch (an operator split over several kernels)."""
     fr, wr = _counter(fetch_dir), _counter(write_dir)
 
     def is_kernel(r):
@@ -80,7 +83,8 @@ def pmc_summary(fetch_dir: str, write_dir: str, kernel: str, workload: str, shas
         "dispatches": [nf, nw],
         "copy_ref": {"bytes_read": copy_bytes // 2, "bytes_written": copy_bytes // 2,
                      "fetch_kib": cf, "write_kib": cw, "fetch_scale": fs, "write_scale": ws},
-        "hbm_bytes_per_launch": (fetch_kib * fs + write_kib * ws) * 1024.0,
+        "dispatches_per_launch": per_launch,
+        "hbm_bytes_per_launch": (fetch_kib * fs + write_kib * ws) * 1024.0 * per_launch,
         "commands": commands,
     }
     with open(out_json, "w") as f:
@@ -93,8 +97,8 @@ if __name__ == "__main__":
     if a and a[0] == "trace":
         print(json.dumps(trace_summary(a[1], a[2], a[3]), indent=1))
     elif a and a[0] == "pmc":
-        print(json.dumps(pmc_summary(a[1], a[2], a[3], a[4], a[5], int(a[6]), a[7], a[8]),
-                         indent=1))
+        print(json.dumps(pmc_summary(a[1], a[2], a[3], a[4], a[5], int(a[6]), a[7], a[8],
+                                     int(a[9]) if len(a) > 9 else 1), indent=1))
     else:
         print(__doc__)
         sys.exit(2)
