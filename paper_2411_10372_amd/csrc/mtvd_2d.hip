@@ -341,7 +341,7 @@ __global__ __launch_bounds__(256) void sweep_z2d(Coef c, Shared* sh, const doubl
                                                  int nstrips, int nwaves) {
   const int lane = threadIdx.x & 63;
   // wave-uniform by construction; readfirstlane lets the compiler keep it scalar
-  const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  const int w = __builtin_amdgcn_readfirstlane(xcd_block() * (blockDim.x >> 6) + (threadIdx.x >> 6));
   const double dt = step_dt(c, sh, slot);
   step_head(c, sh, slot, first, dt);
   if (w >= nwaves) return;
@@ -500,7 +500,7 @@ __global__ __launch_bounds__(256) void sweep_x2d(Coef c, Shared* sh, const doubl
                                                  int nstrips, int nwaves) {
   const int lane = threadIdx.x & 63;
   // wave-uniform by construction; readfirstlane lets the compiler keep it scalar
-  const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  const int w = __builtin_amdgcn_readfirstlane(xcd_block() * (blockDim.x >> 6) + (threadIdx.x >> 6));
   const double dt = step_dt(c, sh, slot);
   step_head(c, sh, slot, first, dt);
   if (w >= nwaves) return;
@@ -522,7 +522,7 @@ __global__ __launch_bounds__(256) void sweep_batch2d(const BoxDesc* __restrict__
                                                      double* Y) {
   const int lane = threadIdx.x & 63;
   // wave-uniform by construction; readfirstlane lets the compiler keep it scalar
-  const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  const int w = __builtin_amdgcn_readfirstlane(xcd_block() * (blockDim.x >> 6) + (threadIdx.x >> 6));
   if (w >= nitems) return;
   const int4 it = items[w];
   const BoxDesc* bd = boxes + it.x;

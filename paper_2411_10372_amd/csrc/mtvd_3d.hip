@@ -412,7 +412,7 @@ __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const double dt = step_dt(c, sh, slot);
   head3(sh, slot, first, dt);
-  int bid = blockIdx.x;
+  int bid = xcd_block();
   const int strip = bid % nstrips;
   bid /= nstrips;
   const int bb = bid % nbb;
@@ -590,7 +590,7 @@ __global__ __launch_bounds__(64 * kNW) void sweep_lf3d(Coef c, Shared* sh, const
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const double dt = step_dt(c, sh, slot);
   head3(sh, slot, first, dt);
-  int bid = blockIdx.x;
+  int bid = xcd_block();
   const int strip = bid % nstrips;
   bid /= nstrips;
   const int bb = bid % nbb;

@@ -53,6 +53,19 @@ struct Shared {
 // the part a block folds into
 __device__ __forceinline__ int max_part() { return (int)(blockIdx.x % kMaxParts); }
 
+// Work index of this block, XCD-aware.  The dispatcher hands consecutive
+// blocks to the 8 XCDs in turn, and each XCD has its own L2; this bijection
+// of [0, nblocks) gives every XCD a contiguous range of work indices, so
+// blocks that share halo rows, planes and cache lines run on the same L2 at
+// about the same time instead of fetching the shared data once per XCD.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block() {
+  const int b = (int)blockIdx.x, G = (int)gridDim.x;
+  const int x = b % kXcds, k = b / kXcds;
+  const int q = G / kXcds, r = G % kXcds;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
+
 // One box of a batch: its constants, the offset of its state in the state
 // arenas (field stride c.cnt from there), of its plate table in the z
 // arena, and its rows per wave for each operator.
