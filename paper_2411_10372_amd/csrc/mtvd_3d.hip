@@ -130,8 +130,12 @@ __device__ __forceinline__ void store3(const Coef& c, double* __restrict__ Y, lo
 }
 
 // Two scalars of every wave to LDS, barrier, and their central differences
-// across neighbouring waves (dual buffers alternate so one barrier per
-// exchange suffices).
+// across neighbouring waves.  Each exchange array has two buffers that
+// alternate with the parity of the march row: two exchanges in a row on the
+// same array (at a chunk's first rows, at the top plate) then use different
+// buffers, and the barrier of the second one orders every read of the first
+// before the next write to its buffer, so a wave that runs ahead never
+// overwrites a value a slower wave has yet to read.
 __device__ __forceinline__ void exchange(double (&buf)[2][kNW][64], int w, int lane,
                                          double a, double b, double ih2, double& da,
                                          double& db) {
@@ -211,7 +215,7 @@ template <int AX, int S, bool FUSE, bool PL>
 __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, int fe, int m0,
                                         int m1, int w, int lane, const Lane3& L, int bidx,
                                         bool bval, bool bwall, bool owave,
-                                        double (&xa)[2][kNW][64], double (&xb)[2][kNW][64],
+                                        double (&xa)[2][2][kNW][64], double (&xb)[2][2][kNW][64],
                                         const double* __restrict__ zr,
                                         const double* __restrict__ X, double* __restrict__ Y,
                                         double tau, double lm, int bload, double zb) {
@@ -255,7 +259,7 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
   double bb = 0.0, bm = 0.0;   // d_B u_B and d_B u_AX of X^n at row r
   if (r >= m0 - 2 && rin_F) {
     const double ub = bval ? st.pn[c2].u[B] : 0.0, um = bval ? st.pn[c2].u[AX] : 0.0;
-    exchange(xa, w, lane, ub, um, ihb2, bb, bm);
+    exchange(xa[S & 1], w, lane, ub, um, ihb2, bb, bm);
   }
   if (r >= m0 - 2 && rin_F && role >= 1 && bval && !bwall) {
     P3 q0 = st.pn[c2];
@@ -313,7 +317,7 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
     }
     double ub = (role >= 1 && bval) ? st.pp[c2].u[B] : 0.0;
     double um = (role >= 1 && bval) ? st.pp[c2].u[AX] : 0.0;
-    exchange(xb, w, lane, ub, um, ihb2, pb, pm);
+    exchange(xb[S & 1], w, lane, ub, um, ihb2, pb, pm);
   }
   // D: corrector flux F^P_r (inner derivatives backward along the march)
   const bool rin_FP = P ? (r >= 1 && r <= M) : true;
@@ -405,8 +409,8 @@ __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const
                                                        const double* __restrict__ X,
                                                        double* __restrict__ Y, int kc,
                                                        int nstrips, int nbb, int chunk0) {
-  __shared__ double xa[2][kNW][64];
-  __shared__ double xb[2][kNW][64];
+  __shared__ double xa[2][2][kNW][64];
+  __shared__ double xb[2][2][kNW][64];
   constexpr int B = (AX == 2) ? 1 : 2;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
@@ -477,8 +481,8 @@ struct LF {
 template <int S, bool FUSE>
 __device__ __forceinline__ void lf_iter(const Coef& c, LF& st, int f, int fs, int fe, int k0,
                                         int k1, int w, int lane, const Lane3& L, int j,
-                                        bool owave, double (&xa)[2][kNW][64],
-                                        double (&xb)[2][kNW][64],
+                                        bool owave, double (&xa)[2][2][kNW][64],
+                                        double (&xb)[2][2][kNW][64],
                                         const double* __restrict__ zr,
                                         const double* __restrict__ X, double* __restrict__ Y,
                                         double lx) {
@@ -496,7 +500,7 @@ __device__ __forceinline__ void lf_iter(const Coef& c, LF& st, int f, int fs, in
     st.pf[e0] = load3(c, X, node(fp));
     st.pn[c0] = prim3(c, st.x[c0], zrow(f, M));
     st.s[c0] = fabs(st.pn[c0].u[0]) + sound(c, st.pn[c0].T);
-    exchange(xa, w, lane, st.pn[c0].u[0], st.pn[c0].u[1], ihy2, st.yx[c0], st.yy[c0]);
+    exchange(xa[S & 1], w, lane, st.pn[c0].u[0], st.pn[c0].u[1], ihy2, st.yx[c0], st.yy[c0]);
   }
   if (f < fs || f > fe) return;
   // predictor on row f-1
@@ -531,7 +535,7 @@ __device__ __forceinline__ void lf_iter(const Coef& c, LF& st, int f, int fs, in
     }
     double a = (role >= 1) ? st.pp[c1].u[0] : 0.0;
     double b = (role >= 1) ? st.pp[c1].u[1] : 0.0;
-    exchange(xb, w, lane, a, b, ihy2, st.pyx[c1], st.pyy[c1]);
+    exchange(xb[S & 1], w, lane, a, b, ihy2, st.pyx[c1], st.pyy[c1]);
   }
   // corrector, average and TVD term on row f-2
   const int r = f - 2;
@@ -584,8 +588,8 @@ __global__ __launch_bounds__(64 * kNW) void sweep_lf3d(Coef c, Shared* sh, const
                                                        const double* __restrict__ X,
                                                        double* __restrict__ Y, int kc,
                                                        int nstrips, int nbb) {
-  __shared__ double xa[2][kNW][64];
-  __shared__ double xb[2][kNW][64];
+  __shared__ double xa[2][2][kNW][64];
+  __shared__ double xb[2][2][kNW][64];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const double dt = step_dt(c, sh, slot);
