@@ -102,10 +102,18 @@ __device__ __forceinline__ void out_max(const Coef& c, const N2& o, double z, do
 // L_z(tau): flux differences along the march, cross x-derivatives from the
 // neighbouring lanes.
 
+// Rows are prefetched kPF march steps ahead of their use (2; 4 was
+// measured slower: its 20 extra registers cost more than the added slack).
+#ifndef MTVD_PF
+#define MTVD_PF 2
+#endif
+constexpr int kPF = MTVD_PF;
+static_assert(kPF == 2 || kPF == 4, "prefetch ring period must divide the unroll");
+
 struct Z2 {
-  N2 pf[2];     // prefetched rows f+1, f+2, slot row & 1
-  double pz[2]; // their heights z_k, prefetched with them (a height loaded
-                // on use would make the wave wait for every load in flight)
+  N2 pf[kPF];     // prefetched rows f+1 .. f+kPF, slot row % kPF
+  double pz[kPF]; // their heights z_k, prefetched with them (a height loaded
+                  // on use would make the wave wait for every load in flight)
   N2 x[4];      // X^n rows f-3..f, slot row & 3
   double zz[4]; // their heights
   P2 pn[4];     // primitives of X^n (p filled on use)
@@ -128,9 +136,10 @@ struct ZS {
   static constexpr int c0 = S & 3, c1 = (S + 3) & 3, c2 = (S + 2) & 3, c3 = (S + 1) & 3;
   static constexpr int c4 = S & 3;   // row f-4 (its slot is reused by row f)
   static constexpr int e0 = S & 1, e1 = (S + 1) & 1;
+  static constexpr int q0 = S % kPF;   // prefetch slot of row f (and f+kPF)
 };
 
-// A: row f (prefetched two steps ago) and its primitives; prefetch row f+2.
+// A: row f (prefetched kPF steps ago) and its primitives; prefetch row f+kPF.
 //    Every step of the march runs this head, whether or not it computes:
 //    the row index is clamped into [0, M], and no guard surrounds the
 //    loads, because a guarded load has to be copied into the loop-carried
@@ -141,11 +150,11 @@ __device__ __forceinline__ void z2_load(const Coef& c, Z2& st, int f, const Cols
                                         const double* __restrict__ zr,
                                         const double* __restrict__ X) {
   using Z = ZS<S>;
-  st.x[Z::c0] = st.pf[Z::e0];
-  st.zz[Z::c0] = st.pz[Z::e0];
-  const int fp = min(max(f + 2, 0), c.M);
-  st.pf[Z::e0] = load2(c, X, fp, L.col);
-  st.pz[Z::e0] = zr[fp];
+  st.x[Z::c0] = st.pf[Z::q0];
+  st.zz[Z::c0] = st.pz[Z::q0];
+  const int fp = min(max(f + kPF, 0), c.M);
+  st.pf[Z::q0] = load2(c, X, fp, L.col);
+  st.pz[Z::q0] = zr[fp];
   st.pn[Z::c0] = prim2(c, st.x[Z::c0], st.zz[Z::c0]);
   st.s[Z::c0] = fabs(st.pn[Z::c0].uz) + sound(c, st.pn[Z::c0].T);
 }
@@ -320,11 +329,13 @@ __device__ __forceinline__ void z2_wave(const Coef& c, Shared* sh, const double*
   st.Dp = N2{0.0, 0.0, 0.0, 0.0};
   const int fs = max(0, k0 - 2);
   const int fe = k1 + 2;
-  // the steps fs-2 and fs-1 only load rows fs and fs+1 (their heads); the
-  // heads before them copy this defined, unused row
-  st.pf[0] = st.pf[1] = N2{1.0, 0.0, 0.0, 1.0};
-  st.pz[0] = st.pz[1] = 0.0;
-  for (int fb = (fs - 2) & ~3; fb <= fe; fb += 4) {
+  // the kPF steps before fs only load rows fs .. fs+kPF-1 (their heads);
+  // the heads before them copy this defined, unused row
+  for (int q = 0; q < kPF; ++q) {
+    st.pf[q] = N2{1.0, 0.0, 0.0, 1.0};
+    st.pz[q] = 0.0;
+  }
+  for (int fb = (fs - kPF) & ~3; fb <= fe; fb += 4) {
     z2_iter<0, FUSE>(c, st, fb + 0, fs, fe, k0, k1, L, zr, X, Y, tau, lz);
     z2_iter<1, FUSE>(c, st, fb + 1, fs, fe, k0, k1, L, zr, X, Y, tau, lz);
     z2_iter<2, FUSE>(c, st, fb + 2, fs, fe, k0, k1, L, zr, X, Y, tau, lz);
@@ -353,8 +364,8 @@ __global__ __launch_bounds__(256) void sweep_z2d(Coef c, Shared* sh, const doubl
 // march.  Plate rows are copied through.
 
 struct X2 {
-  N2 pf[2];      // as in Z2
-  double pz[2];
+  N2 pf[kPF];    // as in Z2
+  double pz[kPF];
   N2 x[4];
   double zz[4];
   P2 pn[4];      // p filled on use
@@ -371,11 +382,11 @@ __device__ __forceinline__ void x2_load(const Coef& c, X2& st, int f, const Cols
                                         const double* __restrict__ zr,
                                         const double* __restrict__ X) {
   using Z = ZS<S>;
-  st.x[Z::c0] = st.pf[Z::e0];
-  st.zz[Z::c0] = st.pz[Z::e0];
-  const int fp = min(max(f + 2, 0), c.M);
-  st.pf[Z::e0] = load2(c, X, fp, L.col);
-  st.pz[Z::e0] = zr[fp];
+  st.x[Z::c0] = st.pf[Z::q0];
+  st.zz[Z::c0] = st.pz[Z::q0];
+  const int fp = min(max(f + kPF, 0), c.M);
+  st.pf[Z::q0] = load2(c, X, fp, L.col);
+  st.pz[Z::q0] = zr[fp];
   st.pn[Z::c0] = prim2(c, st.x[Z::c0], st.zz[Z::c0]);
 }
 
@@ -479,11 +490,13 @@ __device__ __forceinline__ void x2_wave(const Coef& c, Shared* sh, const double*
   st.bad = false;
   const int fs = max(0, k0 - 2);
   const int fe = k1 + 1;
-  // the steps fs-2 and fs-1 only load rows fs and fs+1 (their heads); the
-  // heads before them copy this defined, unused row
-  st.pf[0] = st.pf[1] = N2{1.0, 0.0, 0.0, 1.0};
-  st.pz[0] = st.pz[1] = 0.0;
-  for (int fb = (fs - 2) & ~3; fb <= fe; fb += 4) {
+  // the kPF steps before fs only load rows fs .. fs+kPF-1 (their heads);
+  // the heads before them copy this defined, unused row
+  for (int q = 0; q < kPF; ++q) {
+    st.pf[q] = N2{1.0, 0.0, 0.0, 1.0};
+    st.pz[q] = 0.0;
+  }
+  for (int fb = (fs - kPF) & ~3; fb <= fe; fb += 4) {
     x2_iter<0, FUSE>(c, st, fb + 0, fs, fe, k0, k1, L, zr, X, Y, lx);
     x2_iter<1, FUSE>(c, st, fb + 1, fs, fe, k0, k1, L, zr, X, Y, lx);
     x2_iter<2, FUSE>(c, st, fb + 2, fs, fe, k0, k1, L, zr, X, Y, lx);
