@@ -20,12 +20,15 @@ namespace {
 enum Stage { kFwAll, kRvTc, kRvPred, kRvPrim };
 
 constexpr int kBlk = 256;
-constexpr int kObjBlk = 256;
 
-template <int ST>
+// AX: the operator's axis as a compile-time constant, so that every axis
+// test of the stage functions folds away
+template <int ST, int AX>
 __global__ __launch_bounds__(kBlk) void adj_stage(AC c, Arr A, const Shared* sh) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= c.cnt) return;
+  c.axis = AX;
+  c.iha = AX == 0 ? c.ihx : c.ihz;
   c.tau = 0.5 * sh->dt_frozen;
   c.lm = c.tau * c.iha;
   const int i = (int)(t % c.nx), k = (int)(t / c.nx);
@@ -84,29 +87,30 @@ __device__ __forceinline__ void nu_rows(const Coef& c, int r, int* row, double* 
   *wgt = w[r];
 }
 
-// acc[0] += w * Nu_mean(X): one block; row means by a fixed-order tree
-__global__ __launch_bounds__(kObjBlk) void nu_obj_kernel(Coef c, const double* zr,
-                                                         const double* __restrict__ X, double w,
-                                                         double* acc) {
-  __shared__ double red[6][kObjBlk];
-  const int t = threadIdx.x;
-  for (int r = 0; r < 6; ++r) {
-    int k;
-    double wr;
-    nu_rows(c, r, &k, &wr);
-    double s = 0.0;
-    for (int i = t; i < c.nx; i += kObjBlk) s += node_T(c, X, (long long)k * c.nx + i, zr[k]);
-    red[r][t] = s;
-  }
+// acc[0] += w * Nu_mean(X): one wave per row that Nu_mean reads (6 waves).
+// Each lane sums the temperatures of nodes lane, lane + 64, ... in that
+// order, the wave adds its 64 partial sums by a fixed butterfly, and the
+// first thread combines the six row means: a fixed order of operations, so
+// repeated runs give the same bits.
+__global__ __launch_bounds__(6 * 64) void nu_obj_kernel(Coef c, const double* zr,
+                                                        const double* __restrict__ X, double w,
+                                                        double* acc) {
+  __shared__ double rows[6];
+  const int r = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int k;
+  double wr;
+  nu_rows(c, r, &k, &wr);
+  const double z = zr[k];
+  const long long base = (long long)k * c.nx;
+  double s = 0.0;
+#pragma unroll 8
+  for (int i = lane; i < c.nx; i += 64) s += node_T(c, X, base + i, z);
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) rows[r] = s;
   __syncthreads();
-  for (int h = kObjBlk / 2; h > 0; h >>= 1) {
-    if (t < h)
-      for (int r = 0; r < 6; ++r) red[r][t] += red[r][t + h];
-    __syncthreads();
-  }
-  if (t == 0) {
+  if (threadIdx.x == 0) {
     double tm[6];
-    for (int r = 0; r < 6; ++r) tm[r] = red[r][0] / (double)c.nx;
+    for (int q = 0; q < 6; ++q) tm[q] = rows[q] / (double)c.nx;
     const double gb = ((-3.0 * tm[0] + 4.0 * tm[1]) - tm[2]) * (0.5 * c.ihz);
     const double gt = ((3.0 * tm[5] - 4.0 * tm[4]) + tm[3]) * (0.5 * c.ihz);
     const double nub = -(gb + c.D) / c.eps, nut = -(gt + c.D) / c.eps;
@@ -183,10 +187,17 @@ hipError_t launch_adj_sweep(int axis, const AC& c0, const Arr& A, const Shared* 
   c.axis = axis;
   c.iha = axis == 0 ? c.ihx : c.ihz;
   const unsigned g = blocks_for(c.cnt, kBlk);
-  adj_stage<kFwAll><<<g, kBlk, 0, s>>>(c, A, sh);
-  adj_stage<kRvTc><<<g, kBlk, 0, s>>>(c, A, sh);
-  adj_stage<kRvPred><<<g, kBlk, 0, s>>>(c, A, sh);
-  adj_stage<kRvPrim><<<g, kBlk, 0, s>>>(c, A, sh);
+  if (axis == 0) {
+    adj_stage<kFwAll, 0><<<g, kBlk, 0, s>>>(c, A, sh);
+    adj_stage<kRvTc, 0><<<g, kBlk, 0, s>>>(c, A, sh);
+    adj_stage<kRvPred, 0><<<g, kBlk, 0, s>>>(c, A, sh);
+    adj_stage<kRvPrim, 0><<<g, kBlk, 0, s>>>(c, A, sh);
+  } else {
+    adj_stage<kFwAll, 2><<<g, kBlk, 0, s>>>(c, A, sh);
+    adj_stage<kRvTc, 2><<<g, kBlk, 0, s>>>(c, A, sh);
+    adj_stage<kRvPred, 2><<<g, kBlk, 0, s>>>(c, A, sh);
+    adj_stage<kRvPrim, 2><<<g, kBlk, 0, s>>>(c, A, sh);
+  }
   return hipGetLastError();
 }
 
@@ -204,7 +215,7 @@ hipError_t launch_ra_reduce(long long cnt, const double* MU, const double* KB, d
 
 hipError_t launch_nu_obj(const Coef& c, const double* zr, const double* X, double w, double* acc,
                          hipStream_t s) {
-  nu_obj_kernel<<<1, kObjBlk, 0, s>>>(c, zr, X, w, acc);
+  nu_obj_kernel<<<1, 6 * 64, 0, s>>>(c, zr, X, w, acc);
   return hipGetLastError();
 }
 

@@ -30,6 +30,12 @@ def _one(pattern: str) -> str:
     return hits[0]
 
 
+def _short(name: str) -> str:
+    """Kernel name without its argument list and return type."""
+    name = name.replace("(anonymous namespace)::", "")
+    return name.split("(")[0].replace("void ", "")
+
+
 def trace_summary(trace_dir: str, out_md: str, command: str, top: int = 12) -> list:
     rows = list(csv.DictReader(open(_one(os.path.join(trace_dir, "*kernel_stats.csv")))))
     lines = ["# Kernel trace summary", "", "Command:", "", "```", command, "```", "",
@@ -37,7 +43,7 @@ def trace_summary(trace_dir: str, out_md: str, command: str, top: int = 12) -> l
              "|---|---|---|---|---|---|"]
     out = []
     for r in rows[:top]:
-        name = r["Name"].split("(")[0].replace("void ", "")
+        name = _short(r["Name"])
         avg, mn, mx = (float(r[k]) / 1e3 for k in ("AverageNs", "MinNs", "MaxNs"))
         lines.append(f"| `{name}` | {r['Calls']} | {avg:.1f} | {mn:.1f} | {mx:.1f} | "
                      f"{float(r['Percentage']):.2f} % |")
