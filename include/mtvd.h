@@ -96,6 +96,23 @@ typedef struct mtvd_diag {
                             non-positive rho/T seen) */
 } mtvd_diag;
 
+/* Snapshot scalars of the analysis of Sec. 4 (and Re of Sec. 2), made on
+ * the host from the row means of mtvd_profiles; volume means <.>_V use the
+ * trapezoid rule in z over a box of height 1. */
+typedef struct mtvd_analysis {
+  double Re;             /* sqrt(Ra/Pr) sqrt(<|u|^2>_V) (Sec. 2, Eq. Re) */
+  double C;              /* <rho u_z T_sa>_V / sqrt(<(rho u_z)^2>_V <T_sa^2>_V),
+                            0 when either factor is 0 (Sec. 4, C(Ra)) */
+  double Fn, Fp, Fb, Fv; /* <F>_V of the z-momentum terms (Sec. 4) */
+  double u2, rho_uz_Tsa, rho_uz2, Tsa2;   /* <.>_V of the inputs above */
+} mtvd_analysis;
+
+/* Rows of the mtvd_profiles output, in order. */
+#define MTVD_NUM_PROFILES 10
+/* 0 T  1 rho  2 |u|^2  3 rho u_z T_sa  4 (rho u_z)^2  5 T_sa^2
+   6 F_n = rho (u . grad) u_z   7 F_p = -dp/dz   8 F_b = rho g
+   9 F_v = d_i tau_iz                                               */
+
 typedef struct mtvd_ctx mtvd_ctx;
 
 void mtvd_default_params(mtvd_params* p);
@@ -135,6 +152,40 @@ int mtvd_sweep(mtvd_ctx* c, int32_t axis);
 /* Compute the diagnostics of the current state; synchronises the stream.
  * Returns MTVD_ENONFINITE (and still fills *out) if a device flag is set. */
 int mtvd_diagnostics(mtvd_ctx* c, mtvd_diag* out);
+
+/* Row means <.>_A (over the nx x ny nodes of each row k) of the ten node
+ * quantities listed with MTVD_NUM_PROFILES, for the analysis of Sec. 4
+ * (profiles T_sa(z), rho - rho_A(z), U(z), the correlation C(Ra), the
+ * z-momentum balance F_n, F_p, F_b, F_v) and Re (Sec. 2).  Derivatives:
+ * central second order along x, y and inside; second-order one-sided on
+ * the plates ((-3, 4, -1)/(2 dz), (3, -4, 1)/(2 dz); second derivatives
+ * (2, -5, 4, -1)/dz^2); F_v = mu (lap u_z + (1 + lambda) d_z div u); F_b
+ * = rho g with g = gravity_scale/eps; T_sa = T - (1 - D z).
+ * out: host array of count >= MTVD_NUM_PROFILES * nz doubles, written
+ * quantity-major (out[q * nz + k]).  Device work on the context's stream,
+ * then synchronises.  MTVD_ESTATE without a state, MTVD_ESIZE if count is
+ * too small, MTVD_ENONFINITE if the device flag is set. */
+int mtvd_profiles(mtvd_ctx* c, double* out, size_t count);
+
+/* Host only, no device work: the snapshot scalars of a profile array
+ * (count >= MTVD_NUM_PROFILES * p->nz) and, into each non-NULL array of
+ * p->nz doubles, T_sa(z) = <T>_A - (1 - D z), rho(z) - rho_A(z) with
+ * rho_A = (1 - D z)^(1/(gamma-1)), and U(z) = sqrt(<|u|^2>_A) (Sec. 4).
+ * MTVD_EINVAL on bad arguments, MTVD_ESIZE if count is too small. */
+int mtvd_analysis_from_profiles(const mtvd_params* p, const double* prof, size_t count,
+                                mtvd_analysis* out, double* tsa_z, double* drho_z,
+                                double* U_z);
+
+/* Host only: thermal boundary-layer thicknesses of a (time-averaged)
+ * profile tmean[k] = <T>_A(z_k), z_k = k/(nz-1) (Sec. 4: where the slope of
+ * <T>_A meets the adiabatic gradient -D).  With slopes taken between
+ * neighbouring rows, *lam_b is the height where, going up from z = 0, the
+ * slope first rises to -(1 + rtol) D (linear interpolation between the
+ * midpoints; half a cell if the first one already has), *lam_t the same
+ * from z = 1 down, measured from the top; -1 where it never does.
+ * MTVD_EINVAL on bad arguments (nz < 3, D <= 0, rtol < 0). */
+int mtvd_bl_thickness(const double* tmean, int32_t nz, double D, double rtol, double* lam_b,
+                      double* lam_t);
 
 /* Copy the current state to host memory in the canonical layout; count
  * must equal nf*nz*ny*nx.  Synchronises. */

@@ -99,6 +99,14 @@ class Params:
         return self.nx * (self.ny if self.ndim == 3 else 1) * self.nz
 
 
+class _Analysis(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in (
+        "Re", "C", "Fn", "Fp", "Fb", "Fv", "u2", "rho_uz_Tsa", "rho_uz2", "Tsa2")]
+
+
+# rows of Solver.profiles(), in order (the library's MTVD_NUM_PROFILES rows)
+PROFILE_NAMES = ("T", "rho", "u2", "rho_uz_Tsa", "rho_uz2", "Tsa2", "Fn", "Fp", "Fb", "Fv")
+
 _lib = None
 
 
@@ -109,6 +117,12 @@ def lib() -> ctypes.CDLL:
         if not os.path.exists(LIB_PATH):
             raise MtvdError(MTVD_EHIP, f"{LIB_PATH} is missing: run __graft_entry__.build() "
                                        "(or python paper_2411_10372_amd/build.py)")
+        # torch first: its HIP runtime and the one the library was linked
+        # against share the soname libamdhip64.so.7, and the process keeps
+        # whichever is loaded first for both.  Loading the library first
+        # would hand torch a runtime it was not built with (the GPU calls of
+        # both then fail).
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         P = ctypes.POINTER(_Params)
         vp = ctypes.c_void_p
@@ -166,6 +180,13 @@ def lib() -> ctypes.CDLL:
         L.mtvd_adj_destroy.argtypes = [vp]
         L.mtvd_adj_last_error.argtypes = [vp]
         L.mtvd_adj_last_error.restype = ctypes.c_char_p
+        L.mtvd_profiles.argtypes = [vp, dp, ctypes.c_size_t]
+        L.mtvd_analysis_from_profiles.argtypes = [P, dp, ctypes.c_size_t,
+                                                  ctypes.POINTER(_Analysis), dp, dp, dp]
+        L.mtvd_bl_thickness.argtypes = [dp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                        dp, dp]
+        for fn in ("mtvd_profiles", "mtvd_analysis_from_profiles", "mtvd_bl_thickness"):
+            getattr(L, fn).restype = ctypes.c_int
         for fn in ("mtvd_adj_bytes", "mtvd_adj_create", "mtvd_adj_bind", "mtvd_adj_forward",
                    "mtvd_adj_backward", "mtvd_adj_coef_grads", "mtvd_adj_destroy"):
             getattr(L, fn).restype = ctypes.c_int
@@ -182,6 +203,35 @@ def lib() -> ctypes.CDLL:
             getattr(L, fn).restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def analysis(p: Params, prof: np.ndarray) -> dict:
+    """Snapshot scalars (Re, C, volume means) and the derived profiles
+    T_sa(z), rho - rho_A(z), U(z) of a (10, nz) profile array."""
+    prof = np.ascontiguousarray(prof, dtype=np.float64)
+    a = _Analysis()
+    tsa, drho, U = (np.empty(p.nz, dtype=np.float64) for _ in range(3))
+    dp = ctypes.POINTER(ctypes.c_double)
+    pc = p._c()
+    rc = lib().mtvd_analysis_from_profiles(ctypes.byref(pc), prof.ctypes.data_as(dp), prof.size,
+                                           ctypes.byref(a), tsa.ctypes.data_as(dp),
+                                           drho.ctypes.data_as(dp), U.ctypes.data_as(dp))
+    if rc != MTVD_OK:
+        raise MtvdError(rc, lib().mtvd_strerror(rc).decode())
+    out = {n: getattr(a, n) for n, _ in _Analysis._fields_}
+    out.update(Tsa_z=tsa, drho_z=drho, U_z=U)
+    return out
+
+
+def bl_thickness(tmean, D: float, rtol: float = 0.1):
+    """(lambda_b, lambda_t) of a <T>_A profile; -1 where not found."""
+    t = np.ascontiguousarray(tmean, dtype=np.float64)
+    lb, lt = ctypes.c_double(), ctypes.c_double()
+    rc = lib().mtvd_bl_thickness(t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), t.size,
+                                 D, rtol, ctypes.byref(lb), ctypes.byref(lt))
+    if rc != MTVD_OK:
+        raise MtvdError(rc, lib().mtvd_strerror(rc).decode())
+    return lb.value, lt.value
 
 
 def state_bytes(p: Params):
@@ -249,6 +299,13 @@ class Solver:
             self._check(rc)
         out = {n: getattr(d, n) for n, _ in _Diag._fields_ if n != "tmean"}
         out["tmean"] = list(d.tmean)
+        return out
+
+    def profiles(self) -> np.ndarray:
+        """(10, nz) row means of the analysis quantities (PROFILE_NAMES)."""
+        out = np.empty((len(PROFILE_NAMES), self.p.nz), dtype=np.float64)
+        self._check(lib().mtvd_profiles(self.ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        out.size))
         return out
 
     def get_state(self) -> np.ndarray:

@@ -33,7 +33,7 @@ constexpr int kDiagOut = 32;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t shared, zrow, part, out, total;
+  size_t shared, zrow, part, out, ppart, pout, total;
   int diag_nb;  // blocks per row of the diagnostics reduction
 };
 
@@ -54,6 +54,10 @@ Layout layout_of(const mtvd_params* p) {
   off = align_up(off + sizeof(double) * (size_t)p->nz * (size_t)nb * kDiagVals);
   L.out = off;
   off = align_up(off + sizeof(double) * kDiagOut);
+  L.ppart = off;   // analysis row partials, then the row means
+  off = align_up(off + sizeof(double) * (size_t)p->nz * (size_t)nb * kNumProfiles);
+  L.pout = off;
+  off = align_up(off + sizeof(double) * (size_t)p->nz * kNumProfiles);
   L.total = off;
   return L;
 }
@@ -685,6 +689,23 @@ int mtvd_diagnostics(mtvd_ctx* c, mtvd_diag* out) {
   for (int i = 0; i < 6; ++i) out->tmean[i] = host[9 + i];
   out->flags = (int32_t)hs.flags;
   return hs.flags ? MTVD_ENONFINITE : MTVD_OK;
+}
+
+int mtvd_profiles(mtvd_ctx* c, double* out, size_t count) {
+  if (!c || !out) return MTVD_EINVAL;
+  if (!c->have_state) return set_err(c, MTVD_ESTATE, "no state");
+  const size_t n = (size_t)kNumProfiles * (size_t)c->c.nz;
+  if (count < n) return set_err(c, MTVD_ESIZE, "profile array too small");
+  double* part = (double*)(c->ws + c->L.ppart);
+  double* dout = (double*)(c->ws + c->L.pout);
+  hipError_t e = launch_profiles(c->c, zrow_of(c), c->buf[c->cur], part, c->L.diag_nb, dout,
+                                 c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "profiles launch");
+  HIPCHK(c, hipMemcpyAsync(out, dout, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+  unsigned int flags = 0;
+  int rc = read_flags(c, &flags);
+  if (rc) return rc;
+  return flags ? MTVD_ENONFINITE : MTVD_OK;
 }
 
 int mtvd_get_state(mtvd_ctx* c, double* host, size_t count) {

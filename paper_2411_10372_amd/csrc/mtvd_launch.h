@@ -45,4 +45,10 @@ hipError_t launch_init_theta(const Coef& c, const double* zr, const double* thet
 hipError_t launch_grad_theta(const Coef& c, const double* X0, const double* xb, double* gt,
                              hipStream_t s);
 
+// analysis row means (Sec. 4): out[q nz + k], q < kNumProfiles, from
+// per-segment partials part[nz][nb][kNumProfiles]
+constexpr int kNumProfiles = 10;
+hipError_t launch_profiles(const Coef& c, const double* zr, const double* X, double* part,
+                           int nb, double* out, hipStream_t s);
+
 }  // namespace mtvd

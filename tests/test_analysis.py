@@ -1,0 +1,142 @@
+"""The analysis quantities of Sec. 4 through the C-ABI, against the oracle
+(oracle/analysis.py).
+
+Host-only functions of the library (snapshot scalars from a profile array,
+boundary-layer thicknesses) run on the CPU: their inputs come from the
+oracle.  The device row means (mtvd_profiles) are GPU tests, on states the
+oracle makes (perturbed by the seeded generator of tests/inputs.py), in 2D
+and 3D, at small sizes spanning several blocks and ragged row segments and
+at the headline 4096x1024 size.
+
+Bars: a row mean is a sum of n node values in a different order on the two
+sides (tree on the device, pairwise in numpy) and each node value may
+differ by a few ulps (contraction of a*b + c on the device), so each row is
+compared against 1e-12 times the mean of the absolute node values of that
+row (the oracle's second output) -- a relative error of 1e-12 of the
+scale, ~1e4 ulps, room for log2(n) rounding steps of the sums and for the
+cancellation inside the difference stencils (second differences divide
+values of size |u| by h^2).  Host scalars: 1e-13 relative (a few roundings
+of sequential vs pairwise sums over nz rows).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2411_10372_amd as mtvd
+from oracle import analysis as an
+from helpers import both, gpu_or_skip
+from inputs import perturb
+
+
+def _oracle_state(po, steps, seed):
+    X = oracle.init(po)
+    if steps:
+        X, _, _ = oracle.step(po, X, steps)
+    return perturb(X, seed=seed, amp=0.02)
+
+
+# ---- host-only functions (CPU) ------------------------------------------------
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_host_analysis_matches_oracle(ndim):
+    kw = dict(ndim=ndim, nx=48, nz=17, ny=16 if ndim == 3 else 1, Ra=1e5, Pr=0.7, seed=3)
+    po, pg = both(**kw)
+    prof, _ = an.profiles(po, _oracle_state(po, 0, seed=11))
+    want = an.analysis(po, prof)
+    got = mtvd.analysis(pg, prof)
+    for k in ("Re", "C", "Fn", "Fp", "Fb", "Fv", "u2", "rho_uz_Tsa", "rho_uz2", "Tsa2"):
+        assert abs(got[k] - want[k]) <= 1e-13 * max(abs(want[k]), 1e-300), (k, got[k], want[k])
+    for k in ("Tsa_z", "drho_z", "U_z"):
+        assert np.max(np.abs(got[k] - want[k])) <= 1e-14 * max(1.0, np.max(np.abs(want[k]))), k
+
+
+def test_host_bl_thickness_matches_oracle():
+    D = 0.4
+    for nz, (Ab, db, At, dt), r in (((129, (6.0, 0.02, 3.0, 0.05), 0.1)),
+                                    ((257, (2.0, 0.05, 8.0, 0.01), 0.25)),
+                                    ((65, (0.01, 0.1, 0.01, 0.1), 0.1))):
+        z = np.arange(nz) / (nz - 1)
+        t = 1.0 - D * z - Ab * db * (1.0 - np.exp(-z / db)) + At * dt * (1.0 - np.exp(-(1.0 - z) / dt))
+        want = an.bl_thickness(t, D, r)
+        got = mtvd.bl_thickness(t, D, r)
+        assert abs(got[0] - want[0]) <= 1e-14 and abs(got[1] - want[1]) <= 1e-14, (nz, got, want)
+    with pytest.raises(mtvd.MtvdError):
+        mtvd.bl_thickness(np.zeros(2), D)
+    with pytest.raises(mtvd.MtvdError):
+        mtvd.bl_thickness(np.zeros(9), -1.0)
+
+
+# ---- device row means (GPU) ---------------------------------------------------
+
+def _check_profiles(got, want, scale, label):
+    for q, name in enumerate(mtvd.PROFILE_NAMES):
+        bar = 1e-12 * np.maximum(scale[q], 1e-300)
+        err = np.abs(got[q] - want[q])
+        worst = int(np.argmax(err / bar))
+        assert np.all(err <= bar), (label, name, worst, got[q][worst], want[q][worst],
+                                    float(np.max(err / bar)))
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", [
+    dict(ndim=2, nx=256, nz=64, steps=40, Ra=1e6),
+    dict(ndim=2, nx=8200, nz=9, steps=0, Ra=1e10),   # 3 ragged segments per row
+    dict(ndim=3, nx=40, ny=24, nz=17, steps=4, Ra=1e6),
+    dict(ndim=3, nx=96, ny=72, nz=9, steps=0, Ra=1e6),   # 2 segments per row
+])
+def test_profiles_match_oracle(case):
+    gpu_or_skip()
+    case = dict(case)
+    steps = case.pop("steps")
+    kw = dict(case, Pr=0.7, seed=2)
+    if kw["ndim"] == 2:
+        kw["ny"] = 1
+    po, pg = both(**kw)
+    X = _oracle_state(po, steps, seed=21)
+    want, scale = an.profiles(po, X)
+    print(f"[case] profiles {case} steps={steps}", flush=True)
+    s = mtvd.Solver(pg)
+    s.set_state(X)
+    got = s.profiles()
+    s.close()
+    _check_profiles(got, want, scale, case)
+
+
+@pytest.mark.gpu
+def test_profiles_at_the_headline_size():
+    # 4096 x 1024, a perturbed initial state
+    gpu_or_skip()
+    kw = dict(ndim=2, nx=4096, nz=1024, Ra=1e10, Pr=1.0, seed=1)
+    po, pg = both(**kw)
+    X = _oracle_state(po, 0, seed=31)
+    want, scale = an.profiles(po, X)
+    print("[case] profiles 4096x1024", flush=True)
+    s = mtvd.Solver(pg)
+    s.set_state(X)
+    got = s.profiles()
+    s.close()
+    _check_profiles(got, want, scale, "4096x1024")
+
+
+@pytest.mark.gpu
+def test_profiles_of_a_running_simulation_are_consistent():
+    # on the solver's own state after some steps: F_b = g <rho>, |u|^2 >= 0,
+    # and the derived scalars agree with the oracle's formulas on the same rows
+    gpu_or_skip()
+    kw = dict(ndim=2, nx=256, nz=64, Ra=1e6, Pr=1.0, seed=0)
+    po, pg = both(**kw)
+    s = mtvd.Solver(pg)
+    s.init_state()
+    s.step(100)
+    prof = s.profiles()
+    d = s.diagnostics()
+    s.close()
+    g = 1.0 / po.eps
+    assert np.max(np.abs(prof[8] - g * prof[1])) <= 1e-13 * g * np.max(prof[1])
+    assert np.all(prof[2] >= 0.0)
+    A = mtvd.analysis(pg, prof)
+    W = an.analysis(po, prof)
+    assert abs(A["Re"] - W["Re"]) <= 1e-13 * W["Re"]
+    # the rows the Nusselt diagnostic reads are the same row means of T
+    rows = [0, 1, 2, po.nz - 3, po.nz - 2, po.nz - 1]
+    assert np.max(np.abs(prof[0][rows] - np.array(d["tmean"]))) <= 1e-13
