@@ -96,14 +96,14 @@ typedef struct mtvd_diag {
                             non-positive rho/T seen) */
 } mtvd_diag;
 
-/* Snapshot scalars of the analysis of Sec. 4 (and Re of Sec. 2), made on
+/* Snapshot scalars of the analysis of Secs. 4-6 (and Re of Sec. 2), made on
  * the host from the row means of mtvd_profiles; volume means <.>_V use the
  * trapezoid rule in z over a box of height 1. */
 typedef struct mtvd_analysis {
   double Re;             /* sqrt(Ra/Pr) sqrt(<|u|^2>_V) (Sec. 2, Eq. Re) */
   double C;              /* <rho u_z T_sa>_V / sqrt(<(rho u_z)^2>_V <T_sa^2>_V),
-                            0 when either factor is 0 (Sec. 4, C(Ra)) */
-  double Fn, Fp, Fb, Fv; /* <F>_V of the z-momentum terms (Sec. 4) */
+                            0 when either factor is 0 (Sec. 6.2, C(Ra)) */
+  double Fn, Fp, Fb, Fv; /* <F>_V of the z-momentum terms (Sec. 6.1) */
   double u2, rho_uz_Tsa, rho_uz2, Tsa2;   /* <.>_V of the inputs above */
 } mtvd_analysis;
 
@@ -154,7 +154,7 @@ int mtvd_sweep(mtvd_ctx* c, int32_t axis);
 int mtvd_diagnostics(mtvd_ctx* c, mtvd_diag* out);
 
 /* Row means <.>_A (over the nx x ny nodes of each row k) of the ten node
- * quantities listed with MTVD_NUM_PROFILES, for the analysis of Sec. 4
+ * quantities listed with MTVD_NUM_PROFILES, for the analysis of Secs. 4-6
  * (profiles T_sa(z), rho - rho_A(z), U(z), the correlation C(Ra), the
  * z-momentum balance F_n, F_p, F_b, F_v) and Re (Sec. 2).  Derivatives:
  * central second order along x, y and inside; second-order one-sided on
@@ -170,14 +170,14 @@ int mtvd_profiles(mtvd_ctx* c, double* out, size_t count);
 /* Host only, no device work: the snapshot scalars of a profile array
  * (count >= MTVD_NUM_PROFILES * p->nz) and, into each non-NULL array of
  * p->nz doubles, T_sa(z) = <T>_A - (1 - D z), rho(z) - rho_A(z) with
- * rho_A = (1 - D z)^(1/(gamma-1)), and U(z) = sqrt(<|u|^2>_A) (Sec. 4).
+ * rho_A = (1 - D z)^(1/(gamma-1)), and U(z) = sqrt(<|u|^2>_A) (Sec. 5).
  * MTVD_EINVAL on bad arguments, MTVD_ESIZE if count is too small. */
 int mtvd_analysis_from_profiles(const mtvd_params* p, const double* prof, size_t count,
                                 mtvd_analysis* out, double* tsa_z, double* drho_z,
                                 double* U_z);
 
 /* Host only: thermal boundary-layer thicknesses of a (time-averaged)
- * profile tmean[k] = <T>_A(z_k), z_k = k/(nz-1) (Sec. 4: where the slope of
+ * profile tmean[k] = <T>_A(z_k), z_k = k/(nz-1) (Sec. 5: where the slope of
  * <T>_A meets the adiabatic gradient -D).  With slopes taken between
  * neighbouring rows, *lam_b is the height where, going up from z = 0, the
  * slope first rises to -(1 + rtol) D (linear interpolation between the

@@ -1,4 +1,4 @@
-"""Plain CPU FP64 oracle of the analysis quantities of the paper's Sec. 4.
+"""Plain CPU FP64 oracle of the analysis quantities of the paper's Secs. 4-6.
 
 TEST INFRASTRUCTURE ONLY (as the rest of ``oracle/``): only ``tests/`` may
 import it.  Plain numpy, one formula per quantity, no blocking or fusion.
@@ -7,14 +7,14 @@ Paper: Tiwari, Sharma & Verma, arXiv:2411.10372.
   Sec. 2, Eq. (Re): Re = sqrt(Ra/Pr) U, U the rms velocity of a snapshot;
       the adiabatic profiles T_A(z) = 1 - D z, rho_A(z) = (1 - D z)^beta with
       beta = 1/(gamma - 1); T_sa = T - T_A.
-  Sec. 4 (flow structures and boundary layers): horizontally averaged
+  Secs. 4-5 (adiabatic profile, boundary layers): horizontally averaged
       profiles <T>_A(z), T_sa(z), rho - rho_A(z) and the rms velocity U(z);
       the boundary-layer thicknesses lambda_b, lambda_t where the slope of
       <T>_A meets the adiabatic gradient -D.
-  Sec. 4 (momentum balance): z components F_n = rho (u . grad) u_z,
+  Sec. 6.1 (Re scaling, momentum balance): z components F_n = rho (u . grad) u_z,
       F_p = -dp/dz, F_b = rho g (g = 1/eps in these units: the momentum
       equation's source is -rho/eps), F_v = d_i tau_iz, volume averaged.
-  Sec. 4 (Nusselt scaling): the correlation
+  Sec. 6.2 (Nu scaling): the correlation
       C = <rho u_z T_sa> / sqrt(<(rho u_z)^2> <T_sa^2>).
 
 Readings where the paper is silent (listed with the others in the design
@@ -167,7 +167,7 @@ def volume_mean(prof_row):
 
 
 def analysis(p, prof):
-    """Snapshot scalars of Sec. 4 from the (10, nz) profile array: Re, the
+    """Snapshot scalars of Secs. 2 and 4-6 from the (10, nz) profile array: Re, the
     correlation C, the volume means of F_n, F_p, F_b, F_v and of the
     correlation's three inputs, and the derived profiles T_sa(z),
     rho - rho_A(z), U(z)."""

@@ -1,9 +1,10 @@
-// mtvd_analysis.hip -- the analysis quantities of the paper's Sec. 4 as
+// mtvd_analysis.hip -- the analysis quantities of the paper's Secs. 4-6 as
 // row means on the device: <T>_A, <rho>_A, <|u|^2>_A, <rho u_z T_sa>_A,
 // <(rho u_z)^2>_A, <T_sa^2>_A and the z-momentum terms F_n = rho (u.grad)
 // u_z, F_p = -dp/dz, F_b = rho g, F_v = d_i tau_iz; and, on the host, the
-// snapshot scalars made from them (Re, Sec. 2; the correlation C and the
-// volume means, Sec. 4) and the boundary-layer thicknesses of a profile.
+// snapshot scalars made from them (Re, Sec. 2; the correlation C, Sec.
+// 6.2; the volume means of the momentum terms, Sec. 6.1) and the
+// boundary-layer thicknesses of a profile (Sec. 5).
 //
 // Discretisation (the paper gives none for these diagnostics): central
 // second-order differences along x, y (periodic) and on interior rows;
@@ -15,7 +16,8 @@
 // d_i tau_iz for the constant mu of these units.
 //
 // Paper: Tiwari, Sharma & Verma, arXiv:2411.10372, Sec. 2 (Re, T_A, rho_A)
-// and Sec. 4 (profiles, boundary layers, momentum balance, C(Ra)).
+// Secs. 4-5 (profiles, boundary layers), Sec. 6.1 (momentum balance) and
+// Sec. 6.2 (C(Ra)).
 #include <math.h>
 
 #include "../../include/mtvd.h"
@@ -206,7 +208,7 @@ int mtvd_analysis_from_profiles(const mtvd_params* p, const double* prof, size_t
   out->Fv = V[9];
   // Re = sqrt(Ra/Pr) U with U the rms velocity (Sec. 2)
   out->Re = sqrt(p->Ra / p->Pr) * sqrt(V[2]);
-  // C = <rho u_z T_sa> / sqrt(<(rho u_z)^2> <T_sa^2>) (Sec. 4)
+  // C = <rho u_z T_sa> / sqrt(<(rho u_z)^2> <T_sa^2>) (Sec. 6.2)
   const double den = sqrt(V[4] * V[5]);
   out->C = den > 0.0 ? V[3] / den : 0.0;
   const double beta = 1.0 / (p->gamma - 1.0);

@@ -1,9 +1,9 @@
 """Long runs to a statistically steady state and their time averages.
 
 The quantities are those the paper reports for its runs (Sec. 2: Nu-bar,
-the bulk Nu with Nu_conv and Nu_K, Re; Sec. 4: the correlation C, the
-z-momentum balance, the profiles T_sa(z), rho - rho_A(z), U(z) and the
-boundary-layer thicknesses).  Every number comes from the library's
+the bulk Nu with Nu_conv and Nu_K, Re; Secs. 4-6: the profiles T_sa(z),
+rho - rho_A(z), U(z), the boundary-layer thicknesses, the z-momentum
+balance and the correlation C).  Every number comes from the library's
 diagnostics and analysis entry points; this module only steps the solver,
 samples snapshots and averages them over time.  The mean of each scalar
 comes with the standard error of five consecutive block means.
@@ -14,8 +14,8 @@ Command line (one JSON line on stdout, progress on stderr):
         --aspect 2 --gamma 5/3 --D 0.49 --Ra 1e6 --t0 50 --t1 150
 
 Paper: Tiwari, Sharma & Verma, arXiv:2411.10372, Sec. 2 (Nu, Re), Sec. 3.3
-(validation runs, Tables 1 and 2), Sec. 4 (profiles, boundary layers,
-momentum balance, C(Ra)).
+(validation runs, Tables 1 and 2), Secs. 4-5 (profiles, boundary layers),
+Sec. 6 (momentum balance, C(Ra)).
 """
 from __future__ import annotations
 

@@ -1,4 +1,4 @@
-"""The analysis quantities of Sec. 4 through the C-ABI, against the oracle
+"""The analysis quantities of Secs. 4-6 through the C-ABI, against the oracle
 (oracle/analysis.py).
 
 Host-only functions of the library (snapshot scalars from a profile array,

@@ -8,7 +8,7 @@ fluctuate, Nu-bar and the bulk Nu are 1 up to that error, the pressure
 gradient balances gravity (F_p = F_b), and the residual Re falls at about
 second order when the grid is refined (9 -> 17 rows: at least 3x).
 
-Paper: arXiv:2411.10372, Sec. 2 (Nu, Re), Sec. 4 (momentum balance).
+Paper: arXiv:2411.10372, Sec. 2 (Nu, Re), Sec. 6.1 (momentum balance).
 """
 import math
 

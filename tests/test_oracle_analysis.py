@@ -4,8 +4,9 @@ fields with known derivatives (second-order convergence), the limits of a
 correlation coefficient, the Reynolds number of a uniform flow and a
 boundary-layer profile whose crossing height is known in closed form.
 
-Paper: arXiv:2411.10372, Sec. 2 (Re, adiabatic profiles) and Sec. 4
-(profiles, boundary layers, momentum balance, correlation C).
+Paper: arXiv:2411.10372, Sec. 2 (Re, adiabatic profiles), Secs. 4-5
+(profiles, boundary layers), Sec. 6.1 (momentum balance), Sec. 6.2
+(correlation C).
 """
 import numpy as np
 import pytest
