@@ -276,3 +276,19 @@ def test_errors_are_reported_not_crashes():
     s.sync()
     with pytest.raises(ValueError):
         s.set_state(X[:, :-1])
+
+
+@pytest.mark.parametrize("axis", [0, 2])
+def test_2d_results_do_not_depend_on_the_tiling(axis):
+    # as in 3D: 2-row and 64-row chunks give the same bits
+    po, pg = both(nx=300, nz=65, Ra=1e6, seed=4)
+    X0 = perturb(oracle.init(po), seed=78, amp=0.03)
+    out = []
+    for rows in (2, 64):
+        _say("tiling2d", axis, rows)
+        s = _solver(pg, (rows, rows))
+        s.set_state(X0)
+        s.sweep(axis)
+        out.append(s.get_state())
+        s.close()
+    assert np.array_equal(out[0], out[1]), float(np.max(np.abs(out[0] - out[1])))

@@ -137,3 +137,29 @@ def test_3d_full_size_one_step_sampled():
         got = Xg[:, :, jj][:, :, :, ii].cpu().numpy()
         e = parity_error(got, ref, po)
         assert e <= TOL, (i0, j0, e)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_3d_results_do_not_depend_on_the_tiling(axis):
+    # rows per wave only change which wave computes a node: one operator
+    # with 4-row chunks and with 32-row chunks (every chunk touches a plate).
+    # L_x and L_y agree bit for bit.  L_z runs the chunks clear of the plates
+    # in a separately compiled copy whose fused multiply-adds can round
+    # differently, so there the two agree to rounding: 1e-15 of each field's
+    # scale (a few ulps, far below the 1e-13 parity bar)
+    po, pg = both(ndim=3, nx=70, ny=24, nz=33, Ra=1e6, seed=4)
+    X0 = perturb(oracle.init(po), seed=77, amp=0.03)
+    out = []
+    for rows in (4, 32):
+        _say("tiling3d", axis, rows)
+        s = _solver(pg, (rows, rows))
+        s.set_state(X0)
+        s.sweep(axis)
+        out.append(s.get_state())
+        s.close()
+    if axis != 2:
+        assert np.array_equal(out[0], out[1]), float(np.max(np.abs(out[0] - out[1])))
+    else:
+        e = parity_error(out[0], out[1], po)
+        _say("tiling3d L_z difference", e)
+        assert e <= 1e-15, e
