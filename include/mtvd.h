@@ -282,9 +282,11 @@ const char* mtvd_batch_last_error(const mtvd_batch* b);
  * sqrt(Ra Pr)); dt and the initial density do not depend on theta or Ra.
  * The reverse of each directional operator is hand-written stage by stage;
  * at a kink of max/min/abs/phi it takes the branch the forward pass took.
- * Memory: checkpoints every `every` steps, and one interval's operator
- * inputs (4 every states) recomputed during the backward pass, plus about 54
- * doubles per node of stage arrays (mtvd_adj_bytes gives the total).
+ * Memory: checkpoints every `every` steps, and two intervals' operator
+ * inputs (2 x 4 every states: the backward pass recomputes the next interval
+ * on a second stream of its own, default priority, while it reverses the
+ * current one), plus about 54 doubles per node of stage arrays
+ * (mtvd_adj_bytes gives the total).
  * Restrictions: ndim = 2 and limiter_form = 0 (MTVD_EINVAL otherwise);
  * dt_mode is ignored (dt is always frozen).
  */
@@ -294,7 +296,9 @@ typedef struct mtvd_adj mtvd_adj;
  * `every` >= 1 steps (clamped to nsteps). */
 int mtvd_adj_bytes(const mtvd_params* p, int32_t nsteps, int32_t every,
                    size_t* workspace_bytes);
-/* Validate and create (no device work); stream as mtvd_create. */
+/* Validate and create (no device work; creates the second stream and its
+ * events on the current device, MTVD_EHIP if that fails); stream as
+ * mtvd_create. */
 int mtvd_adj_create(const mtvd_params* p, int32_t nsteps, int32_t every, void* hip_stream,
                     mtvd_adj** out);
 /* Attach a caller-owned, 256-byte aligned device workspace of at least

@@ -1361,8 +1361,10 @@ struct mtvd_adj {
   adj::AC ac;
   int nsteps, every, nseg, kc;
   hipStream_t stream;
+  hipStream_t side;       // recomputes the next segment while one is reversed
+  hipEvent_t rec_done[2], rev_done[2];
   unsigned char* ws;
-  double *zr, *acc, *ckpt, *segs, *tmp[2], *cot[2];
+  double *zr, *acc, *ckpt, *segs[2], *tmp[2], *cot[2];
   Shared* sh;
   adj::Arr A;
   size_t total;
@@ -1399,7 +1401,8 @@ size_t adj_layout(mtvd_adj* a, unsigned char* base) {
   a->zr = (double*)take(sizeof(double) * a->c.nz);
   a->acc = (double*)take(sizeof(double) * 8);
   a->ckpt = (double*)take(S * a->nseg);
-  a->segs = (double*)take(S * 4 * (size_t)a->every);
+  // two segment buffers: one is reversed while the other is recomputed
+  for (int q = 0; q < 2; ++q) a->segs[q] = (double*)take(S * 4 * (size_t)a->every);
   for (int q = 0; q < 2; ++q) a->tmp[q] = (double*)take(S);
   for (int q = 0; q < 2; ++q) a->cot[q] = (double*)take(S);
   adj::Arr& A = a->A;
@@ -1512,6 +1515,18 @@ int mtvd_adj_create(const mtvd_params* p, int32_t nsteps, int32_t every, void* h
   adj_shape(a, p, nsteps, every);
   a->total = adj_layout(a, nullptr);
   a->stream = (hipStream_t)hip_stream;
+  a->side = nullptr;
+  for (int q = 0; q < 2; ++q) a->rec_done[q] = a->rev_done[q] = nullptr;
+  // default priority, as the caller's stream; events without timing
+  bool ok = hipStreamCreateWithFlags(&a->side, hipStreamNonBlocking) == hipSuccess;
+  for (int q = 0; q < 2 && ok; ++q)
+    ok = hipEventCreateWithFlags(&a->rec_done[q], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&a->rev_done[q], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    mtvd_adj_destroy(a);
+    fprintf(stderr, "mtvd_adj_create: stream or event creation failed\n");
+    return MTVD_EHIP;
+  }
   a->ws = nullptr;
   a->bound = a->have_fwd = a->have_bwd = false;
   a->gmu = a->gK = 0.0;
@@ -1587,18 +1602,44 @@ int mtvd_adj_backward(mtvd_adj* a, double Jbar, double* grad_x0, double* grad_th
   AHIP(a, launch_fill(a->A.MU, cnt, 0.0, a->stream));
   AHIP(a, launch_fill(a->A.KB, cnt, 0.0, a->stream));
   AHIP(a, launch_fill(a->acc + 1, 1, 0.0, a->stream));
-  int cur = 0;   // cot[cur] holds the running cotangent
-  for (int seg = a->nseg - 1; seg >= 0; --seg) {
+  // Segment seg's 4m operator inputs are recomputed from its checkpoint
+  // into segs[b] on the side stream while the main stream reverses the
+  // segment after it from segs[b ^ 1]; events order each buffer's
+  // recompute before its reverse and its reverse before its next recompute.
+  auto seg_len = [&](int seg) {
     const int s0 = seg * a->every;
-    const int m = (a->nsteps - s0 < a->every) ? a->nsteps - s0 : a->every;
-    double* base = a->ckpt + S * seg;
-    auto state = [&](int q) -> double* { return q == 0 ? base : a->segs + S * (size_t)(q - 1); };
+    return (a->nsteps - s0 < a->every) ? a->nsteps - s0 : a->every;
+  };
+  auto recompute = [&](int seg, int b) -> hipError_t {
+    const double* base = a->ckpt + S * seg;
+    const int m = seg_len(seg);
     for (int j = 0; j < m; ++j)
       for (int s = 0; s < 4; ++s) {
-        hipError_t e = launch_sweep_2d(o[s], a->c, a->sh, a->zr, 0, 0, false, state(4 * j + s),
-                                       state(4 * j + s + 1), a->kc, a->stream);
-        AHIP(a, e);
+        const int q = 4 * j + s;
+        const double* in = q == 0 ? base : a->segs[b] + S * (size_t)(q - 1);
+        hipError_t e = launch_sweep_2d(o[s], a->c, a->sh, a->zr, 0, 0, false, in,
+                                       a->segs[b] + S * (size_t)q, a->kc, a->side);
+        if (e != hipSuccess) return e;
       }
+    return hipEventRecord(a->rec_done[b], a->side);
+  };
+  // the side stream starts after everything the caller queued before
+  AHIP(a, hipEventRecord(a->rev_done[0], a->stream));
+  AHIP(a, hipEventRecord(a->rev_done[1], a->stream));
+  AHIP(a, hipStreamWaitEvent(a->side, a->rev_done[0], 0));
+  AHIP(a, recompute(a->nseg - 1, 0));
+  int cur = 0;   // cot[cur] holds the running cotangent
+  for (int seg = a->nseg - 1; seg >= 0; --seg) {
+    const int b = (a->nseg - 1 - seg) & 1;
+    if (seg >= 1) {
+      AHIP(a, hipStreamWaitEvent(a->side, a->rev_done[b ^ 1], 0));
+      AHIP(a, recompute(seg - 1, b ^ 1));
+    }
+    AHIP(a, hipStreamWaitEvent(a->stream, a->rec_done[b], 0));
+    const int s0 = seg * a->every;
+    const int m = seg_len(seg);
+    double* base = a->ckpt + S * seg;
+    auto state = [&](int q) -> double* { return q == 0 ? base : a->segs[b] + S * (size_t)(q - 1); };
     for (int j = m - 1; j >= 0; --j) {
       const int n = s0 + j + 1;   // the step maps X_{n-1} to X_n
       if (n == a->nsteps) {
@@ -1616,6 +1657,7 @@ int mtvd_adj_backward(mtvd_adj* a, double Jbar, double* grad_x0, double* grad_th
       if (n - 1 >= 1)
         AHIP(a, launch_nu_vjp(a->ac, a->c, a->zr, state(4 * j), w, a->cot[cur], a->stream));
     }
+    AHIP(a, hipEventRecord(a->rev_done[b], a->stream));
   }
   if (grad_x0)
     AHIP(a, hipMemcpyAsync(grad_x0, a->cot[cur], sizeof(double) * S, hipMemcpyDeviceToDevice,
@@ -1648,6 +1690,15 @@ int mtvd_adj_coef_grads(const mtvd_adj* a, double* grad_mu, double* grad_K) {
 }
 
 int mtvd_adj_destroy(mtvd_adj* a) {
+  if (!a) return MTVD_OK;
+  if (a->side) {
+    (void)hipStreamSynchronize(a->side);
+    (void)hipStreamDestroy(a->side);
+  }
+  for (int q = 0; q < 2; ++q) {
+    if (a->rec_done[q]) (void)hipEventDestroy(a->rec_done[q]);
+    if (a->rev_done[q]) (void)hipEventDestroy(a->rev_done[q]);
+  }
   delete a;
   return MTVD_OK;
 }
