@@ -282,11 +282,12 @@ const char* mtvd_batch_last_error(const mtvd_batch* b);
  * sqrt(Ra Pr)); dt and the initial density do not depend on theta or Ra.
  * The reverse of each directional operator is hand-written stage by stage;
  * at a kink of max/min/abs/phi it takes the branch the forward pass took.
- * Memory: checkpoints every `every` steps, and two intervals' operator
- * inputs (2 x 4 every states: the backward pass recomputes the next interval
- * on a second stream of its own, default priority, while it reverses the
- * current one), plus about 54 doubles per node of stage arrays
- * (mtvd_adj_bytes gives the total).
+ * Memory: checkpoints every `every` steps; for two intervals the operator
+ * inputs (2 x 4 every states) and forward values (2 x 4 every x 13 doubles
+ * per node: the backward pass recomputes the next interval, and its
+ * operators' forward values, on a second stream of its own, default
+ * priority, while it reverses the current one); about 41 doubles per node
+ * of stage arrays (mtvd_adj_bytes gives the total).
  * Restrictions: ndim = 2 and limiter_form = 0 (MTVD_EINVAL otherwise);
  * dt_mode is ignored (dt is always frozen).
  */

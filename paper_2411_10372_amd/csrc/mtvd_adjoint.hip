@@ -181,19 +181,30 @@ unsigned blocks_for(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
-hipError_t launch_adj_sweep(int axis, const AC& c0, const Arr& A, const Shared* sh,
-                            hipStream_t s) {
+hipError_t launch_adj_fw(int axis, const AC& c0, const Arr& A, const Shared* sh,
+                         hipStream_t s) {
+  AC c = c0;
+  c.axis = axis;
+  c.iha = axis == 0 ? c.ihx : c.ihz;
+  const unsigned g = blocks_for(c.cnt, kBlk);
+  if (axis == 0)
+    adj_stage<kFwAll, 0><<<g, kBlk, 0, s>>>(c, A, sh);
+  else
+    adj_stage<kFwAll, 2><<<g, kBlk, 0, s>>>(c, A, sh);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_rev(int axis, const AC& c0, const Arr& A, const Shared* sh,
+                          hipStream_t s) {
   AC c = c0;
   c.axis = axis;
   c.iha = axis == 0 ? c.ihx : c.ihz;
   const unsigned g = blocks_for(c.cnt, kBlk);
   if (axis == 0) {
-    adj_stage<kFwAll, 0><<<g, kBlk, 0, s>>>(c, A, sh);
     adj_stage<kRvTc, 0><<<g, kBlk, 0, s>>>(c, A, sh);
     adj_stage<kRvPred, 0><<<g, kBlk, 0, s>>>(c, A, sh);
     adj_stage<kRvPrim, 0><<<g, kBlk, 0, s>>>(c, A, sh);
   } else {
-    adj_stage<kFwAll, 2><<<g, kBlk, 0, s>>>(c, A, sh);
     adj_stage<kRvTc, 2><<<g, kBlk, 0, s>>>(c, A, sh);
     adj_stage<kRvPred, 2><<<g, kBlk, 0, s>>>(c, A, sh);
     adj_stage<kRvPrim, 2><<<g, kBlk, 0, s>>>(c, A, sh);

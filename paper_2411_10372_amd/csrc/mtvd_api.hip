@@ -1364,7 +1364,7 @@ struct mtvd_adj {
   hipStream_t side;       // recomputes the next segment while one is reversed
   hipEvent_t rec_done[2], rev_done[2];
   unsigned char* ws;
-  double *zr, *acc, *ckpt, *segs[2], *tmp[2], *cot[2];
+  double *zr, *acc, *ckpt, *segs[2], *fw[2], *tmp[2], *cot[2];
   Shared* sh;
   adj::Arr A;
   size_t total;
@@ -1387,6 +1387,18 @@ int aerr(mtvd_adj* a, int code, const std::string& what) {
       return aerr(a, MTVD_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+constexpr size_t kFwDoubles = 13;   // P (4), S (1), XP (4), PP (4) per node
+
+// the forward-value arrays of operator q of an interval in buffer b
+void fw_slice(const mtvd_adj* a, int b, int q, adj::Arr* A) {
+  const size_t one = (size_t)a->c.cnt;
+  double* base = a->fw[b] + kFwDoubles * one * (size_t)q;
+  A->P = base;
+  A->XP = base + 4 * one;
+  A->PP = base + 8 * one;
+  A->S = base + 12 * one;
+}
+
 // byte offsets of the adjoint workspace (or, with base set, its pointers)
 size_t adj_layout(mtvd_adj* a, unsigned char* base) {
   const long long cnt = a->c.cnt;
@@ -1405,16 +1417,17 @@ size_t adj_layout(mtvd_adj* a, unsigned char* base) {
   for (int q = 0; q < 2; ++q) a->segs[q] = (double*)take(S * 4 * (size_t)a->every);
   for (int q = 0; q < 2; ++q) a->tmp[q] = (double*)take(S);
   for (int q = 0; q < 2; ++q) a->cot[q] = (double*)take(S);
+  // forward values (P, S, XP, PP: 13 doubles per node) of every operator of
+  // an interval, computed on the side stream after its recompute
+  for (int q = 0; q < 2; ++q)
+    a->fw[q] = (double*)take(kFwDoubles * one * 4 * (size_t)a->every);
   adj::Arr& A = a->A;
-  A.P = (double*)take(S);
-  A.XP = (double*)take(S);
-  A.PP = (double*)take(S);
+  A.P = A.XP = A.PP = A.S = nullptr;   // set per operator (fw_slice)
   A.XPb = (double*)take(S);
   A.PPb = (double*)take(S);
   A.PB = (double*)take(S);
   A.DPb = (double*)take(5 * one);
   A.DB = (double*)take(5 * one);
-  A.S = (double*)take(one);
   A.SB = (double*)take(one);
   A.MU = (double*)take(one);
   A.KB = (double*)take(one);
@@ -1620,6 +1633,12 @@ int mtvd_adj_backward(mtvd_adj* a, double Jbar, double* grad_x0, double* grad_th
         hipError_t e = launch_sweep_2d(o[s], a->c, a->sh, a->zr, 0, 0, false, in,
                                        a->segs[b] + S * (size_t)q, a->kc, a->side);
         if (e != hipSuccess) return e;
+        // the operator's forward values, which need no cotangent
+        adj::Arr A = a->A;
+        A.X = in;
+        fw_slice(a, b, q, &A);
+        e = launch_adj_fw(o[s], a->ac, A, a->sh, a->side);
+        if (e != hipSuccess) return e;
       }
     return hipEventRecord(a->rec_done[b], a->side);
   };
@@ -1649,9 +1668,10 @@ int mtvd_adj_backward(mtvd_adj* a, double Jbar, double* grad_x0, double* grad_th
       for (int s = 3; s >= 0; --s) {
         adj::Arr A = a->A;
         A.X = state(4 * j + s);
+        fw_slice(a, b, 4 * j + s, &A);
         A.Yb = a->cot[cur];
         A.Xb = a->cot[cur ^ 1];
-        AHIP(a, launch_adj_sweep(o[s], a->ac, A, a->sh, a->stream));
+        AHIP(a, launch_adj_rev(o[s], a->ac, A, a->sh, a->stream));
         cur ^= 1;
       }
       if (n - 1 >= 1)

@@ -27,10 +27,14 @@ hipError_t launch_sweep_3d(int axis, const Coef& c, Shared* sh, const double* zr
                            int first, bool fuse, const double* X, double* Y, int kc,
                            hipStream_t s);
 
-// reverse of one 2D operator L_axis(dt_frozen/2) at A.X: A.Xb = J^T A.Yb,
-// A.MU and A.KB accumulate the mu and K cotangents
-hipError_t launch_adj_sweep(int axis, const adj::AC& c, const adj::Arr& A, const Shared* sh,
-                            hipStream_t s);
+// reverse of one 2D operator L_axis(dt_frozen/2) at A.X, in two parts:
+// launch_adj_fw fills the forward values A.P, A.S, A.XP, A.PP of A.X (it
+// needs no cotangent, so it can run ahead); launch_adj_rev then takes
+// A.Xb = J^T A.Yb, and A.MU and A.KB accumulate the mu and K cotangents
+hipError_t launch_adj_fw(int axis, const adj::AC& c, const adj::Arr& A, const Shared* sh,
+                         hipStream_t s);
+hipError_t launch_adj_rev(int axis, const adj::AC& c, const adj::Arr& A, const Shared* sh,
+                          hipStream_t s);
 hipError_t launch_fill(double* a, long long n, double v, hipStream_t s);
 hipError_t launch_ra_reduce(long long cnt, const double* MU, const double* KB, double s_mu,
                             double s_K, double* out, hipStream_t s);

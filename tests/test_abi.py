@@ -67,16 +67,17 @@ def test_strerror_covers_every_code(L):
 
 
 def test_adjoint_sizes_and_restrictions(L):
-    # workspace: checkpoints (ceil(N/E) states), one interval's operator
-    # inputs (4E states), and per-node stage arrays; 2D and the printed
-    # limiter only
+    # workspace: checkpoints (ceil(N/E) states), two intervals' operator
+    # inputs (2 x 4E states) and forward values (2 x 4E x 13 doubles per
+    # node), and per-node stage arrays; 2D and the printed limiter only
     import paper_2411_10372_amd as mtvd
     wb = ctypes.c_size_t()
     p = mtvd.Params(nx=512, nz=128, Ra=1e7)._c()
     assert L.mtvd_adj_bytes(ctypes.byref(p), 500, 50, ctypes.byref(wb)) == 0
-    state = 4 * 512 * 128 * 8
-    assert wb.value >= (10 + 200) * state
-    assert wb.value <= (10 + 200) * state + 80 * 512 * 128 * 8 + (1 << 20)
+    one = 512 * 128 * 8
+    least = (10 + 2 * 200) * 4 * one + 2 * 200 * 13 * one
+    assert wb.value >= least
+    assert wb.value <= least + 80 * one + (1 << 20)
     small = wb.value
     assert L.mtvd_adj_bytes(ctypes.byref(p), 500, 10, ctypes.byref(wb)) == 0
     assert wb.value < small                      # fewer recomputed states
