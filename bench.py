@@ -34,11 +34,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = {2: ("mtvd_2d.hip", "mtvd_device.h"), 3: ("mtvd_3d.hip", "mtvd_device.h")}
+# the files a sweep kernel's binary depends on (the build script holds its
+# compiler flags)
+KERNEL_SOURCES = {2: ("mtvd_2d.hip", "mtvd_device.h", "../build.py"),
+                  3: ("mtvd_3d.hip", "mtvd_device.h", "../build.py")}
 
 
 def source_hash(files=None) -> str:
-    """Hash of the kernel sources (all of them, or the named files)."""
+    """Hash of the kernel sources (all of them, or the named files, relative
+    to the package's csrc/)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2411_10372_amd", "csrc")
     names = sorted(files) if files else sorted(

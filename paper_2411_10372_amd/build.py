@@ -21,6 +21,21 @@ FLAGS = [
 ]
 
 
+# Instruction-scheduling strategy per source, chosen by timing the step at
+# 4096x1024 and 1024x1024x256 (it only reorders instructions: results are
+# bit for bit the same).  The 2D sweeps gained 2% with max-ilp; the 3D
+# march kernels 1.4% with iterative-minreg; the rest keep the default.
+SCHED = {
+    "mtvd_2d.hip": "max-ilp",
+    "mtvd_3d.hip": "iterative-minreg",
+}
+
+
+def flags_for(src: str) -> list:
+    st = SCHED.get(os.path.basename(src))
+    return FLAGS + (["-mllvm", f"-amdgpu-sched-strategy={st}"] if st else [])
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
@@ -31,7 +46,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
     for src in sources():
         obj = os.path.join(HERE, "_build", os.path.basename(src) + ".o")
-        cmd = [hipcc, *FLAGS, "-c", src, "-o", obj]
+        cmd = [hipcc, *flags_for(src), "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
