@@ -68,6 +68,20 @@ def load_traffic(workload: str, kernel: str, shash: str):
     return d.get("hbm_bytes_per_launch")
 
 
+def copy_ref() -> int:
+    """A plain 256 MiB device-to-device copy, three times: the dispatch whose
+    counter readings scale FETCH_SIZE and WRITE_SIZE to bytes in the
+    rocprofv3 summaries.  Returns the bytes one copy moves."""
+    import torch
+    a = torch.empty(32 << 20, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return 2 * a.numel() * 8
+
+
 def cpu_baseline(kw: dict, budget_s: float):
     """The CPU oracle, as it stands, on a bounded sample of the workload:
     as many full steps from its initial state as fit in about budget_s."""
@@ -136,6 +150,8 @@ def bench_batch(args):
     launch_bytes = nodes * 2 * 4 * 8
     per_launch_s = 1e-3 * gpu_ms / (4 * K)
     achieved = launch_bytes / per_launch_s / 1e9
+    shash = source_hash(KERNEL_SOURCES[2])
+    traffic = load_traffic("batch_64_mixed_2d", "sweep_batch2d", shash)
     out = {
         "metric": METRIC, "value": nodes * K / t_b, "unit": "cell-updates/s", "n_gpus": 1,
         "steps": K, "warmup": W, "ms_per_step": 1e3 * t_b / K, "higher_is_better": True,
@@ -146,13 +162,15 @@ def bench_batch(args):
                    "Ra_range": [min(p.Ra for p in ps), max(p.Ra for p in ps)]},
         "roofline": {"bound": "hbm", "kernel": "sweep_batch2d", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_launch": launch_bytes,
+                     "traffic": traffic, "bytes_per_launch": launch_bytes,
                      "note": "average over the 4 operator launches of a step (graph replay)"},
         "plain_sequential_value": nodes * kp / t_p,
         "speedup_vs_plain_sequential": (nodes * K / t_b) / (nodes * kp / t_p),
         "autotune_s": t_tune, "rows_per_wave_x_z": tiles,
-        "source_hash": source_hash(),
+        "source_hash": shash,
     }
+    if args.copy_ref:
+        out["copy_ref_bytes"] = copy_ref()
     print(json.dumps(out), flush=True)
 
 
@@ -285,14 +303,19 @@ def main():
     torch.cuda.synchronize()
     t_all = time.perf_counter() - t0
 
-    # the same K steps without diagnostics, with HIP events around every
-    # sweep launch on the library's stream
-    s.set_timing(True)
+    # the same K steps without diagnostics
     t0 = time.perf_counter()
     s.step(K)
     s.sync()
     torch.cuda.synchronize()
     t_nodiag = time.perf_counter() - t0
+
+    # and again with HIP events around every sweep launch on the library's
+    # stream (per-kernel durations for the roofline; the events themselves
+    # cost time between launches, so this pass is not used for `value`)
+    s.set_timing(True)
+    s.step(K)
+    s.sync()
     s.set_timing(False)
     ms, cnt = s.kernel_times()
     dfin = s.diagnostics()
@@ -333,13 +356,7 @@ def main():
         "source_hash": shash,
     }
     if args.copy_ref:
-        a = torch.empty(32 << 20, dtype=torch.float64, device="cuda:0")
-        b = torch.empty_like(a)
-        a.fill_(1.0)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        out["copy_ref_bytes"] = 2 * a.numel() * 8
+        out["copy_ref_bytes"] = copy_ref()
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(kw, args.cpu_seconds)

@@ -6,8 +6,8 @@
 ``pmc``: HBM bytes per launch of one kernel from two ``rocprofv3 --pmc``
 runs (``FETCH_SIZE``, then ``WRITE_SIZE``; KiB per dispatch), each scaled by
 what the same counter reads for a plain device copy of known size (the
-largest ``__amd_rocclr_copyBuffer`` dispatch of the run: ``bench.py
---copy-ref`` copies 256 MiB).
+last three ``__amd_rocclr_copyBuffer`` dispatches of the run: ``bench.py
+--copy-ref`` copies 256 MiB three times after everything it times).
 
 Usage (paths are the rocprofv3 output directories):
     python -m paper_2411_10372_amd.profiling trace DIR OUT.md "COMMAND"
@@ -73,9 +73,13 @@ def pmc_summary(fetch_dir: str, write_dir: str, kernel: str, workload: str, shas
         return kernel in r["Kernel_Name"]
 
     def big_copy(rows):
-        copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
-        gmax = max(int(r["Grid_Size"]) for r in copies)
-        return lambda r: "copyBuffer" in r["Kernel_Name"] and int(r["Grid_Size"]) == gmax
+        # the reference copies are the run's last three copy dispatches
+        # (bench.py --copy-ref makes them after everything it times); the
+        # grid size alone does not single them out, other copies share it
+        copies = sorted((r for r in rows if "copyBuffer" in r["Kernel_Name"]),
+                        key=lambda r: int(r["Dispatch_Id"]))
+        ids = {r["Dispatch_Id"] for r in copies[-3:]}
+        return lambda r: "copyBuffer" in r["Kernel_Name"] and r["Dispatch_Id"] in ids
 
     fetch_kib, nf = _mean_for(fr, is_kernel)
     write_kib, nw = _mean_for(wr, is_kernel)
