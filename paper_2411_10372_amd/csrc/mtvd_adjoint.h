@@ -4,11 +4,12 @@
 // The forward operator (Sec. 3.1 of arXiv:2411.10372) is taken as stages
 // over whole arrays (primitives P of X; predictor fluxes F; X^P and its
 // primitives P^P; corrector fluxes F^P; X^C; the TVD coefficient G of every
-// face; the output).  Five passes take the cotangent of the output back to
+// face; the output).  Four passes take the cotangent of the output back to
 // the cotangent of X and accumulate the cotangents of the diffusion
 // coefficients mu and K (from which d/dRa follows): fw_all (P, |u|+c, X^P,
-// P^P), rv_tc (output, TVD faces and corrector), rv_pred (P^P -> X^P and
-// the predictor) and rv_prim (P -> X).  Every pass is a function of one
+// P^P: forward values only, so it can run ahead of the cotangents), rv_tc
+// (output, TVD faces and corrector), rv_pred (P^P -> X^P and the predictor)
+// and rv_prim (P -> X).  Every pass is a function of one
 // node that gathers what its neighbours contribute, recomputing the cheap
 // neighbour values it needs instead of storing them, so each pass is one
 // kernel without atomics.  Limiter kinks take the branch the forward pass
