@@ -998,20 +998,44 @@ int batch_refresh_dt(mtvd_batch* b, int box) {
   return MTVD_OK;
 }
 
+// The rules every box of a batch must meet: valid parameters (a diffusion
+// number above 1/2 is tolerated where only sizes are asked for), 2D, and the
+// dt_mode and sweep_order of the first box.
+int batch_check(const mtvd_params* boxes, int nbox, bool sizes_only, std::string* why) {
+  if (!boxes || nbox < 1) {
+    *why = "no boxes";
+    return MTVD_EINVAL;
+  }
+  for (int i = 0; i < nbox; ++i) {
+    std::string w;
+    int rc = validate(&boxes[i], &w);
+    if (rc != MTVD_OK && !(sizes_only && rc == MTVD_ESTABILITY)) {
+      *why = "box " + std::to_string(i) + ": " + w;
+      return rc;
+    }
+    if (boxes[i].ndim != 2) {
+      *why = "box " + std::to_string(i) + ": batches hold 2D boxes only";
+      return MTVD_EINVAL;
+    }
+    if (boxes[i].dt_mode != boxes[0].dt_mode || boxes[i].sweep_order != boxes[0].sweep_order) {
+      *why = "box " + std::to_string(i) + ": dt_mode and sweep_order differ from box 0";
+      return MTVD_EINVAL;
+    }
+  }
+  return MTVD_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
 int mtvd_batch_bytes(const mtvd_params* boxes, int32_t nbox, size_t* state_bytes,
                      size_t* workspace_bytes) {
-  if (!boxes || nbox < 1) return MTVD_EINVAL;
+  std::string why;
+  int rc = batch_check(boxes, nbox, true, &why);
+  if (rc != MTVD_OK) return rc;
   std::vector<Coef> cs;
-  for (int i = 0; i < nbox; ++i) {
-    std::string why;
-    int rc = validate(&boxes[i], &why);
-    if (rc != MTVD_OK && rc != MTVD_ESTABILITY) return rc;
-    cs.push_back(make_coef(&boxes[i]));
-  }
+  for (int i = 0; i < nbox; ++i) cs.push_back(make_coef(&boxes[i]));
   BatchLayout L = batch_layout(boxes, nbox, cs);
   if (state_bytes) *state_bytes = L.state_doubles * sizeof(double);
   if (workspace_bytes) *workspace_bytes = L.total;
@@ -1020,18 +1044,13 @@ int mtvd_batch_bytes(const mtvd_params* boxes, int32_t nbox, size_t* state_bytes
 
 int mtvd_batch_create(const mtvd_params* boxes, int32_t nbox, void* hip_stream,
                       mtvd_batch** out) {
-  if (!out || !boxes || nbox < 1) return MTVD_EINVAL;
+  if (!out) return MTVD_EINVAL;
   *out = nullptr;
-  for (int i = 0; i < nbox; ++i) {
-    std::string why;
-    int rc = validate(&boxes[i], &why);
-    if (rc != MTVD_OK) {
-      fprintf(stderr, "mtvd_batch_create: box %d: %s\n", i, why.c_str());
-      return rc;
-    }
-    if (boxes[i].ndim != 2) return MTVD_EINVAL;
-    if (boxes[i].dt_mode != boxes[0].dt_mode || boxes[i].sweep_order != boxes[0].sweep_order)
-      return MTVD_EINVAL;
+  std::string why;
+  int rc = batch_check(boxes, nbox, false, &why);
+  if (rc != MTVD_OK) {
+    fprintf(stderr, "mtvd_batch_create: %s\n", why.c_str());
+    return rc;
   }
   mtvd_batch* b = new (std::nothrow) mtvd_batch();
   if (!b) return MTVD_EINVAL;
