@@ -21,6 +21,15 @@ Parity status of each function (what pins it is in ``tests/test_oracle_*``):
                        interior nodes recovered as T0 + theta)
   time_avg_nu       -- pinned through step and diag, plus the conduction
                        value 1 and the one-step identity
+  stretched z grid  -- pinned (tests/test_oracle_stretched.py: grid ends,
+                       symmetry and the map's derivative; the s -> 0 limit;
+                       dual-cell mass conservation; the uniform-pressure
+                       conduction state steady with Nu = 1; second-order
+                       decay of the hydrostatic error; the TVD term at a
+                       spike in z; the z cross derivative of the x operator;
+                       dt from the narrowest face).  The face spacing that
+                       multiplies the TVD flux is a reading (the Harten-Yee
+                       flux form); the spike pin fixes it.
   time_avg_nu_cs    -- complex-step derivative of time_avg_nu: pinned by its
                        real part (equal to time_avg_nu), by central
                        differences where the method is smooth (TVD off) and
@@ -62,7 +71,7 @@ class _Params(ctypes.Structure):
         ("limiter_form", ctypes.c_int32), ("sweep_order", ctypes.c_int32),
         ("tvd_on", ctypes.c_int32), ("gravity_scale", ctypes.c_double),
         ("wall_order", ctypes.c_int32), ("pred_dir", ctypes.c_int32), ("diffusion_scale", ctypes.c_double),
-        ("nthreads", ctypes.c_int32),
+        ("nthreads", ctypes.c_int32), ("stretch", ctypes.c_double),
     ]
 
 
@@ -98,6 +107,7 @@ class Params:
     pred_dir: int = 0
     diffusion_scale: float = 1.0
     nthreads: int = 0
+    stretch: float = 0.0
 
     def _c(self) -> _Params:
         return _Params(**{f.name: getattr(self, f.name) for f in fields(self)})
@@ -132,6 +142,7 @@ def lib():
         L.ora_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         L.ora_splitmix64.restype = ctypes.c_uint64
         L.ora_init.argtypes = [P, dp]
+        L.ora_heights.argtypes = [P, dp]
         L.ora_init_box.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                    ctypes.c_int, dp]
         L.ora_dt.argtypes = [P, dp]
@@ -167,6 +178,14 @@ def threads() -> int:
 
 def splitmix64(seed: int, n: int) -> int:
     return int(lib().ora_splitmix64(seed, n))
+
+
+def heights(p: Params) -> np.ndarray:
+    """The nz node heights z_k (uniform, or the tanh grid when stretch > 0)."""
+    z = np.empty(p.nz, dtype=np.float64)
+    pc = p._c()
+    _ok(lib().ora_heights(ctypes.byref(pc), _ptr(z)), "heights")
+    return z
 
 
 def init(p: Params) -> np.ndarray:

@@ -122,6 +122,8 @@ def d_zz(f, h):
 
 def node_fields(p, X):
     """The ten per-node quantities whose row means make the profiles."""
+    if getattr(p, "stretch", 0.0) != 0.0:
+        raise NotImplementedError("analysis profiles on the uniform z grid only")
     c = _coefs(p)
     rho, ux, uy, uz, T, pr, zz = primitives(p, X)
     TA = 1.0 - p.D * zz

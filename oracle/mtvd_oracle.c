@@ -66,6 +66,8 @@ typedef struct {
   double Tb, Tt;             /* plate temperatures: 1 and 1-(eps+D) */
   double cfl;
   int limiter_form, tvd_on, pred_dir, sweep_order, wall_order;
+  int stretched;             /* 1 on the tanh grid (stretch > 0) */
+  double s, ths;             /* stretch s and tanh(s) */
 } coefs;
 
 static void make_coefs(const ora_params* p, coefs* c) {
@@ -106,6 +108,9 @@ static void make_coefs(const ora_params* p, coefs* c) {
   c->pred_dir = p->pred_dir;
   c->sweep_order = p->sweep_order;
   c->wall_order = p->wall_order;
+  c->stretched = p->stretch > 0.0;
+  c->s = p->stretch;
+  c->ths = c->stretched ? tanh(p->stretch) : 1.0;
 }
 
 static int check_params(const ora_params* p) {
@@ -116,6 +121,7 @@ static int check_params(const ora_params* p) {
   if (!(p->gamma > 1.0) || !(p->eps > 0.0) || !(p->D > 0.0)) return -1;
   if (!(p->Ra > 0.0) || !(p->Pr > 0.0) || !(p->aspect > 0.0)) return -1;
   if (p->wall_order != 1 && p->wall_order != 2) return -1;
+  if (!(p->stretch >= 0.0) || !(p->stretch <= 10.0)) return -1;
   return 0;
 }
 
@@ -127,8 +133,23 @@ static void set_threads(const ora_params* p) {
 #endif
 }
 
-/* height of row k: z_k = k / M, so the plates sit exactly at 0 and 1 */
-static double zrow(const coefs* c, int k) { return (double)k / (double)c->M; }
+/* height of row k: z_k = k / M on the uniform grid; on the tanh grid
+ * z_k = (1 + tanh(s (2k - M)/M) / tanh s) / 2.  Both put the plates exactly
+ * at 0 and 1 (tanh is odd, so the quotient is -1 and 1 at the ends). */
+static double zrow(const coefs* c, int k) {
+  if (!c->stretched) return (double)k / (double)c->M;
+  double xi = (2.0 * (double)k - (double)c->M) / (double)c->M;
+  return 0.5 * (1.0 + tanh(c->s * xi) / c->ths);
+}
+
+/* z spacing of face k+1/2 and the dual cell of row k (trapezoid weight in
+ * units of length: (z_k+1 - z_k-1)/2 inside, half the face at a plate) */
+static double zface(const coefs* c, int k) { return zrow(c, k + 1) - zrow(c, k); }
+static double zdual(const coefs* c, int k) {
+  if (k == 0) return 0.5 * zface(c, 0);
+  if (k == c->M) return 0.5 * zface(c, c->M - 1);
+  return 0.5 * (zrow(c, k + 1) - zrow(c, k - 1));
+}
 
 int ora_threads(void) {
 #ifdef _OPENMP
@@ -141,6 +162,14 @@ int ora_threads(void) {
 size_t ora_state_len(const ora_params* p) {
   size_t ny = (p->ndim == 3) ? (size_t)p->ny : 1;
   return (size_t)(p->ndim + 2) * (size_t)p->nz * ny * (size_t)p->nx;
+}
+
+int ora_heights(const ora_params* p, double* z) {
+  if (check_params(p)) return -1;
+  coefs c;
+  make_coefs(p, &c);
+  for (int k = 0; k < c.nz; ++k) z[k] = zrow(&c, k);
+  return 0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -358,7 +387,13 @@ double ora_dt(const ora_params* p, const double* X) {
         double cs = sqrt(c.gamma * pr / rho);
         for (int d = 0; d < 3; ++d) {
           if (!has_dir(&c, d)) continue;
-          double v = c.h[d] / (fabs(u[d]) + cs);
+          double h = c.h[d];
+          if (d == 2 && c.stretched) {
+            /* the narrower of the node's faces */
+            h = (k == 0) ? zface(&c, 0) : (k == c.M) ? zface(&c, c.M - 1)
+                : fmin(zface(&c, k - 1), zface(&c, k));
+          }
+          double v = h / (fabs(u[d]) + cs);
           if (v < best) best = v;
         }
       }
@@ -454,7 +489,8 @@ int ora_diag(const ora_params* p, const double* X, ora_diag_t* d) {
   csum tot[5];
   memset(tot, 0, sizeof(tot));
   for (int k = 0; k <= M; ++k) {
-    double w = (k == 0 || k == M) ? 0.5 : 1.0;
+    /* on the tanh grid the weights are the dual cells in units of dz */
+    double w = c.stretched ? zdual(&c, k) / c.h[2] : (k == 0 || k == M) ? 0.5 : 1.0;
     for (int q = 0; q < 5; ++q) cadd(&tot[q], w * rs[k * 6 + q]);
   }
   d->mass = cval(&tot[0]) * dV;
@@ -467,9 +503,15 @@ int ora_diag(const ora_params* p, const double* X, ora_diag_t* d) {
   int rows[6] = {0, 1, 2, M - 2, M - 1, M};
   for (int q = 0; q < 6; ++q) d->tmean[q] = rs[rows[q] * 6 + 5] / (double)plane;
   double dz = c.h[2];
-  /* d<T_sa>/dz = d<T>/dz + D; second-order one-sided at each plate */
-  double gb = ((-3.0 * d->tmean[0] + 4.0 * d->tmean[1]) - d->tmean[2]) / (2.0 * dz);
-  double gt = ((3.0 * d->tmean[5] - 4.0 * d->tmean[4]) + d->tmean[3]) / (2.0 * dz);
+  /* d<T_sa>/dz = d<T>/dz + D; second-order one-sided at each plate (on the
+   * tanh grid the same stencil applied to the heights is the divisor) */
+  double db = 2.0 * dz, dt_ = 2.0 * dz;
+  if (c.stretched) {
+    db = (-3.0 * zrow(&c, 0) + 4.0 * zrow(&c, 1)) - zrow(&c, 2);
+    dt_ = (3.0 * zrow(&c, M) - 4.0 * zrow(&c, M - 1)) + zrow(&c, M - 2);
+  }
+  double gb = ((-3.0 * d->tmean[0] + 4.0 * d->tmean[1]) - d->tmean[2]) / db;
+  double gt = ((3.0 * d->tmean[5] - 4.0 * d->tmean[4]) + d->tmean[3]) / dt_;
   d->nu_bottom = -(gb + c.D) / c.eps;
   d->nu_top = -(gt + c.D) / c.eps;
   d->nu_mean = 0.5 * (d->nu_bottom + d->nu_top);
@@ -503,8 +545,13 @@ static double complex nu_mean_cs(const coefs* c, const double complex* X) {
     tm[q] = sum / (double)plane;
   }
   double dz = c->h[2];
-  double complex gb = ((-3.0 * tm[0] + 4.0 * tm[1]) - tm[2]) / (2.0 * dz);
-  double complex gt = ((3.0 * tm[5] - 4.0 * tm[4]) + tm[3]) / (2.0 * dz);
+  double db = 2.0 * dz, dt_ = 2.0 * dz;
+  if (c->stretched) {
+    db = (-3.0 * zrow(c, 0) + 4.0 * zrow(c, 1)) - zrow(c, 2);
+    dt_ = (3.0 * zrow(c, M) - 4.0 * zrow(c, M - 1)) + zrow(c, M - 2);
+  }
+  double complex gb = ((-3.0 * tm[0] + 4.0 * tm[1]) - tm[2]) / db;
+  double complex gt = ((3.0 * tm[5] - 4.0 * tm[4]) + tm[3]) / dt_;
   double complex nb = -(gb + c->D) / c->eps, nt = -(gt + c->D) / c->eps;
   return 0.5 * (nb + nt);
 }

@@ -12,8 +12,18 @@
  *   fields f (2D): rho, rho*u_x, rho*u_z, E
  *   fields f (3D): rho, rho*u_x, rho*u_y, rho*u_z, E
  * x and y are periodic without a duplicated end point (dx = aspect/nx,
- * dy = aspect/ny); z has nz nodes with the plates on k = 0 and k = nz-1
- * (dz = 1/(nz-1)).
+ * dy = aspect/ny); z has nz nodes with the plates on k = 0 and k = nz-1,
+ * uniform (dz = 1/(nz-1)) or tanh-stretched (the stretch parameter).
+ *
+ * On a stretched grid every z difference divides by the same difference of
+ * the node heights (forward (q_k+1 - q_k)/(z_k+1 - z_k), central over
+ * z_k+1 - z_k-1, the one-sided plate stencils over the same stencil of
+ * z), the flux differences of predictor and corrector divide by the dual
+ * cell w_k = (z_k+1 - z_k-1)/2 (half the adjacent face at a plate), and
+ * the TVD term is the difference of face fluxes h_k+1/2 G dX_k+1/2 divided
+ * by w_k with the face Courant number tau |lambda| / h_k+1/2.  On the
+ * uniform grid each of these is the printed scheme; the uniform code path
+ * is kept as it was, so its results do not change.
  */
 #ifndef MTVD_ORACLE_H
 #define MTVD_ORACLE_H
@@ -48,6 +58,9 @@ typedef struct ora_params {
                             printed); 1: forward (periodic axes only) */
   double diffusion_scale;/* multiplies mu* and K*; 1 normally */
   int32_t nthreads;      /* OpenMP threads; 0 = runtime default */
+  double stretch;        /* s of the tanh z grid (Sec. 3.1 grid): z_k =
+                            (1 + tanh(s (2k/M - 1)) / tanh s) / 2; 0 gives
+                            the uniform grid z_k = k/M */
 } ora_params;
 
 typedef struct ora_diag {
@@ -65,6 +78,9 @@ size_t ora_state_len(const ora_params* p);
 /* n-th output (n >= 1) of the SplitMix64 generator started from `seed`
  * (Steele, Lea & Flood 2014): mix64(seed + n * 0x9E3779B97F4A7C15). */
 uint64_t ora_splitmix64(uint64_t seed, uint64_t n);
+
+/* the nz node heights z_k of the grid (uniform or tanh) */
+int ora_heights(const ora_params* p, double* z);
 
 /* initial state: conductive T, hydrostatic rho, seeded T noise, u = 0 */
 int ora_init(const ora_params* p, double* X);

@@ -57,6 +57,7 @@ static ora_params base(int ndim, int nx, int ny, int nz) {
   p.pred_dir = 0;
   p.diffusion_scale = 1.0;
   p.nthreads = 1 + (nx % 3);  /* 1-3 OpenMP threads where built with OpenMP */
+  p.stretch = 0.0;
   return p;
 }
 
@@ -148,7 +149,7 @@ int main(void) {
   };
   char label[128];
   for (size_t g = 0; g < sizeof grids / sizeof grids[0]; ++g) {
-    for (int variant = 0; variant < 6; ++variant) {
+    for (int variant = 0; variant < 7; ++variant) {
       ora_params p = base(grids[g].ndim, grids[g].nx, grids[g].ny, grids[g].nz);
       switch (variant) {
         case 1: p.limiter_form = 1; break;
@@ -156,6 +157,7 @@ int main(void) {
         case 3: p.tvd_on = 0; p.dt_mode = 1; break;
         case 4: p.pred_dir = 1; p.bulk_coef = 0.0; break;
         case 5: p.gravity_scale = 0.0; p.diffusion_scale = 0.0; break;
+        case 6: p.stretch = 1.7; p.wall_order = 2; break;
         default: break;
       }
       snprintf(label, sizeof label, "%dD %dx%dx%d variant %d", p.ndim, p.nx, p.ny, p.nz,
@@ -168,6 +170,8 @@ int main(void) {
   ora_params p2 = base(2, 9, 1, 6);
   run_box(&p2, 0, 0, 5, 1, "2D box 5");
   run_box(&p2, 7, 0, 11, 1, "2D box wrap");
+  p2.stretch = 2.0;
+  run_box(&p2, 3, 0, 6, 1, "2D box stretched");
   ora_params p3 = base(3, 6, 5, 4);
   run_box(&p3, 0, 0, 5, 5, "3D box 5x5");
   run_box(&p3, 4, 3, 8, 6, "3D box wrap");
@@ -185,6 +189,16 @@ int main(void) {
   bad.wall_order = 3;
   CHECK(ora_step(&bad, dummy, 1, dummy, dummy) == -1, "wall_order=3 accepted");
   CHECK(ora_init(NULL, dummy) == -1, "NULL params accepted");
+  bad = base(2, 8, 1, 5);
+  bad.stretch = -1.0;
+  CHECK(ora_init(&bad, dummy) == -1, "stretch < 0 accepted");
+  {
+    ora_params g = base(2, 4, 1, 7);
+    g.stretch = 1.5;
+    double* z = alloc(7);
+    CHECK(ora_heights(&g, z) == 0 && z[0] == 0.0 && z[6] == 1.0, "heights");
+    free(z);
+  }
 
   CHECK(ora_splitmix64(0, 1) == 0xE220A8397B1DCDAFULL, "splitmix64(0, 1)");
 
