@@ -46,3 +46,40 @@ def unit_directions(nz: int, nx: int, count: int, seed: int) -> np.ndarray:
     V[:, 1:nz - 1, :] = rng.standard_normal((count, nz - 2, nx))
     V /= np.sqrt(np.sum(V * V, axis=(1, 2)))[:, None, None]
     return V
+
+
+def random_case(seed: int, ndim: int) -> dict:
+    """One seeded random problem for the parameter fuzz: a small grid (down
+    to one column in x and y and the minimum nz = 5), every parameter of
+    Sec. 2 drawn over a wide range and every switch of the scheme drawn,
+    plus the perturbation and the rows per wave.  Keys: the parameter
+    names, and 'amp', 'pseed', 'tiling', 'steps'."""
+    rng = np.random.default_rng(seed)
+    if ndim == 2:
+        nx, ny, nz = int(rng.integers(1, 131)), 1, int(rng.integers(5, 41))
+    else:
+        nx, ny, nz = int(rng.integers(1, 41)), int(rng.integers(1, 25)), int(rng.integers(5, 21))
+    eps = float(rng.uniform(0.02, 0.3))
+    kw = dict(
+        ndim=ndim, nx=nx, ny=ny, nz=nz,
+        aspect=float(rng.uniform(0.5, 8.0)),
+        gamma=float(rng.uniform(1.1, 1.8)),
+        Pr=float(10.0 ** rng.uniform(-0.5, 1.0)),
+        Ra=float(10.0 ** rng.uniform(4.0, 9.0)),
+        eps=eps,
+        D=float(rng.uniform(0.05, 0.9 - eps)),
+        cfl=float(rng.uniform(0.2, 0.9)),
+        seed=int(rng.integers(0, 2**31)),
+        noise_amp=float(rng.choice([0.0, 1e-3, 1e-2])),
+        dt_mode=int(rng.integers(0, 2)),
+        bulk_coef=float(rng.choice([-2.0 / 3.0, 2.0 / 3.0, 0.0])),
+        limiter_form=int(rng.integers(0, 2)),
+        sweep_order=int(rng.integers(0, 2)),
+        tvd_on=int(rng.random() >= 0.2),
+        gravity_scale=float(rng.choice([1.0, 1.0, 0.5, 0.0])),
+        wall_order=int(rng.integers(1, 3)),
+    )
+    tiling = (0, 0) if rng.random() < 0.3 else (int(rng.integers(1, 9)), int(rng.integers(1, 9)))
+    kw.update(amp=float(rng.uniform(0.0, 0.03)), pseed=int(rng.integers(0, 2**31)),
+              tiling=tiling, steps=int(rng.integers(1, 5)))
+    return kw
