@@ -345,7 +345,7 @@ def main():
         "data": "synthetic (seeded initial state generated on the GPU)",
         "config": {"workload": args.workload, "ndim": p.ndim, "nx": p.nx, "ny": p.ny,
                    "nz": p.nz, "Ra": p.Ra, "Pr": p.Pr, "gamma": p.gamma, "eps": p.eps,
-                   "D": p.D, "cfl": p.cfl, "diag_every": diag_every},
+                   "D": p.D, "cfl": p.cfl, "stretch": p.stretch, "diag_every": diag_every},
         "roofline": {"bound": "hbm", "kernel": AXES[dom], "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "bytes_per_launch": per_launch_bytes},

@@ -79,6 +79,21 @@ typedef struct mtvd_params {
   int32_t wall_order;    /* 2 (default): z-derivatives inside the plate
                             fluxes are second-order one-sided; 1: interior
                             first differences */
+  double stretch;        /* z grid (Sec. 3.1: tangent-hyperbolic in z):
+                            0 (default) uniform, z_k = k/(nz-1); s in
+                            (0, 10]: z_k = (1 + tanh(s (2k - M)/M)/tanh s)/2,
+                            M = nz-1, nodes crowded at both plates.  Every z
+                            difference then divides by the same difference
+                            of the heights, the flux differences of
+                            predictor and corrector by the dual cell
+                            w_k = (z_k+1 - z_k-1)/2 (half the face at a
+                            plate), and the TVD term is the difference of
+                            the face fluxes h_k+1/2 G dX over w_k with the
+                            face's own Courant number; dt takes the
+                            narrowest face of each node, the diagnostics
+                            weigh rows by w_k.  2D single boxes only:
+                            MTVD_EINVAL in 3D, in batches, for the adjoint
+                            and for the analysis profiles. */
 } mtvd_params;
 
 /* Diagnostics of the current state (Sec. 2: mass, kinetic energy, total

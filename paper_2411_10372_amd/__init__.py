@@ -46,7 +46,7 @@ class _Params(ctypes.Structure):
         ("dt_mode", ctypes.c_int32), ("bulk_coef", ctypes.c_double),
         ("limiter_form", ctypes.c_int32), ("sweep_order", ctypes.c_int32),
         ("tvd_on", ctypes.c_int32), ("gravity_scale", ctypes.c_double),
-        ("wall_order", ctypes.c_int32),
+        ("wall_order", ctypes.c_int32), ("stretch", ctypes.c_double),
     ]
 
 
@@ -80,6 +80,7 @@ class Params:
     tvd_on: int = 1
     gravity_scale: float = 1.0
     wall_order: int = 2
+    stretch: float = 0.0
 
     def _c(self) -> _Params:
         return _Params(**{f.name: getattr(self, f.name) for f in fields(self)})

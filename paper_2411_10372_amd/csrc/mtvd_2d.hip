@@ -86,11 +86,13 @@ __device__ __forceinline__ void fold_max(Shared* sh, int slot, double mx, double
   }
 }
 
-__device__ __forceinline__ void out_max(const Coef& c, const N2& o, double z, double& mx,
-                                        double& mz, bool& bad, bool lane_out) {
+// izs: 1 on the uniform grid; 1/h_z of the row on a stretched one (the z
+// slot then collects (|u_z| + c)/h_z, which dt divides into 1)
+__device__ __forceinline__ void out_max(const Coef& c, const N2& o, double z, double izs,
+                                        double& mx, double& mz, bool& bad, bool lane_out) {
   P2 q = prim2(c, o, z);
   double cs = sound(c, q.T);
-  double sx = fabs(q.ux) + cs, sz = fabs(q.uz) + cs;
+  double sx = fabs(q.ux) + cs, sz = (fabs(q.uz) + cs) * izs;
   if (lane_out) {
     mx = fmax(mx, sx);
     mz = fmax(mz, sz);
@@ -126,6 +128,11 @@ struct Z2 {
   N2 FP[2];     // corrector flux (backward inner derivatives)
   double mx, mz;
   bool bad;
+  // stretched grid only: metrics derived from the ring heights and carried
+  // one march step (a table read per row would wait behind the row loads)
+  double ihf1, ihf2;  // 1/h of faces f-3+1/2 and f-4+1/2
+  double iw1;         // 1/w of row f-3
+  double iwb, iwt;    // the two plate stencils' 1/(stencil applied to z)
 };
 
 // The stages of one march step f of L_z.  Ring slots: row f in S & 3,
@@ -161,22 +168,25 @@ __device__ __forceinline__ void z2_load(const Coef& c, Z2& st, int f, const Cols
 
 // B: predictor flux F_r of row r = f-2 (inner z forward; second-order
 //    forward at the bottom plate when `wall`), central x cross-derivatives
-template <int S>
-__device__ __forceinline__ void z2_pflux(const Coef& c, Z2& st, bool wall) {
+//    On a stretched grid (STR) each difference is over the same difference
+//    of the heights: face r+1/2, or the wall stencil applied to z.
+template <int S, bool STR>
+__device__ __forceinline__ void z2_pflux(const Coef& c, Z2& st, bool wall, double ihf) {
   using Z = ZS<S>;
   const P2& q0 = st.pn[Z::c2];
   const P2& q1 = st.pn[Z::c1];
   double dzux, dzuz, dzT;
   if (wall) {
     const P2& q2 = st.pn[Z::c0];
-    double h2 = 0.5 * c.ihz;
+    double h2 = STR ? st.iwb : 0.5 * c.ihz;
     dzux = ((-3.0 * q0.ux + 4.0 * q1.ux) - q2.ux) * h2;
     dzuz = ((-3.0 * q0.uz + 4.0 * q1.uz) - q2.uz) * h2;
     dzT = ((-3.0 * q0.T + 4.0 * q1.T) - q2.T) * h2;
   } else {
-    dzux = (q1.ux - q0.ux) * c.ihz;
-    dzuz = (q1.uz - q0.uz) * c.ihz;
-    dzT = (q1.T - q0.T) * c.ihz;
+    const double ih = STR ? ihf : c.ihz;
+    dzux = (q1.ux - q0.ux) * ih;
+    dzuz = (q1.uz - q0.uz) * ih;
+    dzT = (q1.T - q0.T) * ih;
   }
   double dxux = (up(q0.ux) - dn(q0.ux)) * (0.5 * c.ihx);
   double dxuz = (up(q0.uz) - dn(q0.uz)) * (0.5 * c.ihx);
@@ -200,7 +210,7 @@ __device__ __forceinline__ void z2_pred(const Coef& c, Z2& st, double z, double 
 
 // D: corrector flux F^P_r (inner z backward; second-order backward at the
 //    top plate when `wall`), central x cross-derivatives of X^P
-template <int S>
+template <int S, bool STR>
 __device__ __forceinline__ void z2_cflux(const Coef& c, Z2& st, bool wall) {
   using Z = ZS<S>;
   const P2& q0 = st.pp[Z::c2];
@@ -208,14 +218,15 @@ __device__ __forceinline__ void z2_cflux(const Coef& c, Z2& st, bool wall) {
   double dzux, dzuz, dzT;
   if (wall) {
     const P2& qmm = st.pp[Z::c4];
-    double h2 = 0.5 * c.ihz;
+    double h2 = STR ? st.iwt : 0.5 * c.ihz;
     dzux = ((3.0 * q0.ux - 4.0 * qm.ux) + qmm.ux) * h2;
     dzuz = ((3.0 * q0.uz - 4.0 * qm.uz) + qmm.uz) * h2;
     dzT = ((3.0 * q0.T - 4.0 * qm.T) + qmm.T) * h2;
   } else {
-    dzux = (q0.ux - qm.ux) * c.ihz;
-    dzuz = (q0.uz - qm.uz) * c.ihz;
-    dzT = (q0.T - qm.T) * c.ihz;
+    const double ih = STR ? st.ihf1 : c.ihz;   // face r-1/2
+    dzux = (q0.ux - qm.ux) * ih;
+    dzuz = (q0.uz - qm.uz) * ih;
+    dzT = (q0.T - qm.T) * ih;
   }
   double dxux = (up(q0.ux) - dn(q0.ux)) * (0.5 * c.ihx);
   double dxuz = (up(q0.uz) - dn(q0.uz)) * (0.5 * c.ihx);
@@ -236,7 +247,10 @@ __device__ __forceinline__ double z2_tvd(const Coef& c, const Z2& st, double lz)
 
 // F: corrector, average and TVD term of row o = f-3 (when `emit`); the face
 //    o+1/2 term G dX is carried to the next row as its o-1/2 term
-template <int S, bool FUSE>
+//    On a stretched grid G carries the face spacing (h G dX is the face's
+//    dissipative flux) and the difference of the two face fluxes is taken
+//    over the row's dual cell, as the flux differences are.
+template <int S, bool FUSE, bool STR>
 __device__ __forceinline__ void z2_out(const Coef& c, Z2& st, bool emit, int o, const Cols& L,
                                        double* __restrict__ Y, double tau, double lz) {
   using Z = ZS<S>;
@@ -244,6 +258,11 @@ __device__ __forceinline__ void z2_out(const Coef& c, Z2& st, bool emit, int o, 
   double G = st.G[Z::e1];
   N2 Dc{G * d0.r, G * d0.mx, G * d0.mz, G * d0.E};
   if (emit) {
+    double iw = 1.0;
+    if (STR) {
+      iw = st.iw1;
+      lz = tau * iw;
+    }
     const N2& fp1 = st.FP[Z::e0];
     const N2& fp0 = st.FP[Z::e1];
     N2 xc = st.x[Z::c3] - N2{lz * (fp1.r - fp0.r), lz * (fp1.mx - fp0.mx),
@@ -252,18 +271,27 @@ __device__ __forceinline__ void z2_out(const Coef& c, Z2& st, bool emit, int o, 
     const N2& xp = st.xp[Z::c3];
     const N2& Dm = st.Dp;
     N2 out;
-    out.r = 0.5 * (xp.r + xc.r) + (Dc.r - Dm.r);
-    out.mx = 0.5 * (xp.mx + xc.mx) + (Dc.mx - Dm.mx);
-    out.mz = 0.5 * (xp.mz + xc.mz) + (Dc.mz - Dm.mz);
-    out.E = 0.5 * (xp.E + xc.E) + (Dc.E - Dm.E);
-    if (FUSE) out_max(c, out, st.zz[Z::c3], st.mx, st.mz, st.bad, L.out);
+    if (STR) {
+      out.r = 0.5 * (xp.r + xc.r) + (Dc.r - Dm.r) * iw;
+      out.mx = 0.5 * (xp.mx + xc.mx) + (Dc.mx - Dm.mx) * iw;
+      out.mz = 0.5 * (xp.mz + xc.mz) + (Dc.mz - Dm.mz) * iw;
+      out.E = 0.5 * (xp.E + xc.E) + (Dc.E - Dm.E) * iw;
+    } else {
+      out.r = 0.5 * (xp.r + xc.r) + (Dc.r - Dm.r);
+      out.mx = 0.5 * (xp.mx + xc.mx) + (Dc.mx - Dm.mx);
+      out.mz = 0.5 * (xp.mz + xc.mz) + (Dc.mz - Dm.mz);
+      out.E = 0.5 * (xp.E + xc.E) + (Dc.E - Dm.E);
+    }
+    if (FUSE)
+      out_max(c, out, st.zz[Z::c3], STR ? fmax(st.ihf1, st.ihf2) : 1.0, st.mx, st.mz, st.bad,
+              L.out);
     if (L.out) store2(c, Y, o, L.col, out);
   }
   st.Dp = Dc;
 }
 
 // One march step: plates, chunk edges and the end of the grid are guarded.
-template <int S, bool FUSE>
+template <int S, bool FUSE, bool STR>
 __device__ __forceinline__ void z2_iter(const Coef& c, Z2& st, int f, int fs, int fe,
                                         int k0, int k1, const Cols& L,
                                         const double* __restrict__ zr,
@@ -274,7 +302,16 @@ __device__ __forceinline__ void z2_iter(const Coef& c, Z2& st, int f, int fs, in
   if (f < fs || f > fe) return;
   const int M = c.M;
   const int r = f - 2;
-  if (r >= k0 - 2 && r >= 0 && r <= M - 1) z2_pflux<S>(c, st, r == 0 && c.wall_order == 2);
+  // stretched grid: face r+1/2 and dual cell of row r from the ring heights
+  // (rows past a plate hold clamped heights; their values are never used)
+  double hf = 0.0, ihf = 0.0, iw = 0.0;
+  if (STR) {
+    hf = st.zz[Z::c1] - st.zz[Z::c2];
+    ihf = frcp(hf);
+    iw = 2.0 * frcp(st.zz[Z::c1] - st.zz[Z::c3]);
+  }
+  if (r >= k0 - 2 && r >= 0 && r <= M - 1)
+    z2_pflux<S, STR>(c, st, r == 0 && c.wall_order == 2, ihf);
   // C: plates: u = 0, T = T_plate, top density from the backward mass-flux
   //    difference
   if (r >= k0 - 1 && r >= 0 && r <= M) {
@@ -283,36 +320,54 @@ __device__ __forceinline__ void z2_iter(const Coef& c, Z2& st, int f, int fs, in
       st.xp[Z::c2] = N2{rho, 0.0, 0.0, rho * (c.cv * c.Tb + c.g * st.zz[Z::c2])};
       st.pp[Z::c2] = P2{0.0, 0.0, c.Tb, c.a * rho * c.Tb};
     } else if (r == M) {
-      double rho = st.x[Z::c2].r - lz * (st.x[Z::c2].mz - st.x[Z::c3].mz);
+      const double lt = STR ? tau * st.ihf1 : lz;   // face M-1/2
+      double rho = st.x[Z::c2].r - lt * (st.x[Z::c2].mz - st.x[Z::c3].mz);
       st.xp[Z::c2] = N2{rho, 0.0, 0.0, rho * (c.cv * c.Tt + c.g * st.zz[Z::c2])};
       st.pp[Z::c2] = P2{0.0, 0.0, c.Tt, c.a * rho * c.Tt};
     } else {
-      z2_pred<S>(c, st, st.zz[Z::c2], tau, lz);
+      z2_pred<S>(c, st, st.zz[Z::c2], tau, STR ? tau * iw : lz);
     }
   }
-  if (r >= k0 && r >= 1 && r <= M) z2_cflux<S>(c, st, r == M && c.wall_order == 2);
-  // E: zero on the two faces next to the plates
-  if (r >= k0 - 1 && r >= 0 && r <= M - 1)
-    st.G[Z::e0] = (c.tvd_on && r >= 1 && r <= M - 2) ? z2_tvd<S>(c, st, lz) : 0.0;
+  if (r >= k0 && r >= 1 && r <= M) z2_cflux<S, STR>(c, st, r == M && c.wall_order == 2);
+  // E: zero on the two faces next to the plates (on a stretched grid the
+  //    face's own spacing sets Co, and G carries that spacing)
+  if (r >= k0 - 1 && r >= 0 && r <= M - 1) {
+    double G = 0.0;
+    if (c.tvd_on && r >= 1 && r <= M - 2) {
+      if (STR)
+        G = z2_tvd<S>(c, st, tau * ihf) * hf;
+      else
+        G = z2_tvd<S>(c, st, lz);
+    }
+    st.G[Z::e0] = G;
+  }
   const int o = f - 3;
   if (o >= k0 - 1 && o >= 0 && o < k1 && o <= M - 1)
-    z2_out<S, FUSE>(c, st, o >= k0 && o >= 1, o, L, Y, tau, lz);
+    z2_out<S, FUSE, STR>(c, st, o >= k0 && o >= 1, o, L, Y, tau, lz);
   if (o >= k0 && o < k1 && (o == 0 || o == M)) {
     N2 out;
     if (o == 0) {
-      double rho = st.x[Z::c3].r - lz * (st.xp[Z::c2].mz - 0.0);
+      const double lb = STR ? tau * st.ihf1 : lz;   // face 1/2
+      double rho = st.x[Z::c3].r - lb * (st.xp[Z::c2].mz - 0.0);
       out = N2{rho, 0.0, 0.0, rho * (c.cv * c.Tb + c.g * st.zz[Z::c3])};
     } else {
       double rho = st.xp[Z::c3].r;
       out = N2{rho, 0.0, 0.0, rho * (c.cv * c.Tt + c.g * st.zz[Z::c3])};
     }
-    if (FUSE) out_max(c, out, st.zz[Z::c3], st.mx, st.mz, st.bad, L.out);
+    if (FUSE)
+      out_max(c, out, st.zz[Z::c3], STR ? (o == 0 ? st.ihf1 : st.ihf2) : 1.0, st.mx, st.mz,
+              st.bad, L.out);
     if (L.out) store2(c, Y, o, L.col, out);
+  }
+  if (STR) {
+    st.ihf2 = st.ihf1;
+    st.ihf1 = ihf;
+    st.iw1 = iw;
   }
 }
 
 // one wave's share of L_z: columns of `strip`, output rows of `chunk`
-template <bool FUSE>
+template <bool FUSE, bool STR>
 __device__ __forceinline__ void z2_wave(const Coef& c, Shared* sh, const double* zr, int slot,
                                         double dt, const double* __restrict__ X,
                                         double* __restrict__ Y, int kc, int strip,
@@ -327,6 +382,12 @@ __device__ __forceinline__ void z2_wave(const Coef& c, Shared* sh, const double*
   st.mz = 0.0;
   st.bad = false;
   st.Dp = N2{0.0, 0.0, 0.0, 0.0};
+  st.ihf1 = st.ihf2 = st.iw1 = 0.0;
+  st.iwb = st.iwt = 0.0;
+  if (STR) {
+    st.iwb = zmet(c, 0, kZM_IWALL);
+    st.iwt = zmet(c, c.M, kZM_IWALL);
+  }
   const int fs = max(0, k0 - 2);
   const int fe = k1 + 2;
   // the kPF steps before fs only load rows fs .. fs+kPF-1 (their heads);
@@ -336,15 +397,15 @@ __device__ __forceinline__ void z2_wave(const Coef& c, Shared* sh, const double*
     st.pz[q] = 0.0;
   }
   for (int fb = (fs - kPF) & ~3; fb <= fe; fb += 4) {
-    z2_iter<0, FUSE>(c, st, fb + 0, fs, fe, k0, k1, L, zr, X, Y, tau, lz);
-    z2_iter<1, FUSE>(c, st, fb + 1, fs, fe, k0, k1, L, zr, X, Y, tau, lz);
-    z2_iter<2, FUSE>(c, st, fb + 2, fs, fe, k0, k1, L, zr, X, Y, tau, lz);
-    z2_iter<3, FUSE>(c, st, fb + 3, fs, fe, k0, k1, L, zr, X, Y, tau, lz);
+    z2_iter<0, FUSE, STR>(c, st, fb + 0, fs, fe, k0, k1, L, zr, X, Y, tau, lz);
+    z2_iter<1, FUSE, STR>(c, st, fb + 1, fs, fe, k0, k1, L, zr, X, Y, tau, lz);
+    z2_iter<2, FUSE, STR>(c, st, fb + 2, fs, fe, k0, k1, L, zr, X, Y, tau, lz);
+    z2_iter<3, FUSE, STR>(c, st, fb + 3, fs, fe, k0, k1, L, zr, X, Y, tau, lz);
   }
   if (FUSE) fold_max(sh, slot, st.mx, st.mz, st.bad);
 }
 
-template <bool FUSE>
+template <bool FUSE, bool STR>
 __global__ __launch_bounds__(256) void sweep_z2d(Coef c, Shared* sh, const double* zr,
                                                  int slot, int first,
                                                  const double* __restrict__ X,
@@ -353,10 +414,10 @@ __global__ __launch_bounds__(256) void sweep_z2d(Coef c, Shared* sh, const doubl
   const int lane = threadIdx.x & 63;
   // wave-uniform by construction; readfirstlane lets the compiler keep it scalar
   const int w = __builtin_amdgcn_readfirstlane(xcd_block() * (blockDim.x >> 6) + (threadIdx.x >> 6));
-  const double dt = step_dt(c, sh, slot);
+  const double dt = step_dt<STR>(c, sh, slot);
   step_head(c, sh, slot, first, dt);
   if (w >= nwaves) return;
-  z2_wave<FUSE>(c, sh, zr, slot, dt, X, Y, kc, w % nstrips, w / nstrips, lane);
+  z2_wave<FUSE, STR>(c, sh, zr, slot, dt, X, Y, kc, w % nstrips, w / nstrips, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -373,6 +434,7 @@ struct X2 {
   P2 pp[4];
   double mx, mz;
   bool bad;
+  double icen1;  // stretched grid: 1/(z_k+1 - z_k-1) of row f-2, carried
 };
 
 // The stages of one march step f of L_x (ring slots as for L_z).
@@ -391,16 +453,17 @@ __device__ __forceinline__ void x2_load(const Coef& c, X2& st, int f, const Cols
 }
 
 // predictor on interior row f-1: X^P_i = X_i - (tau/dx)(F_i - F_{i-1})
+// icz: 1/(centred z span) of the row: dz/2 uniform, z_k+1 - z_k-1 stretched
 template <int S>
-__device__ __forceinline__ void x2_pred(const Coef& c, X2& st, double z, double lx) {
+__device__ __forceinline__ void x2_pred(const Coef& c, X2& st, double z, double lx, double icz) {
   using Z = ZS<S>;
   P2 q = st.pn[Z::c1];
   q.p = c.a * st.x[Z::c1].r * q.T;
   double dxux = (up(q.ux) - q.ux) * c.ihx;
   double dxuz = (up(q.uz) - q.uz) * c.ihx;
   double dxT = (up(q.T) - q.T) * c.ihx;
-  double dzux = (st.pn[Z::c0].ux - st.pn[Z::c2].ux) * (0.5 * c.ihz);
-  double dzuz = (st.pn[Z::c0].uz - st.pn[Z::c2].uz) * (0.5 * c.ihz);
+  double dzux = (st.pn[Z::c0].ux - st.pn[Z::c2].ux) * icz;
+  double dzuz = (st.pn[Z::c0].uz - st.pn[Z::c2].uz) * icz;
   N2 Fi = flux_x2(c, st.x[Z::c1], q, dxux, dxuz, dxT, dzux, dzuz);
   N2 Fm = dn(Fi);
   N2 v = st.x[Z::c1] - N2{lx * (Fi.r - Fm.r), lx * (Fi.mx - Fm.mx), lx * (Fi.mz - Fm.mz),
@@ -411,14 +474,14 @@ __device__ __forceinline__ void x2_pred(const Coef& c, X2& st, double z, double 
 
 // corrector, average and TVD term on interior row f-2
 template <int S>
-__device__ __forceinline__ N2 x2_corr(const Coef& c, const X2& st, double lx) {
+__device__ __forceinline__ N2 x2_corr(const Coef& c, const X2& st, double lx, double icz) {
   using Z = ZS<S>;
   const P2& q = st.pp[Z::c2];
   double dxux = (q.ux - dn(q.ux)) * c.ihx;
   double dxuz = (q.uz - dn(q.uz)) * c.ihx;
   double dxT = (q.T - dn(q.T)) * c.ihx;
-  double dzux = (st.pp[Z::c1].ux - st.pp[Z::c3].ux) * (0.5 * c.ihz);
-  double dzuz = (st.pp[Z::c1].uz - st.pp[Z::c3].uz) * (0.5 * c.ihz);
+  double dzux = (st.pp[Z::c1].ux - st.pp[Z::c3].ux) * icz;
+  double dzuz = (st.pp[Z::c1].uz - st.pp[Z::c3].uz) * icz;
   N2 Fi = flux_x2(c, st.xp[Z::c2], q, dxux, dxuz, dxT, dzux, dzuz);
   N2 Fp = up(Fi);
   const N2& x0 = st.x[Z::c2];
@@ -447,7 +510,7 @@ __device__ __forceinline__ N2 x2_corr(const Coef& c, const X2& st, double lx) {
 }
 
 // One march step (plate rows are copied through).
-template <int S, bool FUSE>
+template <int S, bool FUSE, bool STR>
 __device__ __forceinline__ void x2_iter(const Coef& c, X2& st, int f, int fs, int fe,
                                         int k0, int k1, const Cols& L,
                                         const double* __restrict__ zr,
@@ -458,24 +521,35 @@ __device__ __forceinline__ void x2_iter(const Coef& c, X2& st, int f, int fs, in
   if (f < fs || f > fe) return;
   const int M = c.M;
   const int r1 = f - 1;
+  // stretched grid: centred span of row r1 from the ring heights (rows past
+  // a plate hold clamped heights; their values are never used)
+  const double icen = STR ? frcp(st.zz[Z::c0] - st.zz[Z::c2]) : 0.5 * c.ihz;
   if (r1 >= k0 - 1 && r1 >= 0 && r1 <= M) {
     if (r1 == 0 || r1 == M) {
       st.xp[Z::c1] = st.x[Z::c1];
       st.pp[Z::c1] = st.pn[Z::c1];
     } else {
-      x2_pred<S>(c, st, st.zz[Z::c1], lx);
+      x2_pred<S>(c, st, st.zz[Z::c1], lx, icen);
     }
   }
   const int r = f - 2;
   if (r >= k0 && r < k1) {
-    N2 out = (r == 0 || r == M) ? st.x[Z::c2] : x2_corr<S>(c, st, lx);
-    if (FUSE) out_max(c, out, st.zz[Z::c2], st.mx, st.mz, st.bad, L.out);
+    N2 out = (r == 0 || r == M) ? st.x[Z::c2] : x2_corr<S>(c, st, lx, STR ? st.icen1 : icen);
+    if (FUSE) {
+      double izs = 1.0;
+      if (STR) {   // 1/(narrowest face of row r); one face at a plate
+        const double hu = st.zz[Z::c1] - st.zz[Z::c2], hd = st.zz[Z::c2] - st.zz[Z::c3];
+        izs = frcp(r == 0 ? hu : r == M ? hd : fmin(hu, hd));
+      }
+      out_max(c, out, st.zz[Z::c2], izs, st.mx, st.mz, st.bad, L.out);
+    }
     if (L.out) store2(c, Y, r, L.col, out);
   }
+  if (STR) st.icen1 = icen;
 }
 
 // one wave's share of L_x: columns of `strip`, output rows of `chunk`
-template <bool FUSE>
+template <bool FUSE, bool STR>
 __device__ __forceinline__ void x2_wave(const Coef& c, Shared* sh, const double* zr, int slot,
                                         double dt, const double* __restrict__ X,
                                         double* __restrict__ Y, int kc, int strip,
@@ -488,6 +562,7 @@ __device__ __forceinline__ void x2_wave(const Coef& c, Shared* sh, const double*
   st.mx = 0.0;
   st.mz = 0.0;
   st.bad = false;
+  st.icen1 = 0.0;
   const int fs = max(0, k0 - 2);
   const int fe = k1 + 1;
   // the kPF steps before fs only load rows fs .. fs+kPF-1 (their heads);
@@ -497,15 +572,15 @@ __device__ __forceinline__ void x2_wave(const Coef& c, Shared* sh, const double*
     st.pz[q] = 0.0;
   }
   for (int fb = (fs - kPF) & ~3; fb <= fe; fb += 4) {
-    x2_iter<0, FUSE>(c, st, fb + 0, fs, fe, k0, k1, L, zr, X, Y, lx);
-    x2_iter<1, FUSE>(c, st, fb + 1, fs, fe, k0, k1, L, zr, X, Y, lx);
-    x2_iter<2, FUSE>(c, st, fb + 2, fs, fe, k0, k1, L, zr, X, Y, lx);
-    x2_iter<3, FUSE>(c, st, fb + 3, fs, fe, k0, k1, L, zr, X, Y, lx);
+    x2_iter<0, FUSE, STR>(c, st, fb + 0, fs, fe, k0, k1, L, zr, X, Y, lx);
+    x2_iter<1, FUSE, STR>(c, st, fb + 1, fs, fe, k0, k1, L, zr, X, Y, lx);
+    x2_iter<2, FUSE, STR>(c, st, fb + 2, fs, fe, k0, k1, L, zr, X, Y, lx);
+    x2_iter<3, FUSE, STR>(c, st, fb + 3, fs, fe, k0, k1, L, zr, X, Y, lx);
   }
   if (FUSE) fold_max(sh, slot, st.mx, st.mz, st.bad);
 }
 
-template <bool FUSE>
+template <bool FUSE, bool STR>
 __global__ __launch_bounds__(256) void sweep_x2d(Coef c, Shared* sh, const double* zr,
                                                  int slot, int first,
                                                  const double* __restrict__ X,
@@ -514,10 +589,10 @@ __global__ __launch_bounds__(256) void sweep_x2d(Coef c, Shared* sh, const doubl
   const int lane = threadIdx.x & 63;
   // wave-uniform by construction; readfirstlane lets the compiler keep it scalar
   const int w = __builtin_amdgcn_readfirstlane(xcd_block() * (blockDim.x >> 6) + (threadIdx.x >> 6));
-  const double dt = step_dt(c, sh, slot);
+  const double dt = step_dt<STR>(c, sh, slot);
   step_head(c, sh, slot, first, dt);
   if (w >= nwaves) return;
-  x2_wave<FUSE>(c, sh, zr, slot, dt, X, Y, kc, w % nstrips, w / nstrips, lane);
+  x2_wave<FUSE, STR>(c, sh, zr, slot, dt, X, Y, kc, w % nstrips, w / nstrips, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -551,9 +626,11 @@ __global__ __launch_bounds__(256) void sweep_batch2d(const BoxDesc* __restrict__
   }
   const double* zr = zarena + bd->zoff;
   if (AXIS == 2)
-    z2_wave<FUSE>(c, sh, zr, slot, dt, X + bd->off, Y + bd->off, bd->kc_z, it.y, it.z, lane);
+    z2_wave<FUSE, false>(c, sh, zr, slot, dt, X + bd->off, Y + bd->off, bd->kc_z, it.y, it.z,
+                         lane);
   else
-    x2_wave<FUSE>(c, sh, zr, slot, dt, X + bd->off, Y + bd->off, bd->kc_x, it.y, it.z, lane);
+    x2_wave<FUSE, false>(c, sh, zr, slot, dt, X + bd->off, Y + bd->off, bd->kc_x, it.y, it.z,
+                         lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -567,9 +644,9 @@ int wave_slots_2d(int axis, bool fuse) {
     return 0;
   const void* fn;
   if (axis == 2)
-    fn = fuse ? (const void*)sweep_z2d<true> : (const void*)sweep_z2d<false>;
+    fn = fuse ? (const void*)sweep_z2d<true, false> : (const void*)sweep_z2d<false, false>;
   else
-    fn = fuse ? (const void*)sweep_x2d<true> : (const void*)sweep_x2d<false>;
+    fn = fuse ? (const void*)sweep_x2d<true, false> : (const void*)sweep_x2d<false, false>;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, 0) != hipSuccess) return 0;
   // at most two waves per SIMD (two 4-wave blocks per CU): where a third
   // fits, longer marches for two still measured faster (fewer halo rows)
@@ -602,17 +679,22 @@ hipError_t launch_sweep_2d(int axis, const Coef& c, Shared* sh, const double* zr
   const int nwaves = nstrips * nchunks;
   const int block = 256;
   const int grid = (nwaves + 3) / 4;
+#define MTVD_LAUNCH(K, F, T) K<F, T><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nwaves)
+  const bool st = c.stretched != 0;
   if (axis == 2) {
-    if (fuse)
-      sweep_z2d<true><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nwaves);
-    else
-      sweep_z2d<false><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nwaves);
+    if (st) {
+      if (fuse) MTVD_LAUNCH(sweep_z2d, true, true); else MTVD_LAUNCH(sweep_z2d, false, true);
+    } else {
+      if (fuse) MTVD_LAUNCH(sweep_z2d, true, false); else MTVD_LAUNCH(sweep_z2d, false, false);
+    }
   } else {
-    if (fuse)
-      sweep_x2d<true><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nwaves);
-    else
-      sweep_x2d<false><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nwaves);
+    if (st) {
+      if (fuse) MTVD_LAUNCH(sweep_x2d, true, true); else MTVD_LAUNCH(sweep_x2d, false, true);
+    } else {
+      if (fuse) MTVD_LAUNCH(sweep_x2d, true, false); else MTVD_LAUNCH(sweep_x2d, false, false);
+    }
   }
+#undef MTVD_LAUNCH
   return hipGetLastError();
 }
 

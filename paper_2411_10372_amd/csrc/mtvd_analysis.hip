@@ -192,7 +192,7 @@ extern "C" {
 int mtvd_analysis_from_profiles(const mtvd_params* p, const double* prof, size_t count,
                                 mtvd_analysis* out, double* tsa_z, double* drho_z, double* U_z) {
   if (!p || !prof || !out || p->nz < 5 || !(p->Ra > 0.0) || !(p->Pr > 0.0) ||
-      !(p->gamma > 1.0))
+      !(p->gamma > 1.0) || p->stretch != 0.0)
     return MTVD_EINVAL;
   const int nz = p->nz;
   if (count < (size_t)mtvd::kNumProfiles * (size_t)nz) return MTVD_ESIZE;

@@ -33,7 +33,7 @@ constexpr int kDiagOut = 32;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t shared, zrow, part, out, ppart, pout, total;
+  size_t shared, zrow, zmet, part, out, ppart, pout, total;
   int diag_nb;  // blocks per row of the diagnostics reduction
 };
 
@@ -50,6 +50,8 @@ Layout layout_of(const mtvd_params* p) {
   off = align_up(off + sizeof(Shared));
   L.zrow = off;
   off = align_up(off + sizeof(double) * (size_t)p->nz);
+  L.zmet = off;   // metric table of a stretched grid (empty when uniform)
+  if (p->stretch > 0.0) off = align_up(off + sizeof(double) * (size_t)p->nz * kZM);
   L.part = off;
   off = align_up(off + sizeof(double) * (size_t)p->nz * (size_t)nb * kDiagVals);
   L.out = off;
@@ -137,6 +139,7 @@ __global__ __launch_bounds__(256) void dt_kernel(Coef c, Shared* sh, const doubl
     double T = (X[n + (c.nf - 1) * c.cnt] * ri - ke - c.g * zr[k]) * c.icv;
     double cs = sqrt(c.gam_a * T);
     double sx = fabs(ux) + cs, sy = fabs(uy) + cs, sz = fabs(uz) + cs;
+    if (c.stretched) sz *= c.zm[(size_t)k * kZM + kZM_IHMIN];   // (|u_z| + c)/h_z,k
     m[0] = fmax(m[0], sx);
     m[1] = fmax(m[1], sy);
     m[2] = fmax(m[2], sz);
@@ -158,7 +161,7 @@ __global__ void freeze_dt_kernel(Coef c, Shared* sh, int slot) {
   if (threadIdx.x == 0) {
     Coef cc = c;
     cc.dt_mode = 0;
-    sh->dt_frozen = step_dt(cc, sh, slot);
+    sh->dt_frozen = cc.stretched ? step_dt<true>(cc, sh, slot) : step_dt<false>(cc, sh, slot);
   }
 }
 
@@ -214,7 +217,9 @@ __global__ __launch_bounds__(kDiagBlock) void diag_final_kernel(Coef c, const do
   const int t = threadIdx.x;
   double acc[5] = {0, 0, 0, 0, 0};
   for (int k = t; k < c.nz; k += kDiagBlock) {
-    double w = (k == 0 || k == c.M) ? 0.5 : 1.0;
+    // trapezoid weights in units of dz; a stretched grid's dual cells
+    double w = c.stretched ? c.zm[(size_t)k * kZM + kZM_W] * c.ihz
+                           : (k == 0 || k == c.M) ? 0.5 : 1.0;
     for (int q = 0; q < 5; ++q) {
       double s = 0.0;
       for (int b = 0; b < nb; ++b) s += part[((size_t)k * nb + b) * kDiagVals + q];
@@ -241,8 +246,13 @@ __global__ __launch_bounds__(kDiagBlock) void diag_final_kernel(Coef c, const do
     double mass = red[0][0] * dV, kin = red[1][0] * dV, Etot = red[2][0] * dV;
     double nuc = c.sRP / c.eps * (red[3][0] * dV / V);
     double nuk = c.D * c.sRP / 2.0 * (red[4][0] * dV / V);
-    double gb = ((-3.0 * tm[0] + 4.0 * tm[1]) - tm[2]) * (0.5 * c.ihz);
-    double gt = ((3.0 * tm[5] - 4.0 * tm[4]) + tm[3]) * (0.5 * c.ihz);
+    double ib = 0.5 * c.ihz, it = 0.5 * c.ihz;
+    if (c.stretched) {   // the plate stencils applied to the heights divide
+      ib = c.zm[kZM_IWALL];
+      it = c.zm[(size_t)c.M * kZM + kZM_IWALL];
+    }
+    double gb = ((-3.0 * tm[0] + 4.0 * tm[1]) - tm[2]) * ib;
+    double gt = ((3.0 * tm[5] - 4.0 * tm[4]) + tm[3]) * it;
     double nub = -(gb + c.D) / c.eps, nut = -(gt + c.D) / c.eps;
     out[0] = mass;
     out[1] = kin;
@@ -303,6 +313,57 @@ int hip_fail(mtvd_ctx* c, hipError_t e, const char* where) {
     if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
   } while (0)
 
+// Heights of the nz rows: uniform k/M, or the tanh grid of the stretch
+// parameter s, z_k = (1 + tanh(s (2k - M)/M) / tanh s) / 2, whose quotient
+// is exactly -1 and 1 at the ends (tanh is odd), so the plates sit at 0, 1.
+std::vector<double> grid_heights(double s, int nz) {
+  const int M = nz - 1;
+  std::vector<double> z(nz);
+  if (!(s > 0.0)) {
+    for (int k = 0; k < nz; ++k) z[k] = (double)k / (double)M;
+    return z;
+  }
+  const double ts = tanh(s);
+  for (int k = 0; k < nz; ++k) {
+    const double xi = (2.0 * (double)k - (double)M) / (double)M;
+    z[k] = 0.5 * (1.0 + tanh(s * xi) / ts);
+  }
+  return z;
+}
+
+// The per-row metric table of a stretched grid (kZM doubles per row, the
+// kZM_* slots): reciprocals of the face, centred and dual-cell spans, the
+// face length, the narrowest face of each node and the two plate stencils.
+std::vector<double> grid_metrics(const std::vector<double>& z) {
+  const int nz = (int)z.size(), M = nz - 1;
+  std::vector<double> m((size_t)nz * kZM, 0.0);
+  for (int k = 0; k < nz; ++k) {
+    double* r = &m[(size_t)k * kZM];
+    if (k < M) {
+      r[kZM_HF] = z[k + 1] - z[k];
+      r[kZM_IHF] = 1.0 / r[kZM_HF];
+    }
+    double w, hmin;
+    if (k == 0) {
+      w = 0.5 * (z[1] - z[0]);
+      hmin = z[1] - z[0];
+      r[kZM_IWALL] = 1.0 / ((-3.0 * z[0] + 4.0 * z[1]) - z[2]);
+    } else if (k == M) {
+      w = 0.5 * (z[M] - z[M - 1]);
+      hmin = z[M] - z[M - 1];
+      r[kZM_IWALL] = 1.0 / ((3.0 * z[M] - 4.0 * z[M - 1]) + z[M - 2]);
+    } else {
+      w = 0.5 * (z[k + 1] - z[k - 1]);
+      hmin = fmin(z[k] - z[k - 1], z[k + 1] - z[k]);
+      r[kZM_ICEN] = 1.0 / (z[k + 1] - z[k - 1]);
+    }
+    r[kZM_W] = w;
+    r[kZM_IW] = 1.0 / w;
+    r[kZM_IHMIN] = 1.0 / hmin;
+  }
+  return m;
+}
+
 int validate(const mtvd_params* p, std::string* why) {
   if (!p) { *why = "null params"; return MTVD_EINVAL; }
   if (p->ndim != 2 && p->ndim != 3) { *why = "ndim must be 2 or 3"; return MTVD_EINVAL; }
@@ -328,10 +389,16 @@ int validate(const mtvd_params* p, std::string* why) {
   if (p->sweep_order != 0 && p->sweep_order != 1) { *why = "sweep_order must be 0 or 1"; return MTVD_EINVAL; }
   if (p->tvd_on != 0 && p->tvd_on != 1) { *why = "tvd_on must be 0 or 1"; return MTVD_EINVAL; }
   if (p->wall_order != 1 && p->wall_order != 2) { *why = "wall_order must be 1 or 2"; return MTVD_EINVAL; }
+  if (!(p->stretch >= 0.0) || !(p->stretch <= 10.0)) { *why = "stretch must lie in [0, 10]"; return MTVD_EINVAL; }
+  if (p->stretch > 0.0 && p->ndim != 2) { *why = "a stretched z grid is 2D only"; return MTVD_EINVAL; }
   if (!(p->cfl > 0.0) || !(p->cfl <= 1.0)) { *why = "cfl must lie in (0, 1]"; return MTVD_ESTABILITY; }
   // diffusion number of the initial state (the acoustic limit sets dt):
   // max(mu(2+|lambda|), K/c_v) * tau / (rho_min h_min^2) <= 1/2
   double hx = p->aspect / p->nx, hz = 1.0 / (p->nz - 1);
+  if (p->stretch > 0.0) {
+    std::vector<double> z = grid_heights(p->stretch, p->nz);
+    hz = z[1] - z[0];   // the tanh grid's narrowest face sits at a plate
+  }
   double hmin = fmin(hx, hz);
   if (p->ndim == 3) hmin = fmin(hmin, p->aspect / p->ny);
   double Delta = p->eps + p->D;
@@ -390,6 +457,8 @@ Coef make_coef(const mtvd_params* p) {
   c.tvd_on = p->tvd_on;
   c.wall_order = p->wall_order;
   c.dt_mode = p->dt_mode;
+  c.stretched = p->stretch > 0.0;
+  c.zm = nullptr;   // set when the workspace is bound
   return c;
 }
 
@@ -588,8 +657,22 @@ int mtvd_bind(mtvd_ctx* c, double* buf_a, double* buf_b, void* workspace) {
   c->bound = true;
   c->have_state = false;
   HIPCHK(c, hipMemsetAsync(c->ws, 0, c->L.total, c->stream));
-  zrow_kernel<<<(c->c.nz + 255) / 256, 256, 0, c->stream>>>(c->c.nz, zrow_of(c));
-  HIPCHK(c, hipGetLastError());
+  if (c->c.stretched) {
+    // heights and metrics of the tanh grid, made on the host (the same
+    // libm tanh for every row) and copied once
+    std::vector<double> z = grid_heights(c->p.stretch, c->c.nz);
+    std::vector<double> m = grid_metrics(z);
+    double* zm = (double*)(c->ws + c->L.zmet);
+    HIPCHK(c, hipMemcpyAsync(zrow_of(c), z.data(), sizeof(double) * z.size(),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(zm, m.data(), sizeof(double) * m.size(), hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->c.zm = zm;
+  } else {
+    zrow_kernel<<<(c->c.nz + 255) / 256, 256, 0, c->stream>>>(c->c.nz, zrow_of(c));
+    HIPCHK(c, hipGetLastError());
+  }
   return MTVD_OK;
 }
 
@@ -673,7 +756,7 @@ int mtvd_diagnostics(mtvd_ctx* c, mtvd_diag* out) {
     // the same arithmetic as step_dt on the device
     double S[3];
     host_slot_max(hs, c->slot, S);
-    double m = fmin(c->c.hx / S[0], c->c.hz / S[2]);
+    double m = fmin(c->c.hx / S[0], (c->c.stretched ? 1.0 : c->c.hz) / S[2]);
     if (c->c.ndim == 3) m = fmin(m, c->c.hy / S[1]);
     out->dt = c->c.cfl * m;
   }
@@ -694,6 +777,7 @@ int mtvd_diagnostics(mtvd_ctx* c, mtvd_diag* out) {
 int mtvd_profiles(mtvd_ctx* c, double* out, size_t count) {
   if (!c || !out) return MTVD_EINVAL;
   if (!c->have_state) return set_err(c, MTVD_ESTATE, "no state");
+  if (c->c.stretched) return set_err(c, MTVD_EINVAL, "analysis profiles need the uniform z grid");
   const size_t n = (size_t)kNumProfiles * (size_t)c->c.nz;
   if (count < n) return set_err(c, MTVD_ESIZE, "profile array too small");
   double* part = (double*)(c->ws + c->L.ppart);
@@ -1015,6 +1099,10 @@ int batch_check(const mtvd_params* boxes, int nbox, bool sizes_only, std::string
     }
     if (boxes[i].ndim != 2) {
       *why = "box " + std::to_string(i) + ": batches hold 2D boxes only";
+      return MTVD_EINVAL;
+    }
+    if (boxes[i].stretch != 0.0) {
+      *why = "box " + std::to_string(i) + ": batches use the uniform z grid";
       return MTVD_EINVAL;
     }
     if (boxes[i].dt_mode != boxes[0].dt_mode || boxes[i].sweep_order != boxes[0].sweep_order) {
@@ -1459,6 +1547,7 @@ int adj_check(const mtvd_params* p, int32_t nsteps, int32_t every, std::string* 
   if (rc != MTVD_OK) return rc;
   if (p->ndim != 2) { *why = "the adjoint is 2D only"; return MTVD_EINVAL; }
   if (p->limiter_form != 0) { *why = "the adjoint reverses the printed limiter form (limiter_form 0) only"; return MTVD_EINVAL; }
+  if (p->stretch != 0.0) { *why = "the adjoint needs the uniform z grid"; return MTVD_EINVAL; }
   if (nsteps < 1) { *why = "nsteps must be >= 1"; return MTVD_EINVAL; }
   if (every < 1) { *why = "checkpoint interval must be >= 1"; return MTVD_EINVAL; }
   return MTVD_OK;

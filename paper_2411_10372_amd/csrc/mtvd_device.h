@@ -30,7 +30,28 @@ struct Coef {
   double noise_amp;
   uint64_t seed;
   int limiter_form, tvd_on, wall_order, dt_mode;
+  // tanh-stretched z grid (2D): per-row metric table of kZM doubles per row
+  // (see the kZM_* slots), device memory in the workspace; null when uniform
+  int stretched;
+  const double* zm;
 };
+
+// Slots of a row's entry in the metric table of a stretched grid.  Every
+// z difference divides by the same difference of the node heights; the
+// table holds the reciprocals (and the two lengths the TVD flux and the
+// volume weights use).
+constexpr int kZM = 8;
+constexpr int kZM_IHF = 0;    // 1/(z_k+1 - z_k), face k+1/2 (rows 0..M-1)
+constexpr int kZM_ICEN = 1;   // 1/(z_k+1 - z_k-1), centred span (rows 1..M-1)
+constexpr int kZM_IW = 2;     // 1/w_k, w_k the dual cell (half a face at a plate)
+constexpr int kZM_HF = 3;     // z_k+1 - z_k
+constexpr int kZM_IHMIN = 4;  // 1/min of the node's faces (dt)
+constexpr int kZM_IWALL = 5;  // row 0: 1/(-3 z0 + 4 z1 - z2); row M: 1/(3 zM - 4 zM-1 + zM-2)
+constexpr int kZM_W = 6;      // w_k (volume weight)
+
+__device__ __forceinline__ double zmet(const Coef& c, int k, int slot) {
+  return c.zm[k * kZM + slot];
+}
 
 // Partial maxima per step slot: the blocks of a launch fold into
 // kMaxParts addresses (block index mod kMaxParts) instead of one, so the
@@ -96,10 +117,12 @@ __device__ __forceinline__ double slot_max(const Shared* sh, int slot, int a) {
   return u2d(m);
 }
 
+// STR: a stretched z grid, whose z slot holds max (|u_z| + c)/h_z,k already
+template <bool STR = false>
 __device__ __forceinline__ double step_dt(const Coef& c, const Shared* sh, int slot) {
   if (c.dt_mode) return sh->dt_frozen;
   double m = c.hx / slot_max(sh, slot, 0);
-  double mz = c.hz / slot_max(sh, slot, 2);
+  double mz = (STR ? 1.0 : c.hz) / slot_max(sh, slot, 2);
   m = fmin(m, mz);
   if (c.ndim == 3) m = fmin(m, c.hy / slot_max(sh, slot, 1));
   return c.cfl * m;

@@ -14,6 +14,10 @@ WORKLOADS = {
     # 2D 4096 x 1024, Ra 1e10, 1000 steps, diagnostics every 100: the benchmark case
     "2d_4096x1024_ra1e10": dict(COMMON, ndim=2, nx=4096, ny=1, nz=1024, Ra=1e10, seed=1,
                                 steps=1000, diag_every=100),
+    # the same on the tanh-stretched z grid, s = 1.2 (the plate cells are
+    # 2s/sinh(2s) = 0.44 of the uniform spacing)
+    "2d_4096x1024_ra1e10_tanh1.2": dict(COMMON, ndim=2, nx=4096, ny=1, nz=1024, Ra=1e10,
+                                        seed=1, steps=1000, diag_every=100, stretch=1.2),
     # 3D 1024 x 1024 x 256, Ra 1e9, 200 steps
     "3d_1024x1024x256_ra1e9": dict(COMMON, ndim=3, nx=1024, ny=1024, nz=256, Ra=1e9, seed=2,
                                    steps=200),
@@ -28,7 +32,7 @@ WORKLOADS = {
 }
 
 PARAM_KEYS = ("ndim", "nx", "ny", "nz", "aspect", "gamma", "Pr", "Ra", "eps", "D", "cfl",
-              "seed", "noise_amp", "dt_mode")
+              "seed", "noise_amp", "dt_mode", "stretch")
 
 
 def params_dict(name: str, **overrides) -> dict:
