@@ -132,6 +132,12 @@ typedef struct mtvd_ctx mtvd_ctx;
 
 void mtvd_default_params(mtvd_params* p);
 
+/* Host only, no device work: the nz node heights z_k of the grid these
+ * parameters define (uniform, or the tanh grid of `stretch`; Sec. 3.1) into
+ * z[0..nz-1] (count >= nz).  MTVD_EINVAL on bad parameters, MTVD_ESIZE if
+ * count is too small. */
+int mtvd_grid_heights(const mtvd_params* p, double* z, size_t count);
+
 /* Bytes of one state buffer and of the workspace for these parameters. */
 int mtvd_state_bytes(const mtvd_params* p, size_t* state_bytes,
                      size_t* workspace_bytes);

@@ -132,6 +132,7 @@ def lib() -> ctypes.CDLL:
         L.mtvd_default_params.restype = None
         L.mtvd_state_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t),
                                        ctypes.POINTER(ctypes.c_size_t)]
+        L.mtvd_grid_heights.argtypes = [P, dp, ctypes.c_size_t]
         L.mtvd_create.argtypes = [P, vp, ctypes.POINTER(vp)]
         L.mtvd_bind.argtypes = [vp, vp, vp, vp]
         L.mtvd_init_state.argtypes = [vp]
@@ -233,6 +234,18 @@ def bl_thickness(tmean, D: float, rtol: float = 0.1):
     if rc != MTVD_OK:
         raise MtvdError(rc, lib().mtvd_strerror(rc).decode())
     return lb.value, lt.value
+
+
+def grid_heights(p: Params) -> np.ndarray:
+    """The nz node heights of the grid (uniform, or the tanh grid of
+    p.stretch)."""
+    z = np.empty(p.nz, dtype=np.float64)
+    pc = p._c()
+    rc = lib().mtvd_grid_heights(ctypes.byref(pc), z.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                 z.size)
+    if rc != MTVD_OK:
+        raise MtvdError(rc, lib().mtvd_strerror(rc).decode())
+    return z
 
 
 def state_bytes(p: Params):

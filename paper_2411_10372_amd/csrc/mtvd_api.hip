@@ -595,6 +595,17 @@ void mtvd_default_params(mtvd_params* p) {
   p->wall_order = 2;
 }
 
+int mtvd_grid_heights(const mtvd_params* p, double* z, size_t count) {
+  std::string why;
+  int rc = validate(p, &why);
+  if (rc != MTVD_OK && rc != MTVD_ESTABILITY) return rc;
+  if (!z) return MTVD_EINVAL;
+  if (count < (size_t)p->nz) return MTVD_ESIZE;
+  std::vector<double> h = grid_heights(p->stretch, p->nz);
+  for (int k = 0; k < p->nz; ++k) z[k] = h[k];
+  return MTVD_OK;
+}
+
 int mtvd_state_bytes(const mtvd_params* p, size_t* state_bytes, size_t* workspace_bytes) {
   std::string why;
   int rc = validate(p, &why);

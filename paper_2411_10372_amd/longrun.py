@@ -27,7 +27,7 @@ from fractions import Fraction
 
 import numpy as np
 
-from . import Params, Solver, analysis, bl_thickness
+from . import Params, Solver, analysis, bl_thickness, grid_heights
 
 SCALARS = ("nu_mean", "nu_bottom", "nu_top", "nu_bulk", "nu_conv", "nu_kin", "Re", "C",
            "Fn", "Fp", "Fb", "Fv")
@@ -40,11 +40,33 @@ def _mean_err(x: np.ndarray):
     return float(np.mean(x)), err
 
 
+def _dual_weights(z: np.ndarray) -> np.ndarray:
+    """Trapezoid weights of the rows (the dual cells; half a face at a
+    plate), summing to the height 1."""
+    w = np.empty_like(z)
+    w[1:-1] = 0.5 * (z[2:] - z[:-2])
+    w[0], w[-1] = 0.5 * (z[1] - z[0]), 0.5 * (z[-1] - z[-2])
+    return w
+
+
+def _re_from_state(p: Params, X: np.ndarray, w: np.ndarray) -> float:
+    """Re = sqrt(Ra/Pr) sqrt(<|u|^2>_V) of a snapshot (Sec. 2), with the rows
+    weighted by their dual cells (used on a stretched grid, where the
+    analysis profiles are not available)."""
+    rho = X[0]
+    u2 = sum((X[f] / rho) ** 2 for f in range(1, p.ndim + 1))
+    rows = u2.mean(axis=tuple(range(1, u2.ndim)))
+    return float(np.sqrt(p.Ra / p.Pr) * np.sqrt(np.sum(w * rows)))
+
+
 def time_averages(p: Params, t0: float, t1: float, sample_steps: int = 100,
                   wall_limit: float | None = None, rtol: float = 0.1, progress=None) -> dict:
     """Run from the initial state until the simulated time reaches t1 (or
     the wall-clock limit), sampling every `sample_steps` steps; average the
-    samples with time >= t0."""
+    samples with time >= t0.  On a stretched grid only the step diagnostics
+    and Re (from the state) are sampled."""
+    stretched = p.stretch > 0.0
+    w = _dual_weights(grid_heights(p)) if stretched else None
     s = Solver(p)
     try:
         s.init_state()
@@ -55,15 +77,19 @@ def time_averages(p: Params, t0: float, t1: float, sample_steps: int = 100,
         while True:
             s.step(sample_steps)
             d = s.diagnostics()
-            prof = s.profiles()
-            a = analysis(p, prof)
             row = {k: d[k] for k in SCALARS if k in d}
-            row.update({k: a[k] for k in ("Re", "C", "Fn", "Fp", "Fb", "Fv")})
+            if stretched:
+                a = {"Re": _re_from_state(p, s.get_state(), w)}
+                row["Re"] = a["Re"]
+            else:
+                prof = s.profiles()
+                a = analysis(p, prof)
+                row.update({k: a[k] for k in ("Re", "C", "Fn", "Fp", "Fb", "Fv")})
+                if d["time"] >= t0:
+                    prof_sum = prof.copy() if prof_sum is None else prof_sum + prof
+                    n_prof += 1
             row["time"] = d["time"]
             samples.append(row)
-            if d["time"] >= t0:
-                prof_sum = prof.copy() if prof_sum is None else prof_sum + prof
-                n_prof += 1
             now = time.time()
             if progress and now - last > 20.0:
                 progress({"step": d["step"], "time": round(d["time"], 3), "dt": d["dt"],
@@ -77,7 +103,9 @@ def time_averages(p: Params, t0: float, t1: float, sample_steps: int = 100,
                "wall_s": round(time.time() - start, 1)}
         if len(sel) >= 5:
             for k in SCALARS:
-                out[k] = _mean_err(np.array([r[k] for r in sel]))
+                if k in sel[0]:
+                    out[k] = _mean_err(np.array([r[k] for r in sel]))
+        if len(sel) >= 5 and n_prof:
             mean_prof = prof_sum / n_prof
             a = analysis(p, mean_prof)
             out["lambda_b"], out["lambda_t"] = bl_thickness(mean_prof[0], p.D, rtol)
@@ -103,6 +131,8 @@ def main(argv=None) -> int:
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--noise", type=float, default=1e-3)
     ap.add_argument("--limiter-form", type=int, default=0)
+    ap.add_argument("--stretch", type=float, default=0.0,
+                    help="tanh z-grid parameter s (0: uniform; 2D only)")
     ap.add_argument("--t0", type=float, required=True, help="start of the averaging window")
     ap.add_argument("--t1", type=float, required=True, help="simulated end time")
     ap.add_argument("--sample-steps", type=int, default=100)
@@ -112,14 +142,15 @@ def main(argv=None) -> int:
     a = ap.parse_args(argv)
     p = Params(ndim=a.ndim, nx=a.nx, ny=(a.ny or a.nx) if a.ndim == 3 else 1, nz=a.nz,
                aspect=a.aspect, gamma=float(Fraction(a.gamma)), Pr=a.Pr, Ra=a.Ra, eps=a.eps,
-               D=a.D, seed=a.seed, noise_amp=a.noise, limiter_form=a.limiter_form)
+               D=a.D, seed=a.seed, noise_amp=a.noise, limiter_form=a.limiter_form,
+               stretch=a.stretch)
     out = time_averages(p, a.t0, a.t1, a.sample_steps, a.wall, a.rtol,
                         progress=lambda d: print(json.dumps(d), file=sys.stderr, flush=True))
     if not a.profiles:
         out.pop("profiles", None)
     out["params"] = {k: getattr(p, k) for k in ("ndim", "nx", "ny", "nz", "aspect", "gamma", "Pr",
                                                  "Ra", "eps", "D", "seed", "noise_amp",
-                                                 "limiter_form")}
+                                                 "limiter_form", "stretch")}
     print(json.dumps(out), flush=True)
     return 0
 

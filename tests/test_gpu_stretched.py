@@ -224,3 +224,15 @@ def test_stretched_grid_rules_on_the_host():
     prof = np.ones(10 * 17)
     with pytest.raises(mtvd.MtvdError):
         mtvd.analysis(mtvd.Params(nx=64, nz=17, stretch=1.0), prof.reshape(10, 17))
+
+
+def test_library_and_oracle_grids_are_the_same_bits():
+    # the heights the kernels use (made on the host, copied at bind) and the
+    # oracle's: the same definition evaluated with the same libm tanh
+    mtvd, _ = _lib()
+    for nz, s in ((5, 2.0), (37, 0.8), (1024, 1.2), (64, 0.0)):
+        po = oracle.Params(nz=nz, stretch=s)
+        zg = mtvd.grid_heights(mtvd.Params(nz=nz, stretch=s))
+        assert np.array_equal(zg, oracle.heights(po)), (nz, s)
+    with pytest.raises(mtvd.MtvdError):
+        mtvd.grid_heights(mtvd.Params(nz=9, stretch=-1.0))
