@@ -21,6 +21,9 @@ WORKLOADS = {
     # 3D 1024 x 1024 x 256, Ra 1e9, 200 steps
     "3d_1024x1024x256_ra1e9": dict(COMMON, ndim=3, nx=1024, ny=1024, nz=256, Ra=1e9, seed=2,
                                    steps=200),
+    # the same on the tanh-stretched z grid, s = 1.2
+    "3d_1024x1024x256_ra1e9_tanh1.2": dict(COMMON, ndim=3, nx=1024, ny=1024, nz=256, Ra=1e9,
+                                           seed=2, steps=200, stretch=1.2),
     # 2D 512 x 128, Ra 1e7, 500 steps, dt frozen: the adjoint case
     "2d_512x128_ra1e7": dict(COMMON, ndim=2, nx=512, ny=1, nz=128, Ra=1e7, seed=4, steps=500,
                              dt_mode=1),
