@@ -153,11 +153,13 @@ struct Acc3 {
   bool bad;
 };
 
-__device__ __forceinline__ void acc_out(const Coef& c, const N3& o, double z, Acc3& a,
-                                        bool on) {
+// izs: 1 on the uniform grid; 1/h_z of the node on a stretched one (the z
+// entry then collects (|u_z| + c)/h_z, which dt divides into 1)
+__device__ __forceinline__ void acc_out(const Coef& c, const N3& o, double z, double izs,
+                                        Acc3& a, bool on) {
   P3 q = prim3(c, o, z);
   double cs = sound(c, q.T);
-  double s0 = fabs(q.u[0]) + cs, s1 = fabs(q.u[1]) + cs, s2 = fabs(q.u[2]) + cs;
+  double s0 = fabs(q.u[0]) + cs, s1 = fabs(q.u[1]) + cs, s2 = (fabs(q.u[2]) + cs) * izs;
   if (on) {
     a.s[0] = fmax(a.s[0], s0);
     a.s[1] = fmax(a.s[1], s1);
@@ -205,25 +207,34 @@ struct MF {
   P3 pp[4];
   N3 FP[2];
   Acc3 acc;
+  // stretched grid (L_z) only: heights prefetched with their rows, and the
+  // metrics derived from them carried one march step
+  double pz[2], zz[4];
+  double ihf1, ihf2, iw1;  // 1/h of faces f-3+1/2, f-4+1/2; 1/w of row f-3
+  double iwb, iwt;         // the plate stencils' 1/(stencil applied to z)
 };
 
 // PL: the chunk may touch a plate (L_z).  Chunks that cannot (first row
 // >= 4, last row <= M-4: every stage then works on rows 2..M-4) run a copy
 // compiled without the plate and wall code, whose registers fit without
 // spilling.
-template <int AX, int S, bool FUSE, bool PL>
+// STR: a stretched z grid.  L_z takes every z spacing from the prefetched
+// heights; L_y (waves along z) gets its wave's centred span and narrowest
+// face in ihb2 and izw.
+template <int AX, int S, bool FUSE, bool PL, bool STR>
 __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, int fe, int m0,
                                         int m1, int w, int lane, const Lane3& L, int bidx,
                                         bool bval, bool bwall, bool owave,
                                         double (&xa)[2][2][kNW][64], double (&xb)[2][2][kNW][64],
                                         const double* __restrict__ zr,
                                         const double* __restrict__ X, double* __restrict__ Y,
-                                        double tau, double lm, int bload, double zb) {
+                                        double tau, double lm, int bload, double zb,
+                                        double ihb2, double izw) {
   constexpr int B = (AX == 2) ? 1 : 2;   // axis of the waves
   constexpr bool P = (AX == 2) && PL;    // plate rows possible in this chunk
+  constexpr bool SZ = STR && AX == 2;    // stretched march along z
   const int M = c.M;
   const double ihm = (AX == 2) ? c.ihz : c.ihy;
-  const double ihb2 = 0.5 * ((B == 1) ? c.ihy : c.ihz);
   constexpr int c0 = S & 3, c1 = (S + 3) & 3, c2 = (S + 2) & 3, c3 = (S + 1) & 3, c4 = S & 3;
   constexpr int e0 = S & 1, e1 = (S + 1) & 1;
   const int role = (w == 0 || w == kNW - 1) ? 0 : ((w == 1 || w == kNW - 2) ? 1 : 2);
@@ -241,17 +252,28 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
   //    ring slots no stage reads, and their exchanged values are zeroed.
   {
     st.x[c0] = st.pf[e0];
+    if (SZ) st.zz[c0] = st.pz[e0];
     const int fp = (AX == 2) ? min(max(f + 2, 0), M) : f + 2;
     const long long np = (AX == 2) ? ((long long)fp * c.ny + bidx) * c.nx + L.col
                                    : ((long long)bload * c.ny + wrap(fp, c.ny)) * c.nx + L.col;
     st.pf[e0] = load3(c, X, np);
-    st.pn[c0] = prim3(c, st.x[c0], (AX == 2) ? zrow(f, M) : zb);
+    if (SZ) st.pz[e0] = zr[fp];
+    st.pn[c0] = prim3(c, st.x[c0], SZ ? st.zz[c0] : (AX == 2) ? zrow(f, M) : zb);
     st.s[c0] = fabs(st.pn[c0].u[AX]) + sound(c, st.pn[c0].T);
   }
   if (f < fs || f > fe) return;
   // heights of rows f-2 and f-3 (L_z) or of the wave's plane (L_y)
-  const double z_r = (AX == 2) ? zrow(f - 2, M) : zb, z_o = (AX == 2) ? zrow(f - 3, M) : zb;
+  const double z_r = SZ ? st.zz[c2] : (AX == 2) ? zrow(f - 2, M) : zb;
+  const double z_o = SZ ? st.zz[c3] : (AX == 2) ? zrow(f - 3, M) : zb;
   const int r = f - 2;
+  // stretched L_z: face r+1/2 and dual cell of row r from the ring heights
+  // (rows past a plate hold clamped heights; their values are never used)
+  double hf = 0.0, ihf = 0.0, iw = 0.0;
+  if (SZ) {
+    hf = st.zz[c1] - st.zz[c2];
+    ihf = frcp(hf);
+    iw = 2.0 * frcp(st.zz[c1] - st.zz[c3]);
+  }
   const bool rin_F = P ? (r >= 0 && r <= M - 1) : true;
   // B: predictor flux F_r (inner derivatives forward along the march); the
   //    cross-wave derivatives of row r first (every wave of the block takes
@@ -268,14 +290,15 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
     double dT;
     if (P && r == 0 && c.wall_order == 2) {
       const P3& q2 = st.pn[c0];
-      double h2 = 0.5 * ihm;
+      double h2 = SZ ? st.iwb : 0.5 * ihm;
 #pragma unroll
       for (int g = 0; g < 3; ++g) du[g][AX] = ((-3.0 * q0.u[g] + 4.0 * q1.u[g]) - q2.u[g]) * h2;
       dT = ((-3.0 * q0.T + 4.0 * q1.T) - q2.T) * h2;
     } else {
+      const double ih = SZ ? ihf : ihm;
 #pragma unroll
-      for (int g = 0; g < 3; ++g) du[g][AX] = (q1.u[g] - q0.u[g]) * ihm;
-      dT = (q1.T - q0.T) * ihm;
+      for (int g = 0; g < 3; ++g) du[g][AX] = (q1.u[g] - q0.u[g]) * ih;
+      dT = (q1.T - q0.T) * ih;
     }
     du[0][0] = (shd(q0.u[0]) - shu(q0.u[0])) * (0.5 * c.ihx);
     du[AX][0] = (shd(q0.u[AX]) - shu(q0.u[AX])) * (0.5 * c.ihx);
@@ -298,18 +321,20 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
         st.xp[c2] = N3{rho, {0.0, 0.0, 0.0}, rho * (c.cv * c.Tb + c.g * z_r)};
         st.pp[c2] = P3{{0.0, 0.0, 0.0}, c.Tb, c.a * rho * c.Tb};
       } else if (P && r == M) {
-        double rho = st.x[c2].r - lm * (st.x[c2].m[2] - st.x[c3].m[2]);
+        const double lt = SZ ? tau * st.ihf1 : lm;   // face M-1/2
+        double rho = st.x[c2].r - lt * (st.x[c2].m[2] - st.x[c3].m[2]);
         st.xp[c2] = N3{rho, {0.0, 0.0, 0.0}, rho * (c.cv * c.Tt + c.g * z_r)};
         st.pp[c2] = P3{{0.0, 0.0, 0.0}, c.Tt, c.a * rho * c.Tt};
       } else {
         const N3& Fa = st.F[e0];
         const N3& Fb = st.F[e1];
         const N3& x0 = st.x[c2];
+        const double lr = SZ ? tau * iw : lm;
         N3 v;
-        v.r = x0.r - lm * (Fa.r - Fb.r);
+        v.r = x0.r - lr * (Fa.r - Fb.r);
 #pragma unroll
-        for (int g = 0; g < 3; ++g) v.m[g] = x0.m[g] - lm * (Fa.m[g] - Fb.m[g]);
-        v.E = x0.E - lm * (Fa.E - Fb.E);
+        for (int g = 0; g < 3; ++g) v.m[g] = x0.m[g] - lr * (Fa.m[g] - Fb.m[g]);
+        v.E = x0.E - lr * (Fa.E - Fb.E);
         if (AX == 2) v.m[2] = v.m[2] + tau * (-c.g * x0.r);
         st.xp[c2] = v;
         st.pp[c2] = prim3(c, v, z_r);
@@ -328,14 +353,15 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
     double dT;
     if (P && r == M && c.wall_order == 2) {
       const P3& qmm = st.pp[c4];
-      double h2 = 0.5 * ihm;
+      double h2 = SZ ? st.iwt : 0.5 * ihm;
 #pragma unroll
       for (int g = 0; g < 3; ++g) du[g][AX] = ((3.0 * q0.u[g] - 4.0 * qm.u[g]) + qmm.u[g]) * h2;
       dT = ((3.0 * q0.T - 4.0 * qm.T) + qmm.T) * h2;
     } else {
+      const double ih = SZ ? st.ihf1 : ihm;   // face r-1/2
 #pragma unroll
-      for (int g = 0; g < 3; ++g) du[g][AX] = (q0.u[g] - qm.u[g]) * ihm;
-      dT = (q0.T - qm.T) * ihm;
+      for (int g = 0; g < 3; ++g) du[g][AX] = (q0.u[g] - qm.u[g]) * ih;
+      dT = (q0.T - qm.T) * ih;
     }
     du[0][0] = (shd(q0.u[0]) - shu(q0.u[0])) * (0.5 * c.ihx);
     du[AX][0] = (shd(q0.u[AX]) - shu(q0.u[AX])) * (0.5 * c.ihx);
@@ -352,8 +378,9 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
       N3 dm = sub3(st.x[c2], st.x[c3]);
       N3 d0 = sub3(st.x[c1], st.x[c2]);
       N3 dp = sub3(st.x[c0], st.x[c1]);
-      double Co = lm * fmax(st.s[c2], st.s[c1]);
+      double Co = (SZ ? tau * ihf : lm) * fmax(st.s[c2], st.s[c1]);
       G = tvd_G(c, dot3(dm, d0), dot3(d0, dp), dot3(d0, d0), Co);
+      if (SZ) G = G * hf;   // the face's dissipative flux carries its spacing
     }
     st.G[e0] = G;
   }
@@ -371,18 +398,28 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
       const N3& x0 = st.x[c3];
       const N3& xp = st.xp[c3];
       const N3& Dm = st.Dp;
+      const double lo = SZ ? tau * st.iw1 : lm;
       N3 xc;
-      xc.r = x0.r - lm * (fp1.r - fp0.r);
+      xc.r = x0.r - lo * (fp1.r - fp0.r);
 #pragma unroll
-      for (int g = 0; g < 3; ++g) xc.m[g] = x0.m[g] - lm * (fp1.m[g] - fp0.m[g]);
-      xc.E = x0.E - lm * (fp1.E - fp0.E);
+      for (int g = 0; g < 3; ++g) xc.m[g] = x0.m[g] - lo * (fp1.m[g] - fp0.m[g]);
+      xc.E = x0.E - lo * (fp1.E - fp0.E);
       if (AX == 2) xc.m[2] = xc.m[2] + tau * (-c.g * xp.r);
       N3 out;
-      out.r = 0.5 * (xp.r + xc.r) + (Dc.r - Dm.r);
+      if (SZ) {   // face fluxes over the dual cell of row o
+        const double iwo = st.iw1;
+        out.r = 0.5 * (xp.r + xc.r) + (Dc.r - Dm.r) * iwo;
 #pragma unroll
-      for (int g = 0; g < 3; ++g) out.m[g] = 0.5 * (xp.m[g] + xc.m[g]) + (Dc.m[g] - Dm.m[g]);
-      out.E = 0.5 * (xp.E + xc.E) + (Dc.E - Dm.E);
-      if (FUSE) acc_out(c, out, z_o, st.acc, L.out);
+        for (int g = 0; g < 3; ++g)
+          out.m[g] = 0.5 * (xp.m[g] + xc.m[g]) + (Dc.m[g] - Dm.m[g]) * iwo;
+        out.E = 0.5 * (xp.E + xc.E) + (Dc.E - Dm.E) * iwo;
+      } else {
+        out.r = 0.5 * (xp.r + xc.r) + (Dc.r - Dm.r);
+#pragma unroll
+        for (int g = 0; g < 3; ++g) out.m[g] = 0.5 * (xp.m[g] + xc.m[g]) + (Dc.m[g] - Dm.m[g]);
+        out.E = 0.5 * (xp.E + xc.E) + (Dc.E - Dm.E);
+      }
+      if (FUSE) acc_out(c, out, z_o, SZ ? fmax(st.ihf1, st.ihf2) : izw, st.acc, L.out);
       if (L.out) store3(c, Y, node(o), out);
     }
     st.Dp = Dc;
@@ -392,18 +429,25 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
     if (bwall) {
       out = st.x[c3];
     } else if (o == 0) {
-      double rho = st.x[c3].r - lm * (st.xp[c2].m[2] - 0.0);
+      const double lb = SZ ? tau * st.ihf1 : lm;   // face 1/2
+      double rho = st.x[c3].r - lb * (st.xp[c2].m[2] - 0.0);
       out = N3{rho, {0.0, 0.0, 0.0}, rho * (c.cv * c.Tb + c.g * z_o)};
     } else {
       double rho = st.xp[c3].r;
       out = N3{rho, {0.0, 0.0, 0.0}, rho * (c.cv * c.Tt + c.g * z_o)};
     }
-    if (FUSE) acc_out(c, out, z_o, st.acc, L.out);
+    if (FUSE)
+      acc_out(c, out, z_o, SZ ? (bwall ? izw : o == 0 ? st.ihf1 : st.ihf2) : izw, st.acc, L.out);
     if (L.out) store3(c, Y, node(o), out);
+  }
+  if (SZ) {
+    st.ihf2 = st.ihf1;
+    st.ihf1 = ihf;
+    st.iw1 = iw;
   }
 }
 
-template <int AX, bool FUSE, bool PL>
+template <int AX, bool FUSE, bool PL, bool STR>
 __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const double* zr,
                                                        int slot, int first,
                                                        const double* __restrict__ X,
@@ -414,7 +458,7 @@ __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const
   constexpr int B = (AX == 2) ? 1 : 2;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
-  const double dt = step_dt(c, sh, slot);
+  const double dt = step_dt<STR>(c, sh, slot);
   head3(sh, slot, first, dt);
   int bid = xcd_block();
   const int strip = bid % nstrips;
@@ -451,14 +495,31 @@ __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const
   // height
   const int bload = (AX == 1) ? min(max(bidx, 0), c.M) : bidx;
   const double zb = (AX == 1) ? zr[bload] : 0.0;
+  // the centred span across the waves (y for L_z; z for L_y, which on a
+  // stretched grid is the wave's plane's own) and, for L_y's dt entry, the
+  // plane's narrowest face
+  double ihb2 = 0.5 * ((B == 1) ? c.ihy : c.ihz), izw = 1.0;
+  if (STR) {
+    st.ihf1 = st.ihf2 = st.iw1 = 0.0;
+    st.pz[0] = st.pz[1] = 0.0;
+    st.iwb = st.iwt = 0.0;
+    if (AX == 2) {
+      st.iwb = zmet(c, 0, kZM_IWALL);
+      st.iwt = zmet(c, c.M, kZM_IWALL);
+    } else {
+      const double zu = zr[min(bload + 1, c.M)], zd = zr[max(bload - 1, 0)];
+      if (bload >= 1 && bload <= c.M - 1) ihb2 = frcp(zu - zd);
+      izw = frcp(bload == 0 ? zu - zb : bload == c.M ? zb - zd : fmin(zu - zb, zb - zd));
+    }
+  }
   // the steps fs-2 and fs-1 only load rows fs and fs+1 (their heads); the
   // heads before them copy this defined, unused row
   st.pf[0] = st.pf[1] = N3{1.0, {0.0, 0.0, 0.0}, 1.0};
   for (int fb = (fs - 2) & ~3; fb <= fe; fb += 4) {
-    mf_iter<AX, 0, FUSE, PL>(c, st, fb + 0, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, bload, zb);
-    mf_iter<AX, 1, FUSE, PL>(c, st, fb + 1, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, bload, zb);
-    mf_iter<AX, 2, FUSE, PL>(c, st, fb + 2, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, bload, zb);
-    mf_iter<AX, 3, FUSE, PL>(c, st, fb + 3, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, bload, zb);
+    mf_iter<AX, 0, FUSE, PL, STR>(c, st, fb + 0, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, bload, zb, ihb2, izw);
+    mf_iter<AX, 1, FUSE, PL, STR>(c, st, fb + 1, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, bload, zb, ihb2, izw);
+    mf_iter<AX, 2, FUSE, PL, STR>(c, st, fb + 2, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, bload, zb, ihb2, izw);
+    mf_iter<AX, 3, FUSE, PL, STR>(c, st, fb + 3, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, bload, zb, ihb2, izw);
   }
   if (FUSE) fold3(sh, slot, st.acc);
 }
@@ -476,9 +537,11 @@ struct LF {
   P3 pp[4];
   double pyx[4], pyy[4];   // d_y u_x, d_y u_y of X^P
   Acc3 acc;
+  double pz[2], zz[4];     // stretched grid: heights prefetched with their rows
+  double icen1;            // stretched grid: 1/(z_k+1 - z_k-1) of row f-2
 };
 
-template <int S, bool FUSE>
+template <int S, bool FUSE, bool STR>
 __device__ __forceinline__ void lf_iter(const Coef& c, LF& st, int f, int fs, int fe, int k0,
                                         int k1, int w, int lane, const Lane3& L, int j,
                                         bool owave, double (&xa)[2][2][kNW][64],
@@ -496,13 +559,18 @@ __device__ __forceinline__ void lf_iter(const Coef& c, LF& st, int f, int fs, in
   // every step, guarded by nothing (as in the march kernels of L_z, L_y)
   {
     st.x[c0] = st.pf[e0];
+    if (STR) st.zz[c0] = st.pz[e0];
     const int fp = min(max(f + 2, 0), M);
     st.pf[e0] = load3(c, X, node(fp));
-    st.pn[c0] = prim3(c, st.x[c0], zrow(f, M));
+    if (STR) st.pz[e0] = zr[fp];
+    st.pn[c0] = prim3(c, st.x[c0], STR ? st.zz[c0] : zrow(f, M));
     st.s[c0] = fabs(st.pn[c0].u[0]) + sound(c, st.pn[c0].T);
     exchange(xa[S & 1], w, lane, st.pn[c0].u[0], st.pn[c0].u[1], ihy2, st.yx[c0], st.yy[c0]);
   }
   if (f < fs || f > fe) return;
+  // stretched grid: centred span of row f-1 from the ring heights (rows past
+  // a plate hold clamped heights; their values are never used)
+  const double icen = STR ? frcp(st.zz[c0] - st.zz[c2]) : 0.5 * c.ihz;
   // predictor on row f-1
   const int r1 = f - 1;
   if (r1 >= k0 - 1 && r1 >= 0 && r1 <= M) {
@@ -519,8 +587,8 @@ __device__ __forceinline__ void lf_iter(const Coef& c, LF& st, int f, int fs, in
         double dT = (shd(q.T) - q.T) * c.ihx;
         du[0][1] = st.yx[c1];
         du[1][1] = st.yy[c1];
-        du[0][2] = (st.pn[c0].u[0] - st.pn[c2].u[0]) * (0.5 * c.ihz);
-        du[2][2] = (st.pn[c0].u[2] - st.pn[c2].u[2]) * (0.5 * c.ihz);
+        du[0][2] = (st.pn[c0].u[0] - st.pn[c2].u[0]) * icen;
+        du[2][2] = (st.pn[c0].u[2] - st.pn[c2].u[2]) * icen;
         N3 Fi = flux3<0>(c, st.x[c1], q, du, dT);
         N3 Fm = shu(Fi);
         const N3& x0 = st.x[c1];
@@ -530,7 +598,7 @@ __device__ __forceinline__ void lf_iter(const Coef& c, LF& st, int f, int fs, in
         for (int g = 0; g < 3; ++g) v.m[g] = x0.m[g] - lx * (Fi.m[g] - Fm.m[g]);
         v.E = x0.E - lx * (Fi.E - Fm.E);
         st.xp[c1] = v;
-        st.pp[c1] = prim3(c, v, zrow(r1, M));
+        st.pp[c1] = prim3(c, v, STR ? st.zz[c1] : zrow(r1, M));
       }
     }
     double a = (role >= 1) ? st.pp[c1].u[0] : 0.0;
@@ -551,8 +619,9 @@ __device__ __forceinline__ void lf_iter(const Coef& c, LF& st, int f, int fs, in
       double dT = (q.T - shu(q.T)) * c.ihx;
       du[0][1] = st.pyx[c2];
       du[1][1] = st.pyy[c2];
-      du[0][2] = (st.pp[c1].u[0] - st.pp[c3].u[0]) * (0.5 * c.ihz);
-      du[2][2] = (st.pp[c1].u[2] - st.pp[c3].u[2]) * (0.5 * c.ihz);
+      const double icc = STR ? st.icen1 : icen;
+      du[0][2] = (st.pp[c1].u[0] - st.pp[c3].u[0]) * icc;
+      du[2][2] = (st.pp[c1].u[2] - st.pp[c3].u[2]) * icc;
       N3 Fi = flux3<0>(c, st.xp[c2], q, du, dT);
       N3 Fp = shd(Fi);
       const N3& x0 = st.x[c2];
@@ -577,12 +646,20 @@ __device__ __forceinline__ void lf_iter(const Coef& c, LF& st, int f, int fs, in
       for (int g = 0; g < 3; ++g) out.m[g] = 0.5 * (xp.m[g] + xc.m[g]) + (D.m[g] - Dm.m[g]);
       out.E = 0.5 * (xp.E + xc.E) + (D.E - Dm.E);
     }
-    if (FUSE) acc_out(c, out, zrow(r, M), st.acc, L.out);
+    if (FUSE) {
+      double izs = 1.0;
+      if (STR) {   // 1/(narrowest face of row r); one face at a plate
+        const double hu = st.zz[c1] - st.zz[c2], hd = st.zz[c2] - st.zz[c3];
+        izs = frcp(r == 0 ? hu : r == M ? hd : fmin(hu, hd));
+      }
+      acc_out(c, out, STR ? st.zz[c2] : zrow(r, M), izs, st.acc, L.out);
+    }
     if (L.out) store3(c, Y, node(r), out);
   }
+  if (STR) st.icen1 = icen;
 }
 
-template <bool FUSE>
+template <bool FUSE, bool STR>
 __global__ __launch_bounds__(64 * kNW) void sweep_lf3d(Coef c, Shared* sh, const double* zr,
                                                        int slot, int first,
                                                        const double* __restrict__ X,
@@ -592,7 +669,7 @@ __global__ __launch_bounds__(64 * kNW) void sweep_lf3d(Coef c, Shared* sh, const
   __shared__ double xb[2][2][kNW][64];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
-  const double dt = step_dt(c, sh, slot);
+  const double dt = step_dt<STR>(c, sh, slot);
   head3(sh, slot, first, dt);
   int bid = xcd_block();
   const int strip = bid % nstrips;
@@ -612,11 +689,13 @@ __global__ __launch_bounds__(64 * kNW) void sweep_lf3d(Coef c, Shared* sh, const
   const int fs = max(0, k0 - 2);
   const int fe = k1 + 1;
   st.pf[0] = st.pf[1] = N3{1.0, {0.0, 0.0, 0.0}, 1.0};
+  st.pz[0] = st.pz[1] = 0.0;
+  st.icen1 = 0.0;
   for (int fb = (fs - 2) & ~3; fb <= fe; fb += 4) {
-    lf_iter<0, FUSE>(c, st, fb + 0, fs, fe, k0, k1, w, lane, L, j, owave, xa, xb, zr, X, Y, lx);
-    lf_iter<1, FUSE>(c, st, fb + 1, fs, fe, k0, k1, w, lane, L, j, owave, xa, xb, zr, X, Y, lx);
-    lf_iter<2, FUSE>(c, st, fb + 2, fs, fe, k0, k1, w, lane, L, j, owave, xa, xb, zr, X, Y, lx);
-    lf_iter<3, FUSE>(c, st, fb + 3, fs, fe, k0, k1, w, lane, L, j, owave, xa, xb, zr, X, Y, lx);
+    lf_iter<0, FUSE, STR>(c, st, fb + 0, fs, fe, k0, k1, w, lane, L, j, owave, xa, xb, zr, X, Y, lx);
+    lf_iter<1, FUSE, STR>(c, st, fb + 1, fs, fe, k0, k1, w, lane, L, j, owave, xa, xb, zr, X, Y, lx);
+    lf_iter<2, FUSE, STR>(c, st, fb + 2, fs, fe, k0, k1, w, lane, L, j, owave, xa, xb, zr, X, Y, lx);
+    lf_iter<3, FUSE, STR>(c, st, fb + 3, fs, fe, k0, k1, w, lane, L, j, owave, xa, xb, zr, X, Y, lx);
   }
   if (FUSE) fold3(sh, slot, st.acc);
 }
@@ -629,6 +708,7 @@ hipError_t launch_sweep_3d(int axis, const Coef& c, Shared* sh, const double* zr
   const int nstrips = (c.nx + kStrip3 - 1) / kStrip3;
   const int per = kNW - 4;
   const dim3 block(64 * kNW);
+  const bool str = c.stretched != 0;   // the copies compiled for a stretched z grid
   if (axis == 0 || axis == 2) {
     // waves along y
     const int nbb = (c.ny + per - 1) / per;
@@ -637,8 +717,13 @@ hipError_t launch_sweep_3d(int axis, const Coef& c, Shared* sh, const double* zr
     if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
     const dim3 grid((unsigned)nblk);
     if (axis == 0) {
-      if (fuse) sweep_lf3d<true><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nbb);
-      else sweep_lf3d<false><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nbb);
+#define MTVD_LF(F, T) sweep_lf3d<F, T><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nbb)
+      if (str) {
+        if (fuse) MTVD_LF(true, true); else MTVD_LF(false, true);
+      } else {
+        if (fuse) MTVD_LF(true, false); else MTVD_LF(false, false);
+      }
+#undef MTVD_LF
     } else {
       // chunks [lo, hi] cannot touch a plate (first row >= 4, last row <=
       // M-4): the copy without plate code; the others the general one.  The
@@ -650,13 +735,21 @@ hipError_t launch_sweep_3d(int axis, const Coef& c, Shared* sh, const double* zr
       auto run = [&](int c0, int c1, bool pl) {
         if (c1 < c0) return;
         const dim3 g((unsigned)((long long)nstrips * nbb * (c1 - c0 + 1)));
-        if (pl) {
-          if (fuse) sweep_mf3d<2, true, true><<<g, block, 0, s>>>(c, sh, zr, slot, fst, X, Y, kc, nstrips, nbb, c0);
-          else sweep_mf3d<2, false, true><<<g, block, 0, s>>>(c, sh, zr, slot, fst, X, Y, kc, nstrips, nbb, c0);
+#define MTVD_MF(F, P, T) sweep_mf3d<2, F, P, T><<<g, block, 0, s>>>(c, sh, zr, slot, fst, X, Y, kc, nstrips, nbb, c0)
+        if (str) {
+          if (pl) {
+            if (fuse) MTVD_MF(true, true, true); else MTVD_MF(false, true, true);
+          } else {
+            if (fuse) MTVD_MF(true, false, true); else MTVD_MF(false, false, true);
+          }
         } else {
-          if (fuse) sweep_mf3d<2, true, false><<<g, block, 0, s>>>(c, sh, zr, slot, fst, X, Y, kc, nstrips, nbb, c0);
-          else sweep_mf3d<2, false, false><<<g, block, 0, s>>>(c, sh, zr, slot, fst, X, Y, kc, nstrips, nbb, c0);
+          if (pl) {
+            if (fuse) MTVD_MF(true, true, false); else MTVD_MF(false, true, false);
+          } else {
+            if (fuse) MTVD_MF(true, false, false); else MTVD_MF(false, false, false);
+          }
         }
+#undef MTVD_MF
         fst = 0;
       };
       if (lo > hi) {
@@ -674,8 +767,13 @@ hipError_t launch_sweep_3d(int axis, const Coef& c, Shared* sh, const double* zr
     const long long nblk = (long long)nstrips * nbb * nch;
     if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
     const dim3 grid((unsigned)nblk);
-    if (fuse) sweep_mf3d<1, true, true><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nbb, 0);
-    else sweep_mf3d<1, false, true><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nbb, 0);
+#define MTVD_MY(F, T) sweep_mf3d<1, F, true, T><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nbb, 0)
+    if (str) {
+      if (fuse) MTVD_MY(true, true); else MTVD_MY(false, true);
+    } else {
+      if (fuse) MTVD_MY(true, false); else MTVD_MY(false, false);
+    }
+#undef MTVD_MY
   }
   return hipGetLastError();
 }
