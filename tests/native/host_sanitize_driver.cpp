@@ -79,6 +79,23 @@ static void sizes() {
         "3D box accepted by create");
   std::free(bx);
 
+  // stretched grid: sizes (the metric table is part of the workspace) and
+  // the heights into an exact-size array
+  p = params(2, 64, 1, 33);
+  p.stretch = 1.5;
+  size_t wb0 = 0;
+  mtvd_params pu = params(2, 64, 1, 33);
+  CHECK(mtvd_state_bytes(&pu, &sb, &wb0) == MTVD_OK, "uniform sizes");
+  CHECK(mtvd_state_bytes(&p, &sb, &wb) == MTVD_OK && wb >= wb0 + 33u * 8u * 8u,
+        "stretched workspace %zu vs %zu", wb, wb0);
+  double* z = static_cast<double*>(std::malloc(33 * sizeof(double)));
+  CHECK(mtvd_grid_heights(&p, z, 33) == MTVD_OK && z[0] == 0.0 && z[32] == 1.0, "heights");
+  for (int k = 0; k < 32; ++k) CHECK(z[k + 1] > z[k], "heights not increasing at %d", k);
+  CHECK(mtvd_grid_heights(&p, z, 32) == MTVD_ESIZE, "short heights array accepted");
+  std::free(z);
+  p.stretch = -1.0;
+  CHECK(mtvd_state_bytes(&p, &sb, &wb) == MTVD_EINVAL, "negative stretch accepted");
+
   // adjoint workspace
   p = params(2, 64, 1, 16);
   CHECK(mtvd_adj_bytes(&p, 20, 5, &wb) == MTVD_OK && wb > 0, "adj_bytes");
