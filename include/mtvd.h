@@ -91,9 +91,9 @@ typedef struct mtvd_params {
                             the face fluxes h_k+1/2 G dX over w_k with the
                             face's own Courant number; dt takes the
                             narrowest face of each node, the diagnostics
-                            weigh rows by w_k.  Single boxes, 2D and 3D;
-                            MTVD_EINVAL in batches, for the adjoint and for
-                            the analysis profiles. */
+                            weigh rows by w_k.  Single boxes, 2D and 3D
+                            (3D: nz <= 2048); MTVD_EINVAL in batches, for
+                            the adjoint and for the analysis profiles. */
 } mtvd_params;
 
 /* Diagnostics of the current state (Sec. 2: mass, kinetic energy, total

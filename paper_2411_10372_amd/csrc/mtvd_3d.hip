@@ -207,12 +207,19 @@ struct MF {
   P3 pp[4];
   N3 FP[2];
   Acc3 acc;
-  // stretched grid (L_z) only: heights prefetched with their rows, and the
-  // metrics derived from them carried one march step
-  double pz[2], zz[4];
+  // stretched grid (L_z) only: the metrics derived from the heights (read
+  // from LDS) carried one march step
   double ihf1, ihf2, iw1;  // 1/h of faces f-3+1/2, f-4+1/2; 1/w of row f-3
   double iwb, iwt;         // the plate stencils' 1/(stencil applied to z)
 };
+
+// Heights of the rows of a stretched grid for L_z, copied into LDS once per
+// block: every wave of the block marches the same rows, and an LDS read waits
+// only for LDS, not behind the rows in flight from HBM (a ring of prefetched
+// heights in registers made these kernels spill).  The library accepts a
+// stretched 3D grid up to this many rows.
+constexpr int kZL3 = 2048;
+__shared__ double zlds[kZL3];
 
 // PL: the chunk may touch a plate (L_z).  Chunks that cannot (first row
 // >= 4, last row <= M-4: every stage then works on rows 2..M-4) run a copy
@@ -252,27 +259,27 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
   //    ring slots no stage reads, and their exchanged values are zeroed.
   {
     st.x[c0] = st.pf[e0];
-    if (SZ) st.zz[c0] = st.pz[e0];
     const int fp = (AX == 2) ? min(max(f + 2, 0), M) : f + 2;
     const long long np = (AX == 2) ? ((long long)fp * c.ny + bidx) * c.nx + L.col
                                    : ((long long)bload * c.ny + wrap(fp, c.ny)) * c.nx + L.col;
     st.pf[e0] = load3(c, X, np);
-    if (SZ) st.pz[e0] = zr[fp];
-    st.pn[c0] = prim3(c, st.x[c0], SZ ? st.zz[c0] : (AX == 2) ? zrow(f, M) : zb);
+    st.pn[c0] = prim3(c, st.x[c0], SZ ? zlds[min(max(f, 0), M)] : (AX == 2) ? zrow(f, M) : zb);
     st.s[c0] = fabs(st.pn[c0].u[AX]) + sound(c, st.pn[c0].T);
   }
   if (f < fs || f > fe) return;
   // heights of rows f-2 and f-3 (L_z) or of the wave's plane (L_y)
-  const double z_r = SZ ? st.zz[c2] : (AX == 2) ? zrow(f - 2, M) : zb;
-  const double z_o = SZ ? st.zz[c3] : (AX == 2) ? zrow(f - 3, M) : zb;
+  // (stretched L_z: rows past a plate read clamped heights; the values made
+  // from them are never used)
+  const double z_r = SZ ? zlds[min(max(f - 2, 0), M)] : (AX == 2) ? zrow(f - 2, M) : zb;
+  const double z_o = SZ ? zlds[min(max(f - 3, 0), M)] : (AX == 2) ? zrow(f - 3, M) : zb;
   const int r = f - 2;
-  // stretched L_z: face r+1/2 and dual cell of row r from the ring heights
-  // (rows past a plate hold clamped heights; their values are never used)
+  // stretched L_z: face r+1/2 and dual cell of row r
   double hf = 0.0, ihf = 0.0, iw = 0.0;
   if (SZ) {
-    hf = st.zz[c1] - st.zz[c2];
+    const double z_1 = zlds[min(max(f - 1, 0), M)];
+    hf = z_1 - z_r;
     ihf = frcp(hf);
-    iw = 2.0 * frcp(st.zz[c1] - st.zz[c3]);
+    iw = 2.0 * frcp(z_1 - z_o);
   }
   const bool rin_F = P ? (r >= 0 && r <= M - 1) : true;
   // B: predictor flux F_r (inner derivatives forward along the march); the
@@ -501,11 +508,12 @@ __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const
   double ihb2 = 0.5 * ((B == 1) ? c.ihy : c.ihz), izw = 1.0;
   if (STR) {
     st.ihf1 = st.ihf2 = st.iw1 = 0.0;
-    st.pz[0] = st.pz[1] = 0.0;
     st.iwb = st.iwt = 0.0;
     if (AX == 2) {
       st.iwb = zmet(c, 0, kZM_IWALL);
       st.iwt = zmet(c, c.M, kZM_IWALL);
+      for (int k = threadIdx.x; k <= c.M; k += blockDim.x) zlds[k] = zr[k];
+      __syncthreads();
     } else {
       const double zu = zr[min(bload + 1, c.M)], zd = zr[max(bload - 1, 0)];
       if (bload >= 1 && bload <= c.M - 1) ihb2 = frcp(zu - zd);

@@ -390,6 +390,10 @@ int validate(const mtvd_params* p, std::string* why) {
   if (p->tvd_on != 0 && p->tvd_on != 1) { *why = "tvd_on must be 0 or 1"; return MTVD_EINVAL; }
   if (p->wall_order != 1 && p->wall_order != 2) { *why = "wall_order must be 1 or 2"; return MTVD_EINVAL; }
   if (!(p->stretch >= 0.0) || !(p->stretch <= 10.0)) { *why = "stretch must lie in [0, 10]"; return MTVD_EINVAL; }
+  if (p->stretch > 0.0 && p->ndim == 3 && p->nz > 2048) {
+    *why = "a stretched 3D grid has at most 2048 rows";   // the L_z kernels keep the heights in LDS
+    return MTVD_EINVAL;
+  }
   if (!(p->cfl > 0.0) || !(p->cfl <= 1.0)) { *why = "cfl must lie in (0, 1]"; return MTVD_ESTABILITY; }
   // diffusion number of the initial state (the acoustic limit sets dt):
   // max(mu(2+|lambda|), K/c_v) * tau / (rho_min h_min^2) <= 1/2

@@ -277,7 +277,8 @@ def _lib():
 def test_stretched_grid_rules_on_the_host():
     mtvd, L = _lib()
     ctx = ctypes.c_void_p()
-    for bad in (dict(stretch=-0.5), dict(stretch=10.5), dict(stretch=float("nan"))):
+    for bad in (dict(stretch=-0.5), dict(stretch=10.5), dict(stretch=float("nan")),
+                dict(ndim=3, nx=8, ny=8, nz=2049, Ra=1e12, stretch=0.5)):
         p = mtvd.Params(**bad)._c()
         assert L.mtvd_create(ctypes.byref(p), None, ctypes.byref(ctx)) == -1, bad
     # sizes are still reported for a stretched 2D grid; the metric table adds
