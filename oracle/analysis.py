@@ -32,11 +32,23 @@ notes):
     the constant mu of these units, tau_ij = mu (d_j u_i + d_i u_j +
     lambda div u delta_ij), lambda the solver's bulk coefficient.
   * |u|^2 = u_x^2 (+ u_y^2) + u_z^2.
+  * On the tanh-stretched grid every z derivative is the stencil on the
+    node heights z_k: first derivatives (f_k+1 - f_k-1)/(z_k+1 - z_k-1)
+    inside and the one-sided plate stencil over the same stencil of z
+    (exact for linear f); second derivatives 2[(f_k+1 - f_k)/h+ - (f_k -
+    f_k-1)/h-]/(h+ + h-) inside (exact for quadratics) and the four-point
+    one-sided Lagrange stencil on the plate and the three rows next to it
+    (exact for cubics); both reduce to the uniform stencils above when the
+    spacing is uniform.  <.>_V weighs rows by their dual cells.
   * Boundary layers: slopes of the profile at the midpoints between rows;
     lambda_b is the height where, going up from z = 0, the slope first rises
     to -(1 + rtol) D (linear interpolation between midpoints); lambda_t the
     same from z = 1 going down, measured from the top plate.  rtol
     (default 0.1) states how close "approximates" has to be.
+
+Parity status (stretched grid): the stencils pinned by exactness on
+polynomials of the stated degrees and the uniform limit; the conduction
+state and the second-order hydrostatic balance on a fixed map as below.
 
 Parity status: profiles and volume means pinned (conduction state in
 closed form: u = 0, T_sa = -eps z, rho and rho_A closed forms, F_p - F_b
@@ -53,10 +65,20 @@ import numpy as np
 NAMES = ("T", "rho", "u2", "rho_uz_Tsa", "rho_uz2", "Tsa2", "Fn", "Fp", "Fb", "Fv")
 
 
+def heights(p):
+    """Node heights of the grid (uniform k/M, or the tanh grid)."""
+    if getattr(p, "stretch", 0.0) > 0.0:
+        from . import heights as _h
+        return _h(p)
+    return np.arange(p.nz, dtype=np.float64) / (p.nz - 1)
+
+
 def _coefs(p):
     """The nondimensional constants of Sec. 2 the analysis needs."""
     cv = 1.0 / (p.gamma * p.eps * p.D)
     return dict(
+        z=heights(p),
+        stretched=getattr(p, "stretch", 0.0) > 0.0,
         cv=cv,
         a=(p.gamma - 1.0) / (p.gamma * p.eps * p.D),
         g=p.gravity_scale / p.eps,
@@ -78,8 +100,7 @@ def primitives(p, X):
     uy = X[2] / rho if p.ndim == 3 else np.zeros_like(rho)
     uz = X[p.ndim] / rho
     E = X[p.ndim + 1]
-    z = np.arange(p.nz, dtype=np.float64) / (p.nz - 1)
-    zz = z.reshape((-1,) + (1,) * (rho.ndim - 1))
+    zz = c["z"].reshape((-1,) + (1,) * (rho.ndim - 1))
     u2 = ux * ux + uy * uy + uz * uz
     T = (E / rho - 0.5 * u2 - c["g"] * zz) / c["cv"]
     pr = c["a"] * rho * T
@@ -120,27 +141,71 @@ def d_zz(f, h):
     return out
 
 
+def _col(v, f):
+    """a per-row array shaped to broadcast against f (rows on axis 0)"""
+    return np.asarray(v).reshape((-1,) + (1,) * (f.ndim - 1))
+
+
+def d_z_grid(f, z):
+    """first z derivative on node heights z: central inside, the one-sided
+    second-order stencil on the plates, each over the same stencil of z"""
+    out = np.empty_like(f)
+    out[1:-1] = (f[2:] - f[:-2]) / _col(z[2:] - z[:-2], f)
+    out[0] = (-3.0 * f[0] + 4.0 * f[1] - f[2]) / ((-3.0 * z[0] + 4.0 * z[1]) - z[2])
+    out[-1] = (3.0 * f[-1] - 4.0 * f[-2] + f[-3]) / ((3.0 * z[-1] - 4.0 * z[-2]) + z[-3])
+    return out
+
+
+def lagrange_d2(zs, x0):
+    """weights of the second derivative at x0 of the cubic through the four
+    nodes zs: L_j''(x0) = 2 sum_{l != j} (x0 - z_l) / prod_{l != j} (z_j - z_l)"""
+    w = np.empty(4)
+    for j in range(4):
+        o = [zs[l] for l in range(4) if l != j]
+        w[j] = 2.0 * sum(x0 - zl for zl in o) / np.prod([zs[j] - zl for zl in o])
+    return w
+
+
+def d_zz_grid(f, z):
+    """second z derivative on node heights z: the three-point formula inside,
+    the four-point one-sided Lagrange stencil on the plates"""
+    out = np.empty_like(f)
+    hm = z[1:-1] - z[:-2]
+    hp = z[2:] - z[1:-1]
+    out[1:-1] = 2.0 * ((f[2:] - f[1:-1]) / _col(hp, f) - (f[1:-1] - f[:-2]) / _col(hm, f)) / \
+        _col(hp + hm, f)
+    wb = lagrange_d2(z[:4], z[0])
+    wt = lagrange_d2(z[-1:-5:-1], z[-1])
+    out[0] = ((wb[0] * f[0] + wb[1] * f[1]) + wb[2] * f[2]) + wb[3] * f[3]
+    out[-1] = ((wt[0] * f[-1] + wt[1] * f[-2]) + wt[2] * f[-3]) + wt[3] * f[-4]
+    return out
+
+
 def node_fields(p, X):
     """The ten per-node quantities whose row means make the profiles."""
-    if getattr(p, "stretch", 0.0) != 0.0:
-        raise NotImplementedError("analysis profiles on the uniform z grid only")
     c = _coefs(p)
     rho, ux, uy, uz, T, pr, zz = primitives(p, X)
+    if c["stretched"]:
+        z = c["z"]
+        dz1 = lambda f, h: d_z_grid(f, z)      # noqa: E731
+        dz2 = lambda f, h: d_zz_grid(f, z)     # noqa: E731
+    else:
+        dz1, dz2 = d_z, d_zz
     TA = 1.0 - p.D * zz
     Tsa = T - TA
     u2 = ux * ux + uy * uy + uz * uz
     hx, hy, hz = c["hx"], c["hy"], c["hz"]
-    dzuz = d_z(uz, hz)
+    dzuz = dz1(uz, hz)
     if p.ndim == 3:
         adv = ux * d_x(uz, hx) + uy * d_y(uz, hy) + uz * dzuz
-        lap = d_xx(uz, hx) + d_yy(uz, hy) + d_zz(uz, hz)
-        dz_div = d_z(d_x(ux, hx) + d_y(uy, hy), hz) + d_zz(uz, hz)
+        lap = d_xx(uz, hx) + d_yy(uz, hy) + dz2(uz, hz)
+        dz_div = dz1(d_x(ux, hx) + d_y(uy, hy), hz) + dz2(uz, hz)
     else:
         adv = ux * d_x(uz, hx) + uz * dzuz
-        lap = d_xx(uz, hx) + d_zz(uz, hz)
-        dz_div = d_z(d_x(ux, hx), hz) + d_zz(uz, hz)
+        lap = d_xx(uz, hx) + dz2(uz, hz)
+        dz_div = dz1(d_x(ux, hx), hz) + dz2(uz, hz)
     Fn = rho * adv
-    Fp = -d_z(pr, hz)
+    Fp = -dz1(pr, hz)
     Fb = rho * c["g"]
     Fv = c["mu"] * (lap + (1.0 + c["lam"]) * dz_div)
     ruz = rho * uz
@@ -159,9 +224,15 @@ def profiles(p, X):
     return mean, mabs
 
 
-def volume_mean(prof_row):
-    """<f>_V from row means: trapezoid in z over a height of 1."""
+def volume_mean(prof_row, z=None):
+    """<f>_V from row means: trapezoid in z over a height of 1 (on the node
+    heights z when given: the dual cells as weights)."""
     v = np.asarray(prof_row, dtype=np.float64)
+    if z is not None:
+        w = np.empty_like(z)
+        w[1:-1] = 0.5 * (z[2:] - z[:-2])
+        w[0], w[-1] = 0.5 * (z[1] - z[0]), 0.5 * (z[-1] - z[-2])
+        return float(np.sum(w * v))
     M = v.shape[-1] - 1
     w = np.ones(M + 1)
     w[0] = w[-1] = 0.5
@@ -173,9 +244,10 @@ def analysis(p, prof):
     correlation C, the volume means of F_n, F_p, F_b, F_v and of the
     correlation's three inputs, and the derived profiles T_sa(z),
     rho - rho_A(z), U(z)."""
-    V = {n: volume_mean(prof[i]) for i, n in enumerate(NAMES)}
+    zg = heights(p) if getattr(p, "stretch", 0.0) > 0.0 else None
+    V = {n: volume_mean(prof[i], zg) for i, n in enumerate(NAMES)}
     den = np.sqrt(V["rho_uz2"] * V["Tsa2"])
-    z = np.arange(p.nz, dtype=np.float64) / (p.nz - 1)
+    z = heights(p)
     beta = 1.0 / (p.gamma - 1.0)
     return dict(
         Re=float(np.sqrt(p.Ra / p.Pr) * np.sqrt(V["u2"])),
@@ -188,14 +260,20 @@ def analysis(p, prof):
     )
 
 
-def bl_thickness(tmean, D, rtol=0.1):
-    """(lambda_b, lambda_t) of a profile <T>_A on nz node-counted rows;
-    -1.0 where the slope never reaches -(1 + rtol) D."""
+def bl_thickness(tmean, D, rtol=0.1, z=None):
+    """(lambda_b, lambda_t) of a profile <T>_A on nz node-counted rows
+    (uniform, or on the node heights z); -1.0 where the slope never reaches
+    -(1 + rtol) D."""
     t = np.asarray(tmean, dtype=np.float64)
     M = t.size - 1
-    hz = 1.0 / M
-    s = (t[1:] - t[:-1]) / hz              # slope at midpoint z_(k+1/2)
-    zm = (np.arange(M) + 0.5) * hz
+    if z is None:
+        hz = 1.0 / M
+        s = (t[1:] - t[:-1]) / hz              # slope at midpoint z_(k+1/2)
+        zm = (np.arange(M) + 0.5) * hz
+    else:
+        z = np.asarray(z, dtype=np.float64)
+        s = (t[1:] - t[:-1]) / (z[1:] - z[:-1])
+        zm = 0.5 * (z[1:] + z[:-1])
     thr = -(1.0 + rtol) * D
 
     def crossing(order):

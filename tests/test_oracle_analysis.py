@@ -180,3 +180,77 @@ def test_boundary_layer_thickness_of_an_exponential_profile():
     z = np.arange(65) / 64.0
     assert an.bl_thickness(1.0 - D * z, D, r) == (0.5 / 64, 0.5 / 64)
     assert an.bl_thickness(1.0 - 2.0 * D * z, D, r) == (-1.0, -1.0)
+
+
+# ---- the tanh-stretched grid -------------------------------------------------
+
+@pytest.mark.parametrize("s", [0.7, 1.8])
+def test_stretched_stencils_are_exact_on_polynomials(s):
+    # first derivatives exact for linear data, the interior second derivative
+    # for quadratics, the plate second derivative for cubics (its stencil is
+    # the Lagrange cubic through the plate and three rows)
+    p = _params(nz=13, stretch=s)
+    z = oracle.heights(p)
+    f1 = (0.3 + 1.7 * z)[:, None] * np.ones((1, 4))
+    assert np.max(np.abs(an.d_z_grid(f1, z) - 1.7)) < 1e-12
+    f2 = (0.3 + 1.7 * z - 2.2 * z * z)[:, None] * np.ones((1, 4))
+    assert np.max(np.abs(an.d_zz_grid(f2, z) + 4.4)) < 1e-9
+    f3 = (z ** 3)[:, None] * np.ones((1, 4))
+    d2 = an.d_zz_grid(f3, z)
+    assert abs(d2[0, 0] - 6.0 * z[0]) < 1e-8 and abs(d2[-1, 0] - 6.0 * z[-1]) < 1e-8
+    # and on the uniform grid they are the uniform stencils
+    zu = np.arange(13) / 12.0
+    g = np.sin(3.0 * zu)[:, None] * np.ones((1, 2))
+    assert np.max(np.abs(an.d_z_grid(g, zu) - an.d_z(g, 1.0 / 12))) < 1e-13
+    assert np.max(np.abs(an.d_zz_grid(g, zu) - an.d_zz(g, 1.0 / 12))) < 1e-10
+
+
+def test_stretched_conduction_closed_forms_and_volume_weights():
+    p = _params(nz=33, nx=32, stretch=1.5)
+    X = oracle.init(p)
+    prof, _ = an.profiles(p, X)
+    A = an.analysis(p, prof)
+    z = oracle.heights(p)
+    assert np.max(np.abs(A["Tsa_z"] + p.eps * z)) < 1e-14
+    for n in ("u2", "rho_uz_Tsa", "rho_uz2", "Fn", "Fv"):
+        assert np.all(prof[an.NAMES.index(n)] == 0.0), n
+    # dual-cell weights integrate linear profiles exactly over the height 1
+    assert abs(an.volume_mean(0.4 + 2.0 * z, z) - 1.4) < 1e-15
+
+
+def test_stretched_hydrostatic_balance_converges_at_second_order():
+    errs = []
+    for nz in (17, 33, 65, 129):
+        p = _params(nz=nz, nx=8, stretch=1.2)
+        prof, _ = an.profiles(p, oracle.init(p))
+        errs.append(np.max(np.abs(prof[an.NAMES.index("Fp")] - prof[an.NAMES.index("Fb")])))
+    orders = [np.log2(errs[i] / errs[i + 1]) for i in range(3)]
+    assert all(1.8 < o < 2.3 for o in orders), (errs, orders)
+
+
+def test_stretched_grid_tends_to_the_uniform_analysis():
+    kw = dict(nx=32, nz=17, noise_amp=0.0)
+    pu = _params(**kw)
+    Xu = oracle.init(pu)
+    rng = np.random.default_rng(5)
+    Xu[1, 1:-1] += 1e-2 * rng.uniform(-1, 1, Xu[1, 1:-1].shape)
+    Xu[2, 1:-1] += 1e-2 * rng.uniform(-1, 1, Xu[2, 1:-1].shape)
+    pu_prof, scale = an.profiles(pu, Xu)
+    errs = []
+    for s in (1e-2, 1e-3):
+        ps = _params(stretch=s, **kw)
+        prof, _ = an.profiles(ps, Xu)
+        errs.append(np.max(np.abs(prof - pu_prof) / np.maximum(scale, 1e-300)))
+    assert errs[1] < 1e-4 and errs[0] / errs[1] > 30, errs
+
+
+def test_stretched_boundary_layer_thickness():
+    # the exponential layer of the uniform test, sampled on a tanh grid:
+    # the crossing height of the slope -(1 + r) D is known in closed form
+    D, A, d, r = 0.4, 6.0, 0.02, 0.1
+    p = _params(nz=129, stretch=1.5)
+    z = oracle.heights(p)
+    t = 1.0 - D * z - A * d * (1.0 - np.exp(-z / d)) + A * d * (1.0 - np.exp(-(1.0 - z) / d))
+    lb, lt = an.bl_thickness(t, D, r, z=z)
+    exact = -d * np.log(r * D / A)     # slope -D - A e^{-z/d} meets -(1+r)D
+    assert abs(lb - exact) < 0.05 * exact and abs(lt - exact) < 0.05 * exact, (lb, lt, exact)
