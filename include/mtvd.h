@@ -91,9 +91,10 @@ typedef struct mtvd_params {
                             the face fluxes h_k+1/2 G dX over w_k with the
                             face's own Courant number; dt takes the
                             narrowest face of each node, the diagnostics
-                            weigh rows by w_k.  Single boxes, 2D and 3D
-                            (3D: nz <= 2048); MTVD_EINVAL in batches, for
-                            the adjoint and for the analysis profiles. */
+                            weigh rows by w_k, and the analysis profiles
+                            take every z derivative on the node heights.
+                            Single boxes, 2D and 3D (3D: nz <= 2048);
+                            MTVD_EINVAL in batches and for the adjoint. */
 } mtvd_params;
 
 /* Diagnostics of the current state (Sec. 2: mass, kinetic energy, total
@@ -207,6 +208,13 @@ int mtvd_analysis_from_profiles(const mtvd_params* p, const double* prof, size_t
  * MTVD_EINVAL on bad arguments (nz < 3, D <= 0, rtol < 0). */
 int mtvd_bl_thickness(const double* tmean, int32_t nz, double D, double rtol, double* lam_b,
                       double* lam_t);
+
+/* Host only: the same on a profile sampled at the increasing node heights
+ * z[0..nz-1] (e.g. mtvd_grid_heights of a stretched grid): slopes over the
+ * row spacings, at the midpoints of the rows.  MTVD_EINVAL also if z is
+ * not increasing. */
+int mtvd_bl_thickness_grid(const double* tmean, const double* z, int32_t nz, double D,
+                           double rtol, double* lam_b, double* lam_t);
 
 /* Copy the current state to host memory in the canonical layout; count
  * must equal nf*nz*ny*nx.  Synchronises. */

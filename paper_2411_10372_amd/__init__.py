@@ -187,7 +187,10 @@ def lib() -> ctypes.CDLL:
                                                   ctypes.POINTER(_Analysis), dp, dp, dp]
         L.mtvd_bl_thickness.argtypes = [dp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                         dp, dp]
-        for fn in ("mtvd_profiles", "mtvd_analysis_from_profiles", "mtvd_bl_thickness"):
+        L.mtvd_bl_thickness_grid.argtypes = [dp, dp, ctypes.c_int32, ctypes.c_double,
+                                             ctypes.c_double, dp, dp]
+        for fn in ("mtvd_profiles", "mtvd_analysis_from_profiles", "mtvd_bl_thickness",
+                   "mtvd_bl_thickness_grid"):
             getattr(L, fn).restype = ctypes.c_int
         for fn in ("mtvd_adj_bytes", "mtvd_adj_create", "mtvd_adj_bind", "mtvd_adj_forward",
                    "mtvd_adj_backward", "mtvd_adj_coef_grads", "mtvd_adj_destroy"):
@@ -225,12 +228,21 @@ def analysis(p: Params, prof: np.ndarray) -> dict:
     return out
 
 
-def bl_thickness(tmean, D: float, rtol: float = 0.1):
-    """(lambda_b, lambda_t) of a <T>_A profile; -1 where not found."""
+def bl_thickness(tmean, D: float, rtol: float = 0.1, z=None):
+    """(lambda_b, lambda_t) of a <T>_A profile (on uniform rows, or at the
+    node heights z); -1 where not found."""
     t = np.ascontiguousarray(tmean, dtype=np.float64)
     lb, lt = ctypes.c_double(), ctypes.c_double()
-    rc = lib().mtvd_bl_thickness(t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), t.size,
-                                 D, rtol, ctypes.byref(lb), ctypes.byref(lt))
+    dp = ctypes.POINTER(ctypes.c_double)
+    if z is None:
+        rc = lib().mtvd_bl_thickness(t.ctypes.data_as(dp), t.size, D, rtol, ctypes.byref(lb),
+                                     ctypes.byref(lt))
+    else:
+        zz = np.ascontiguousarray(z, dtype=np.float64)
+        if zz.size != t.size:
+            raise ValueError("z and tmean differ in length")
+        rc = lib().mtvd_bl_thickness_grid(t.ctypes.data_as(dp), zz.ctypes.data_as(dp), t.size, D,
+                                          rtol, ctypes.byref(lb), ctypes.byref(lt))
     if rc != MTVD_OK:
         raise MtvdError(rc, lib().mtvd_strerror(rc).decode())
     return lb.value, lt.value

@@ -81,7 +81,32 @@ __device__ void node_quantities(const Coef& c, const double* zr, const double* _
   };
   const int M = c.M;
   double dz_uz, dz_p, dzz_uz, dz_dxy;
-  if (k == 0) {
+  if (c.stretched) {
+    // the same stencils on the node heights (metric table): first
+    // derivatives over the same stencil of z, second derivatives by the
+    // three-point weights inside and the four-point Lagrange weights at a
+    // plate
+    const double* m = c.zm + (size_t)k * kZM;
+    if (k == 0 || k == M) {
+      const int sg = (k == 0) ? 1 : -1;
+      const P6 a1 = prim_at(c, zr, X, i, j, k + sg), a2 = prim_at(c, zr, X, i, j, k + 2 * sg),
+               a3 = prim_at(c, zr, X, i, j, k + 3 * sg);
+      const double iw = m[kZM_IWALL];
+      const double s3 = (double)sg * 3.0;   // -3, 4, -1 at the bottom; 3, -4, 1 at the top
+      dz_uz = (-s3 * q.uz + sg * 4.0 * a1.uz - sg * a2.uz) * iw;
+      dz_p = (-s3 * q.p + sg * 4.0 * a1.p - sg * a2.p) * iw;
+      dzz_uz = ((m[kZM_D2] * q.uz + m[kZM_D2 + 1] * a1.uz) + m[kZM_D2 + 2] * a2.uz) +
+               m[kZM_D2 + 3] * a3.uz;
+      dz_dxy = (-s3 * dxy(k) + sg * 4.0 * dxy(k + sg) - sg * dxy(k + 2 * sg)) * iw;
+    } else {
+      const P6 zm = prim_at(c, zr, X, i, j, k - 1), zp = prim_at(c, zr, X, i, j, k + 1);
+      const double ic = m[kZM_ICEN];
+      dz_uz = (zp.uz - zm.uz) * ic;
+      dz_p = (zp.p - zm.p) * ic;
+      dzz_uz = (m[kZM_D2] * zm.uz + m[kZM_D2 + 1] * q.uz) + m[kZM_D2 + 2] * zp.uz;
+      dz_dxy = (dxy(k + 1) - dxy(k - 1)) * ic;
+    }
+  } else if (k == 0) {
     const P6 a1 = prim_at(c, zr, X, i, j, 1), a2 = prim_at(c, zr, X, i, j, 2),
              a3 = prim_at(c, zr, X, i, j, 3);
     dz_uz = (-3.0 * q.uz + 4.0 * a1.uz - a2.uz) / (2.0 * hz);
@@ -176,60 +201,32 @@ hipError_t launch_profiles(const Coef& c, const double* zr, const double* X, dou
 
 namespace {
 
-// <f>_V of a row-mean profile: trapezoid in z over a box of height 1
-double volume_mean(const double* v, int nz) {
+// <f>_V of a row-mean profile: trapezoid in z over a box of height 1 (on a
+// stretched grid with the dual cells of the node heights z as weights)
+double volume_mean(const double* v, int nz, const double* z) {
   const int M = nz - 1;
+  if (z) {
+    double s = 0.5 * (z[1] - z[0]) * v[0];
+    for (int k = 1; k < M; ++k) s += 0.5 * (z[k + 1] - z[k - 1]) * v[k];
+    return s + 0.5 * (z[M] - z[M - 1]) * v[M];
+  }
   double s = 0.5 * v[0];
   for (int k = 1; k < M; ++k) s += v[k];
   s += 0.5 * v[M];
   return s / (double)M;
 }
 
-}  // namespace
-
-extern "C" {
-
-int mtvd_analysis_from_profiles(const mtvd_params* p, const double* prof, size_t count,
-                                mtvd_analysis* out, double* tsa_z, double* drho_z, double* U_z) {
-  if (!p || !prof || !out || p->nz < 5 || !(p->Ra > 0.0) || !(p->Pr > 0.0) ||
-      !(p->gamma > 1.0) || p->stretch != 0.0)
-    return MTVD_EINVAL;
-  const int nz = p->nz;
-  if (count < (size_t)mtvd::kNumProfiles * (size_t)nz) return MTVD_ESIZE;
-  double V[mtvd::kNumProfiles];
-  for (int q = 0; q < mtvd::kNumProfiles; ++q) V[q] = volume_mean(prof + (size_t)q * nz, nz);
-  out->u2 = V[2];
-  out->rho_uz_Tsa = V[3];
-  out->rho_uz2 = V[4];
-  out->Tsa2 = V[5];
-  out->Fn = V[6];
-  out->Fp = V[7];
-  out->Fb = V[8];
-  out->Fv = V[9];
-  // Re = sqrt(Ra/Pr) U with U the rms velocity (Sec. 2)
-  out->Re = sqrt(p->Ra / p->Pr) * sqrt(V[2]);
-  // C = <rho u_z T_sa> / sqrt(<(rho u_z)^2> <T_sa^2>) (Sec. 6.2)
-  const double den = sqrt(V[4] * V[5]);
-  out->C = den > 0.0 ? V[3] / den : 0.0;
-  const double beta = 1.0 / (p->gamma - 1.0);
-  for (int k = 0; k < nz; ++k) {
-    const double z = (double)k / (double)(nz - 1);
-    if (tsa_z) tsa_z[k] = prof[k] - (1.0 - p->D * z);
-    if (drho_z) drho_z[k] = prof[(size_t)nz + k] - pow(1.0 - p->D * z, beta);
-    if (U_z) U_z[k] = sqrt(prof[(size_t)2 * nz + k]);
-  }
-  return MTVD_OK;
-}
-
-int mtvd_bl_thickness(const double* tmean, int32_t nz, double D, double rtol, double* lam_b,
-                      double* lam_t) {
-  if (!tmean || !lam_b || !lam_t || nz < 3 || !(D > 0.0) || !(rtol >= 0.0))
-    return MTVD_EINVAL;
+// slopes between rows and their midpoints: the boundary-layer crossings
+// (uniform rows when z is null)
+void bl_crossings(const double* tmean, const double* z, int nz, double D, double rtol,
+                  double* lam_b, double* lam_t) {
   const int M = nz - 1;
   const double hz = 1.0 / (double)M;
   const double thr = -(1.0 + rtol) * D;
-  auto slope = [&](int k) { return (tmean[k + 1] - tmean[k]) / hz; };
-  auto zmid = [&](int k) { return ((double)k + 0.5) * hz; };
+  auto slope = [&](int k) {
+    return z ? (tmean[k + 1] - tmean[k]) / (z[k + 1] - z[k]) : (tmean[k + 1] - tmean[k]) / hz;
+  };
+  auto zmid = [&](int k) { return z ? 0.5 * (z[k] + z[k + 1]) : ((double)k + 0.5) * hz; };
   // from the bottom plate up
   *lam_b = -1.0;
   for (int k = 0; k < M; ++k) {
@@ -258,6 +255,61 @@ int mtvd_bl_thickness(const double* tmean, int32_t nz, double D, double rtol, do
       break;
     }
   }
+}
+
+}  // namespace
+
+extern "C" {
+
+int mtvd_analysis_from_profiles(const mtvd_params* p, const double* prof, size_t count,
+                                mtvd_analysis* out, double* tsa_z, double* drho_z, double* U_z) {
+  if (!p || !prof || !out || p->nz < 5 || !(p->Ra > 0.0) || !(p->Pr > 0.0) ||
+      !(p->gamma > 1.0) || !(p->stretch >= 0.0) || !(p->stretch <= 10.0))
+    return MTVD_EINVAL;
+  const int nz = p->nz;
+  if (count < (size_t)mtvd::kNumProfiles * (size_t)nz) return MTVD_ESIZE;
+  const std::vector<double> zg = mtvd::grid_heights(p->stretch, nz);
+  const double* zw = p->stretch > 0.0 ? zg.data() : nullptr;
+  double V[mtvd::kNumProfiles];
+  for (int q = 0; q < mtvd::kNumProfiles; ++q) V[q] = volume_mean(prof + (size_t)q * nz, nz, zw);
+  out->u2 = V[2];
+  out->rho_uz_Tsa = V[3];
+  out->rho_uz2 = V[4];
+  out->Tsa2 = V[5];
+  out->Fn = V[6];
+  out->Fp = V[7];
+  out->Fb = V[8];
+  out->Fv = V[9];
+  // Re = sqrt(Ra/Pr) U with U the rms velocity (Sec. 2)
+  out->Re = sqrt(p->Ra / p->Pr) * sqrt(V[2]);
+  // C = <rho u_z T_sa> / sqrt(<(rho u_z)^2> <T_sa^2>) (Sec. 6.2)
+  const double den = sqrt(V[4] * V[5]);
+  out->C = den > 0.0 ? V[3] / den : 0.0;
+  const double beta = 1.0 / (p->gamma - 1.0);
+  for (int k = 0; k < nz; ++k) {
+    const double z = zg[k];
+    if (tsa_z) tsa_z[k] = prof[k] - (1.0 - p->D * z);
+    if (drho_z) drho_z[k] = prof[(size_t)nz + k] - pow(1.0 - p->D * z, beta);
+    if (U_z) U_z[k] = sqrt(prof[(size_t)2 * nz + k]);
+  }
+  return MTVD_OK;
+}
+
+int mtvd_bl_thickness(const double* tmean, int32_t nz, double D, double rtol, double* lam_b,
+                      double* lam_t) {
+  if (!tmean || !lam_b || !lam_t || nz < 3 || !(D > 0.0) || !(rtol >= 0.0))
+    return MTVD_EINVAL;
+  bl_crossings(tmean, nullptr, nz, D, rtol, lam_b, lam_t);
+  return MTVD_OK;
+}
+
+int mtvd_bl_thickness_grid(const double* tmean, const double* z, int32_t nz, double D,
+                           double rtol, double* lam_b, double* lam_t) {
+  if (!tmean || !z || !lam_b || !lam_t || nz < 3 || !(D > 0.0) || !(rtol >= 0.0))
+    return MTVD_EINVAL;
+  for (int k = 0; k + 1 < nz; ++k)
+    if (!(z[k + 1] > z[k])) return MTVD_EINVAL;
+  bl_crossings(tmean, z, nz, D, rtol, lam_b, lam_t);
   return MTVD_OK;
 }
 

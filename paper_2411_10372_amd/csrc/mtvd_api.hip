@@ -267,6 +267,24 @@ __global__ __launch_bounds__(kDiagBlock) void diag_final_kernel(Coef c, const do
   }
 }
 
+// Heights of the nz rows: uniform k/M, or the tanh grid of the stretch
+// parameter s, z_k = (1 + tanh(s (2k - M)/M) / tanh s) / 2, whose quotient
+// is exactly -1 and 1 at the ends (tanh is odd), so the plates sit at 0, 1.
+std::vector<double> grid_heights(double s, int nz) {
+  const int M = nz - 1;
+  std::vector<double> z(nz);
+  if (!(s > 0.0)) {
+    for (int k = 0; k < nz; ++k) z[k] = (double)k / (double)M;
+    return z;
+  }
+  const double ts = tanh(s);
+  for (int k = 0; k < nz; ++k) {
+    const double xi = (2.0 * (double)k - (double)M) / (double)M;
+    z[k] = 0.5 * (1.0 + tanh(s * xi) / ts);
+  }
+  return z;
+}
+
 }  // namespace mtvd
 
 // ---------------------------------------------------------------------------
@@ -313,24 +331,6 @@ int hip_fail(mtvd_ctx* c, hipError_t e, const char* where) {
     if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
   } while (0)
 
-// Heights of the nz rows: uniform k/M, or the tanh grid of the stretch
-// parameter s, z_k = (1 + tanh(s (2k - M)/M) / tanh s) / 2, whose quotient
-// is exactly -1 and 1 at the ends (tanh is odd), so the plates sit at 0, 1.
-std::vector<double> grid_heights(double s, int nz) {
-  const int M = nz - 1;
-  std::vector<double> z(nz);
-  if (!(s > 0.0)) {
-    for (int k = 0; k < nz; ++k) z[k] = (double)k / (double)M;
-    return z;
-  }
-  const double ts = tanh(s);
-  for (int k = 0; k < nz; ++k) {
-    const double xi = (2.0 * (double)k - (double)M) / (double)M;
-    z[k] = 0.5 * (1.0 + tanh(s * xi) / ts);
-  }
-  return z;
-}
-
 // The per-row metric table of a stretched grid (kZM doubles per row, the
 // kZM_* slots): reciprocals of the face, centred and dual-cell spans, the
 // face length, the narrowest face of each node and the two plate stencils.
@@ -360,6 +360,27 @@ std::vector<double> grid_metrics(const std::vector<double>& z) {
     r[kZM_W] = w;
     r[kZM_IW] = 1.0 / w;
     r[kZM_IHMIN] = 1.0 / hmin;
+    if (k == 0 || k == M) {
+      // L_j''(z_plate) of the cubic through the plate and three rows:
+      // 2 sum_{l != j} (x0 - z_l) / prod_{l != j} (z_j - z_l)
+      const int sgn = (k == 0) ? 1 : -1;
+      double zs[4];
+      for (int j = 0; j < 4; ++j) zs[j] = z[k + sgn * j];
+      for (int j = 0; j < 4; ++j) {
+        double num = 0.0, den = 1.0;
+        for (int l = 0; l < 4; ++l)
+          if (l != j) {
+            num += zs[0] - zs[l];
+            den *= zs[j] - zs[l];
+          }
+        r[kZM_D2 + j] = 2.0 * num / den;
+      }
+    } else {
+      const double hm = z[k] - z[k - 1], hp = z[k + 1] - z[k];
+      r[kZM_D2 + 0] = 2.0 / (hm * (hm + hp));
+      r[kZM_D2 + 1] = -2.0 / (hm * hp);
+      r[kZM_D2 + 2] = 2.0 / (hp * (hm + hp));
+    }
   }
   return m;
 }
@@ -791,7 +812,6 @@ int mtvd_diagnostics(mtvd_ctx* c, mtvd_diag* out) {
 int mtvd_profiles(mtvd_ctx* c, double* out, size_t count) {
   if (!c || !out) return MTVD_EINVAL;
   if (!c->have_state) return set_err(c, MTVD_ESTATE, "no state");
-  if (c->c.stretched) return set_err(c, MTVD_EINVAL, "analysis profiles need the uniform z grid");
   const size_t n = (size_t)kNumProfiles * (size_t)c->c.nz;
   if (count < n) return set_err(c, MTVD_ESIZE, "profile array too small");
   double* part = (double*)(c->ws + c->L.ppart);

@@ -30,7 +30,7 @@ struct Coef {
   double noise_amp;
   uint64_t seed;
   int limiter_form, tvd_on, wall_order, dt_mode;
-  // tanh-stretched z grid (2D): per-row metric table of kZM doubles per row
+  // tanh-stretched z grid: per-row metric table of kZM doubles per row
   // (see the kZM_* slots), device memory in the workspace; null when uniform
   int stretched;
   const double* zm;
@@ -40,7 +40,7 @@ struct Coef {
 // z difference divides by the same difference of the node heights; the
 // table holds the reciprocals (and the two lengths the TVD flux and the
 // volume weights use).
-constexpr int kZM = 8;
+constexpr int kZM = 16;
 constexpr int kZM_IHF = 0;    // 1/(z_k+1 - z_k), face k+1/2 (rows 0..M-1)
 constexpr int kZM_ICEN = 1;   // 1/(z_k+1 - z_k-1), centred span (rows 1..M-1)
 constexpr int kZM_IW = 2;     // 1/w_k, w_k the dual cell (half a face at a plate)
@@ -48,6 +48,10 @@ constexpr int kZM_HF = 3;     // z_k+1 - z_k
 constexpr int kZM_IHMIN = 4;  // 1/min of the node's faces (dt)
 constexpr int kZM_IWALL = 5;  // row 0: 1/(-3 z0 + 4 z1 - z2); row M: 1/(3 zM - 4 zM-1 + zM-2)
 constexpr int kZM_W = 6;      // w_k (volume weight)
+// second z derivative (analysis): inside, the three-point weights of rows
+// k-1, k, k+1; at a plate, the four-point one-sided Lagrange weights of the
+// plate and the three rows next to it (nearest first)
+constexpr int kZM_D2 = 7;     // slots 7..9 inside, 7..10 on the plates
 
 __device__ __forceinline__ double zmet(const Coef& c, int k, int slot) {
   return c.zm[k * kZM + slot];

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "mtvd_adjoint.h"
 #include "mtvd_device.h"
 
@@ -52,6 +54,9 @@ hipError_t launch_grad_theta(const Coef& c, const double* X0, const double* xb, 
 // analysis row means (Sec. 4): out[q nz + k], q < kNumProfiles, from
 // per-segment partials part[nz][nb][kNumProfiles]
 constexpr int kNumProfiles = 10;
+// Node heights of the z grid (uniform k/M, or the tanh grid of stretch s).
+std::vector<double> grid_heights(double s, int nz);
+
 hipError_t launch_profiles(const Coef& c, const double* zr, const double* X, double* part,
                            int nb, double* out, hipStream_t s);
 

@@ -40,33 +40,12 @@ def _mean_err(x: np.ndarray):
     return float(np.mean(x)), err
 
 
-def _dual_weights(z: np.ndarray) -> np.ndarray:
-    """Trapezoid weights of the rows (the dual cells; half a face at a
-    plate), summing to the height 1."""
-    w = np.empty_like(z)
-    w[1:-1] = 0.5 * (z[2:] - z[:-2])
-    w[0], w[-1] = 0.5 * (z[1] - z[0]), 0.5 * (z[-1] - z[-2])
-    return w
-
-
-def _re_from_state(p: Params, X: np.ndarray, w: np.ndarray) -> float:
-    """Re = sqrt(Ra/Pr) sqrt(<|u|^2>_V) of a snapshot (Sec. 2), with the rows
-    weighted by their dual cells (used on a stretched grid, where the
-    analysis profiles are not available)."""
-    rho = X[0]
-    u2 = sum((X[f] / rho) ** 2 for f in range(1, p.ndim + 1))
-    rows = u2.mean(axis=tuple(range(1, u2.ndim)))
-    return float(np.sqrt(p.Ra / p.Pr) * np.sqrt(np.sum(w * rows)))
-
-
 def time_averages(p: Params, t0: float, t1: float, sample_steps: int = 100,
                   wall_limit: float | None = None, rtol: float = 0.1, progress=None) -> dict:
     """Run from the initial state until the simulated time reaches t1 (or
     the wall-clock limit), sampling every `sample_steps` steps; average the
-    samples with time >= t0.  On a stretched grid only the step diagnostics
-    and Re (from the state) are sampled."""
-    stretched = p.stretch > 0.0
-    w = _dual_weights(grid_heights(p)) if stretched else None
+    samples with time >= t0."""
+    z = grid_heights(p) if p.stretch > 0.0 else None
     s = Solver(p)
     try:
         s.init_state()
@@ -78,16 +57,12 @@ def time_averages(p: Params, t0: float, t1: float, sample_steps: int = 100,
             s.step(sample_steps)
             d = s.diagnostics()
             row = {k: d[k] for k in SCALARS if k in d}
-            if stretched:
-                a = {"Re": _re_from_state(p, s.get_state(), w)}
-                row["Re"] = a["Re"]
-            else:
-                prof = s.profiles()
-                a = analysis(p, prof)
-                row.update({k: a[k] for k in ("Re", "C", "Fn", "Fp", "Fb", "Fv")})
-                if d["time"] >= t0:
-                    prof_sum = prof.copy() if prof_sum is None else prof_sum + prof
-                    n_prof += 1
+            prof = s.profiles()
+            a = analysis(p, prof)
+            row.update({k: a[k] for k in ("Re", "C", "Fn", "Fp", "Fb", "Fv")})
+            if d["time"] >= t0:
+                prof_sum = prof.copy() if prof_sum is None else prof_sum + prof
+                n_prof += 1
             row["time"] = d["time"]
             samples.append(row)
             now = time.time()
@@ -108,7 +83,7 @@ def time_averages(p: Params, t0: float, t1: float, sample_steps: int = 100,
         if len(sel) >= 5 and n_prof:
             mean_prof = prof_sum / n_prof
             a = analysis(p, mean_prof)
-            out["lambda_b"], out["lambda_t"] = bl_thickness(mean_prof[0], p.D, rtol)
+            out["lambda_b"], out["lambda_t"] = bl_thickness(mean_prof[0], p.D, rtol, z)
             out["profiles"] = {"Tsa_z": a["Tsa_z"].tolist(), "drho_z": a["drho_z"].tolist(),
                                "U_z": a["U_z"].tolist()}
         return out

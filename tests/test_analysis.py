@@ -37,9 +37,10 @@ def _oracle_state(po, steps, seed):
 
 # ---- host-only functions (CPU) ------------------------------------------------
 
-@pytest.mark.parametrize("ndim", [2, 3])
-def test_host_analysis_matches_oracle(ndim):
-    kw = dict(ndim=ndim, nx=48, nz=17, ny=16 if ndim == 3 else 1, Ra=1e5, Pr=0.7, seed=3)
+@pytest.mark.parametrize("ndim,s", [(2, 0.0), (3, 0.0), (2, 1.4), (3, 0.9)])
+def test_host_analysis_matches_oracle(ndim, s):
+    kw = dict(ndim=ndim, nx=48, nz=17, ny=16 if ndim == 3 else 1, Ra=1e5, Pr=0.7, seed=3,
+              stretch=s)
     po, pg = both(**kw)
     prof, _ = an.profiles(po, _oracle_state(po, 0, seed=11))
     want = an.analysis(po, prof)
@@ -64,6 +65,13 @@ def test_host_bl_thickness_matches_oracle():
         mtvd.bl_thickness(np.zeros(2), D)
     with pytest.raises(mtvd.MtvdError):
         mtvd.bl_thickness(np.zeros(9), -1.0)
+    # on the node heights of a tanh grid
+    for nz, s in ((129, 1.5), (65, 0.8)):
+        z = oracle.heights(oracle.Params(nz=nz, stretch=s))
+        t = 1.0 - D * z - 6.0 * 0.02 * (1.0 - np.exp(-z / 0.02)) + 3.0 * 0.05 * (1.0 - np.exp(-(1.0 - z) / 0.05))
+        want = an.bl_thickness(t, D, 0.1, z=z)
+        got = mtvd.bl_thickness(t, D, 0.1, z=z)
+        assert abs(got[0] - want[0]) <= 1e-14 and abs(got[1] - want[1]) <= 1e-14, (nz, got, want)
 
 
 # ---- device row means (GPU) ---------------------------------------------------
@@ -83,6 +91,8 @@ def _check_profiles(got, want, scale, label):
     dict(ndim=2, nx=8200, nz=9, steps=0, Ra=1e10),   # 3 ragged segments per row
     dict(ndim=3, nx=40, ny=24, nz=17, steps=4, Ra=1e6),
     dict(ndim=3, nx=96, ny=72, nz=9, steps=0, Ra=1e6),   # 2 segments per row
+    dict(ndim=2, nx=256, nz=64, steps=20, Ra=1e7, stretch=1.3),   # tanh grid
+    dict(ndim=3, nx=40, ny=24, nz=17, steps=2, Ra=1e7, stretch=1.0),
 ])
 def test_profiles_match_oracle(case):
     gpu_or_skip()

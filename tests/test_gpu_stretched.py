@@ -183,18 +183,6 @@ def test_stretched_conduction_with_uniform_pressure_is_steady_on_gpu():
         assert abs(d[k] - 1.0) < 1e-11, (k, d[k])
 
 
-@pytest.mark.gpu
-def test_stretched_profiles_are_rejected():
-    import paper_2411_10372_amd as mtvd
-    _, pg = both(nx=64, nz=17, stretch=1.0)
-    sv = _solver(pg)
-    sv.init_state()
-    with pytest.raises(mtvd.MtvdError) as ei:
-        sv.profiles()
-    sv.close()
-    assert ei.value.code == -1
-
-
 # ---- 3D ----------------------------------------------------------------------
 
 GRIDS3 = [(70, 11, 9), (16, 6, 7), (61, 9, 12), (8, 4, 5), (24, 20, 40)]
@@ -293,10 +281,9 @@ def test_stretched_grid_rules_on_the_host():
     assert L.mtvd_batch_bytes(boxes, 2, ctypes.byref(sb), ctypes.byref(wb)) == -1
     p = mtvd.Params(nx=64, nz=17, stretch=1.0)._c()
     assert L.mtvd_adj_bytes(ctypes.byref(p), 10, 5, ctypes.byref(wb)) == -1
-    # the host analysis functions refuse stretched profiles
-    prof = np.ones(10 * 17)
+    # the grid form of the boundary-layer thickness wants increasing heights
     with pytest.raises(mtvd.MtvdError):
-        mtvd.analysis(mtvd.Params(nx=64, nz=17, stretch=1.0), prof.reshape(10, 17))
+        mtvd.bl_thickness(np.ones(9), 0.4, 0.1, z=np.zeros(9))
 
 
 def test_library_and_oracle_grids_are_the_same_bits():
