@@ -52,8 +52,9 @@ def random_case(seed: int, ndim: int) -> dict:
     """One seeded random problem for the parameter fuzz: a small grid (down
     to one column in x and y and the minimum nz = 5), every parameter of
     Sec. 2 drawn over a wide range and every switch of the scheme drawn,
-    plus the perturbation and the rows per wave.  Keys: the parameter
-    names, and 'amp', 'pseed', 'tiling', 'steps'."""
+    plus the perturbation, the rows per wave and the z grid (uniform or
+    tanh-stretched).  Keys: the parameter names, and 'amp', 'pseed',
+    'tiling', 'steps'."""
     rng = np.random.default_rng(seed)
     if ndim == 2:
         nx, ny, nz = int(rng.integers(1, 131)), 1, int(rng.integers(5, 41))
@@ -82,4 +83,8 @@ def random_case(seed: int, ndim: int) -> dict:
     tiling = (0, 0) if rng.random() < 0.3 else (int(rng.integers(1, 9)), int(rng.integers(1, 9)))
     kw.update(amp=float(rng.uniform(0.0, 0.03)), pseed=int(rng.integers(0, 2**31)),
               tiling=tiling, steps=int(rng.integers(1, 5)))
+    # the z grid: uniform for half of the draws, else the tanh grid with s
+    # in [0.3, 2] (drawn last, so the draws above do not depend on it)
+    u, sv = rng.random(), float(rng.uniform(0.3, 2.0))
+    kw["stretch"] = 0.0 if u < 0.5 else sv
     return kw

@@ -1,9 +1,10 @@
 """Seeded random parameter sets, GPU against the oracle (tiny grids).
 
-Each case draws a grid (down to one column in x and y and the minimum nz),
-all parameters of Sec. 2, every switch of the scheme, the rows per wave and
-a perturbation of the oracle's initial state (tests/inputs.random_case),
-then takes 1-4 full steps (Sec. 3.1) on both sides.  The cases are a fixed
+Each case draws a grid (down to one column in x and y and the minimum nz;
+uniform or tanh-stretched in z), all parameters of Sec. 2, every switch of
+the scheme, the rows per wave and a perturbation of the oracle's initial
+state (tests/inputs.random_case), then takes 1-4 full steps (Sec. 3.1) on
+both sides.  The cases are a fixed
 list: the same draws on every run, each printed before it runs.
 
 Bar: parity error (tests/helpers.parity_error) <= max(3e-13, 16 s), where s
