@@ -459,7 +459,8 @@ __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const
                                                        int slot, int first,
                                                        const double* __restrict__ X,
                                                        double* __restrict__ Y, int kc,
-                                                       int nstrips, int nbb, int chunk0) {
+                                                       int nstrips, int nbb, int row0,
+                                                       int row_end) {
   __shared__ double xa[2][2][kNW][64];
   __shared__ double xb[2][2][kNW][64];
   constexpr int B = (AX == 2) ? 1 : 2;
@@ -471,7 +472,7 @@ __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const
   const int strip = bid % nstrips;
   bid /= nstrips;
   const int bb = bid % nbb;
-  const int chunk = chunk0 + bid / nbb;
+  const int chunk = bid / nbb;   // of this launch's rows [row0, row_end)
   const Lane3 L = lane3(c, strip, lane);
   const int nb_len = (B == 1) ? c.ny : c.nz;
   const int braw = bb * (kNW - 4) - 2 + w;   // index of this wave along B
@@ -487,9 +488,8 @@ __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const
     bwall = bval && (braw == 0 || braw == c.M);
   }
   const bool owave = w >= 2 && w < kNW - 2 && braw >= 0 && braw < nb_len;
-  const int mlen = (AX == 2) ? c.nz : c.ny;
-  const int m0 = chunk * kc;
-  const int m1 = min(m0 + kc, mlen);
+  const int m0 = row0 + chunk * kc;
+  const int m1 = min(m0 + kc, row_end);
   const double tau = 0.5 * dt;
   const double lm = tau * ((AX == 2) ? c.ihz : c.ihy);
   MF st;
@@ -733,17 +733,19 @@ hipError_t launch_sweep_3d(int axis, const Coef& c, Shared* sh, const double* zr
       }
 #undef MTVD_LF
     } else {
-      // chunks [lo, hi] cannot touch a plate (first row >= 4, last row <=
-      // M-4): the copy without plate code; the others the general one.  The
-      // launches of one operator are independent (disjoint output rows); only
-      // the first one does the step's bookkeeping (time, dt, the next slot).
-      const int lo = (4 + kc - 1) / kc;
-      const int hi = (c.M - 4) / kc - 1;
+      // The kPlate rows next to each plate run the copy with the plate and
+      // wall code (its registers spill) in launches of their own; the rows
+      // between (output rows >= 4 and <= M-4, so no stage reaches a plate)
+      // run the copy without it in chunks of kc.  The launches of one
+      // operator are independent (disjoint output rows); only the first one
+      // does the step's bookkeeping (time, dt, the next slot).
+      constexpr int kPlate = 8;
       int fst = first;
-      auto run = [&](int c0, int c1, bool pl) {
-        if (c1 < c0) return;
-        const dim3 g((unsigned)((long long)nstrips * nbb * (c1 - c0 + 1)));
-#define MTVD_MF(F, P, T) sweep_mf3d<2, F, P, T><<<g, block, 0, s>>>(c, sh, zr, slot, fst, X, Y, kc, nstrips, nbb, c0)
+      auto run = [&](int r0, int r1, int k, bool pl) {
+        if (r1 <= r0) return;
+        const long long nck = (r1 - r0 + k - 1) / k;
+        const dim3 g((unsigned)((long long)nstrips * nbb * nck));
+#define MTVD_MF(F, P, T) sweep_mf3d<2, F, P, T><<<g, block, 0, s>>>(c, sh, zr, slot, fst, X, Y, k, nstrips, nbb, r0, r1)
         if (str) {
           if (pl) {
             if (fuse) MTVD_MF(true, true, true); else MTVD_MF(false, true, true);
@@ -760,12 +762,12 @@ hipError_t launch_sweep_3d(int axis, const Coef& c, Shared* sh, const double* zr
 #undef MTVD_MF
         fst = 0;
       };
-      if (lo > hi) {
-        run(0, nch - 1, true);
+      if (c.nz > 2 * kPlate) {
+        run(0, kPlate, kPlate, true);
+        run(kPlate, c.nz - kPlate, kc, false);
+        run(c.nz - kPlate, c.nz, kPlate, true);
       } else {
-        run(0, lo - 1, true);
-        run(lo, hi, false);
-        run(hi + 1, nch - 1, true);
+        run(0, c.nz, kc, true);
       }
     }
   } else {
@@ -775,7 +777,7 @@ hipError_t launch_sweep_3d(int axis, const Coef& c, Shared* sh, const double* zr
     const long long nblk = (long long)nstrips * nbb * nch;
     if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
     const dim3 grid((unsigned)nblk);
-#define MTVD_MY(F, T) sweep_mf3d<1, F, true, T><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nbb, 0)
+#define MTVD_MY(F, T) sweep_mf3d<1, F, true, T><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nbb, 0, c.ny)
     if (str) {
       if (fuse) MTVD_MY(true, true); else MTVD_MY(false, true);
     } else {
