@@ -503,18 +503,17 @@ int default_rows(const mtvd_ctx* c, int axis) {
     // small grids: at least 2 rows (more, shorter waves measured faster
     // down to 2 at 512x128, where every launch is latency-bound)
     if (kc < 2) kc = 2;
+    if (kc > 64) kc = 64;
   } else {
-    // 3D, blocks of 8 waves: a quarter of the marched extent (L_x and L_z
-    // march z, L_y marches y), at most 64 rows; L_z at most 48, so that
-    // most of its chunks stay clear of the plates and run the copy without
-    // plate code (measured at 1024x1024x256: L_x, L_y best at 64-128 rows,
-    // L_z at 24-48)
+    // 3D, blocks of 8 waves (L_x and L_z march z, L_y marches y): L_x and
+    // L_y half the marched extent, at most 128 rows; L_z a quarter, at most
+    // 48 (its plate rows run in launches of their own).  Measured at
+    // 1024x1024x256 over 32-128 rows: L_x, L_y fastest at 128, L_z at 48.
     const long long len = (axis == 1) ? c->c.ny : c->c.nz;
-    kc = len / 4;
-    if (kc > ((axis == 2) ? 48 : 64)) kc = (axis == 2) ? 48 : 64;
+    kc = (axis == 2) ? len / 4 : len / 2;
+    if (kc > ((axis == 2) ? 48 : 128)) kc = (axis == 2) ? 48 : 128;
     if (kc < 4) kc = 4;
   }
-  if (kc > 64) kc = 64;
   return (int)kc;
 }
 
