@@ -265,7 +265,7 @@ def init_theta(p: Params, theta: np.ndarray) -> np.ndarray:
     q = Params(**{**p.__dict__, "noise_amp": 0.0})
     X = init(q)
     M = p.nz - 1
-    z = (np.arange(p.nz, dtype=np.float64) / M)[:, None]
+    z = heights(p)[:, None]     # k/M on the uniform grid
     T0 = 1.0 - (p.eps + p.D) * z
     cv = 1.0 / (p.gamma * p.eps * p.D)
     g = p.gravity_scale / p.eps

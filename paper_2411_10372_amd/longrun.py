@@ -107,7 +107,7 @@ def main(argv=None) -> int:
     ap.add_argument("--noise", type=float, default=1e-3)
     ap.add_argument("--limiter-form", type=int, default=0)
     ap.add_argument("--stretch", type=float, default=0.0,
-                    help="tanh z-grid parameter s (0: uniform; 2D only)")
+                    help="tanh z-grid parameter s (0: uniform; 3D: nz <= 2048)")
     ap.add_argument("--t0", type=float, required=True, help="start of the averaging window")
     ap.add_argument("--t1", type=float, required=True, help="simulated end time")
     ap.add_argument("--sample-steps", type=int, default=100)
