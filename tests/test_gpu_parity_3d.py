@@ -107,14 +107,16 @@ def test_3d_mass_conserved_and_deterministic():
     assert abs(m1 - m0) / m0 <= 1e-13
 
 
-def test_3d_full_size_one_step_sampled():
-    """1024 x 1024 x 256, Ra 1e9: one GPU step from the GPU's own initial
-    state against the oracle on sampled 8 x 8 column patches (one of them
-    across the periodic corner)."""
+@pytest.mark.parametrize("workload", ["3d_1024x1024x256_ra1e9", "3d_1024x1024x256_ra1e9_tanh1.2"])
+def test_3d_full_size_one_step_sampled(workload):
+    """1024 x 1024 x 256, Ra 1e9 (uniform and tanh z grid): one GPU step from
+    the GPU's own initial state against the oracle on sampled 8 x 8 column
+    patches (one of them across the periodic corner), in the launch
+    configuration the benchmark times."""
     from paper_2411_10372_amd.workloads import params_dict
-    kw = params_dict("3d_1024x1024x256_ra1e9")
+    kw = params_dict(workload)
     po, pg = both(**kw)
-    _say("3d full size: oracle dt of the initial state")
+    _say("3d full size: oracle dt of the initial state", workload)
     X0 = oracle.init(po)
     dt = oracle.dt(po, X0)
     del X0
