@@ -221,13 +221,13 @@ struct MF {
 constexpr int kZL3 = 2048;
 __shared__ double zlds[kZL3];
 
-// PL: the chunk may touch a plate (L_z).  Chunks that cannot (first row
-// >= 4, last row <= M-4: every stage then works on rows 2..M-4) run a copy
-// compiled without the plate and wall code, whose registers fit without
-// spilling.
-// STR: a stretched z grid.  L_z takes every z spacing from the prefetched
-// heights; L_y (waves along z) gets its wave's centred span and narrowest
-// face in ihb2 and izw.
+// PL: the launch's rows may touch a plate (L_z).  The rows between (first
+// output row >= 4, last <= M-4: every stage then works on rows 2..M-4) run
+// a copy compiled without the plate and wall code, whose registers fit
+// without spilling.
+// STR: a stretched z grid.  L_z takes every z spacing from the heights in
+// LDS; L_y (waves along z) gets its wave's centred span and narrowest face
+// in ihb2 and izw.
 template <int AX, int S, bool FUSE, bool PL, bool STR>
 __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, int fe, int m0,
                                         int m1, int w, int lane, const Lane3& L, int bidx,
