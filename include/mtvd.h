@@ -181,8 +181,11 @@ int mtvd_diagnostics(mtvd_ctx* c, mtvd_diag* out);
  * z-momentum balance F_n, F_p, F_b, F_v) and Re (Sec. 2).  Derivatives:
  * central second order along x, y and inside; second-order one-sided on
  * the plates ((-3, 4, -1)/(2 dz), (3, -4, 1)/(2 dz); second derivatives
- * (2, -5, 4, -1)/dz^2); F_v = mu (lap u_z + (1 + lambda) d_z div u); F_b
- * = rho g with g = gravity_scale/eps; T_sa = T - (1 - D z).
+ * (2, -5, 4, -1)/dz^2); on a stretched grid the same stencils on the node
+ * heights (first derivatives over the same stencil of z; second derivatives
+ * by the three-point formula inside and the cubic through the plate and
+ * its three neighbours on a plate); F_v = mu (lap u_z + (1 + lambda) d_z
+ * div u); F_b = rho g with g = gravity_scale/eps; T_sa = T - (1 - D z).
  * out: host array of count >= MTVD_NUM_PROFILES * nz doubles, written
  * quantity-major (out[q * nz + k]).  Device work on the context's stream,
  * then synchronises.  MTVD_ESTATE without a state, MTVD_ESIZE if count is
@@ -192,7 +195,9 @@ int mtvd_profiles(mtvd_ctx* c, double* out, size_t count);
 /* Host only, no device work: the snapshot scalars of a profile array
  * (count >= MTVD_NUM_PROFILES * p->nz) and, into each non-NULL array of
  * p->nz doubles, T_sa(z) = <T>_A - (1 - D z), rho(z) - rho_A(z) with
- * rho_A = (1 - D z)^(1/(gamma-1)), and U(z) = sqrt(<|u|^2>_A) (Sec. 5).
+ * rho_A = (1 - D z)^(1/(gamma-1)), and U(z) = sqrt(<|u|^2>_A) (Sec. 5), at
+ * the node heights of the grid p defines (volume means weigh the rows by
+ * their dual cells on a stretched grid).
  * MTVD_EINVAL on bad arguments, MTVD_ESIZE if count is too small. */
 int mtvd_analysis_from_profiles(const mtvd_params* p, const double* prof, size_t count,
                                 mtvd_analysis* out, double* tsa_z, double* drho_z,
