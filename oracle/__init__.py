@@ -11,6 +11,14 @@ equations, Nusselt numbers) and Sec. 3.1 (MacCormack-TVD scheme).
 
 Parity status of each function (what pins it is in ``tests/test_oracle_*``):
   init, splitmix64  -- pinned (closed forms, published SplitMix64 outputs)
+  init_box          -- pinned (equal bit for bit to the matching slice of
+                       init, also for windows across the periodic seams)
+  dt                -- pinned (closed form cfl min h_a/(|u_a| + c) on moving
+                       uniform states in 2D and 3D, each direction deciding
+                       in turn; one fast node on the tanh grid, whose row's
+                       narrowest face decides; gravity inside T)
+  sweep_box         -- pinned (its inner columns equal those of sweep, also
+                       for windows across the periodic seams)
   sweep x/y/z, step -- pinned (linear acoustics/viscous/thermal amplification
                        in closed form, conservation, symmetries, hydrostatic
                        convergence, second-order self-convergence)
