@@ -80,6 +80,7 @@ class _Params(ctypes.Structure):
         ("tvd_on", ctypes.c_int32), ("gravity_scale", ctypes.c_double),
         ("wall_order", ctypes.c_int32), ("pred_dir", ctypes.c_int32), ("diffusion_scale", ctypes.c_double),
         ("nthreads", ctypes.c_int32), ("stretch", ctypes.c_double),
+        ("dt_rule", ctypes.c_int32),
     ]
 
 
@@ -116,6 +117,7 @@ class Params:
     diffusion_scale: float = 1.0
     nthreads: int = 0
     stretch: float = 0.0
+    dt_rule: int = 0
 
     def _c(self) -> _Params:
         return _Params(**{f.name: getattr(self, f.name) for f in fields(self)})

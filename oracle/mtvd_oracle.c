@@ -33,7 +33,8 @@
  *   - TVD: both ratios of one face share the denominator |dX_{k+1/2}|^2; a
  *     face whose denominator is exactly 0 gets no TVD flux; Co of a face is
  *     (tau/h) max over its two nodes of (|u_a| + c) at level n;
- *   - dt = cfl * min over nodes and directions of h_a/(|u_a| + c);
+ *   - dt = cfl * min over nodes and directions of h_a/(|u_a| + c) (with
+ *     dt_rule = 1 also of rho h^2 / kappa, the explicit diffusion limit);
  *   - the initial state: T = 1 - (eps+D) z, rho = T^(m-1) (hydrostatic for
  *     the unperturbed T), m = gamma D / ((gamma-1)(eps+D)), noise on
  *     interior T from SplitMix64.
@@ -122,6 +123,7 @@ static int check_params(const ora_params* p) {
   if (!(p->Ra > 0.0) || !(p->Pr > 0.0) || !(p->aspect > 0.0)) return -1;
   if (p->wall_order != 1 && p->wall_order != 2) return -1;
   if (!(p->stretch >= 0.0) || !(p->stretch <= 10.0)) return -1;
+  if (p->dt_rule != 0 && p->dt_rule != 1) return -1;
   return 0;
 }
 
@@ -394,6 +396,20 @@ double ora_dt(const ora_params* p, const double* X) {
                 : fmin(zface(&c, k - 1), zface(&c, k));
           }
           double v = h / (fabs(u[d]) + cs);
+          if (v < best) best = v;
+        }
+        if (p->dt_rule == 1) {
+          /* explicit diffusion limit: rho h^2 / kappa over the node's
+           * smallest spacing */
+          double hm = c.h[0];
+          if (c.ndim == 3) hm = fmin(hm, c.h[1]);
+          double hz = c.h[2];
+          if (c.stretched)
+            hz = (k == 0) ? zface(&c, 0) : (k == c.M) ? zface(&c, c.M - 1)
+                 : fmin(zface(&c, k - 1), zface(&c, k));
+          hm = fmin(hm, hz);
+          double kappa = fmax(c.mu * (2.0 + fabs(c.lam)), c.K / c.cv);
+          double v = (rho * (hm * hm)) / kappa;
           if (v < best) best = v;
         }
       }

@@ -61,6 +61,8 @@ typedef struct ora_params {
   double stretch;        /* s of the tanh z grid (Sec. 3.1 grid): z_k =
                             (1 + tanh(s (2k/M - 1)) / tanh s) / 2; 0 gives
                             the uniform grid z_k = k/M */
+  int32_t dt_rule;       /* 0: dt from the acoustic CFL condition alone;
+                            1: also the explicit diffusion limit (ora_dt) */
 } ora_params;
 
 typedef struct ora_diag {
@@ -90,7 +92,12 @@ int ora_init(const ora_params* p, double* X);
 int ora_init_box(const ora_params* p, int i0, int j0, int bx, int by,
                  double* B);
 
-/* dt = cfl * min over nodes and directions of h_a / (|u_a| + c) */
+/* dt = cfl * min over nodes and directions of h_a / (|u_a| + c); with
+ * dt_rule = 1 the minimum also runs over rho h^2 / kappa of every node, h
+ * its smallest spacing (the narrowest z face on the tanh grid) and
+ * kappa = max(mu (2 + |lambda|), K / c_v) the largest diffusivity times rho
+ * (viscous with the bulk term, thermal), so that each directional operator
+ * L(dt/2) has diffusion number kappa (dt/2) / (rho h^2) <= cfl/2 */
 double ora_dt(const ora_params* p, const double* X);
 
 /* one directional operator L_axis(tau) on the whole periodic domain;

@@ -208,3 +208,84 @@ def test_sweep_box_inner_columns_are_those_of_sweep(ora, ndim, axis, wrap):
         assert np.array_equal(out[:, :, 2:bx - 2], want[:, :, 2:bx - 2])
     else:
         assert np.array_equal(out[:, :, 2:by - 2, 2:bx - 2], want[:, :, 2:by - 2, 2:bx - 2])
+
+
+# ---------------------------------------------------------------------------
+# the explicit diffusion limit (dt_rule = 1)
+
+
+def _kappa(p):
+    """The largest diffusivity times rho of Sec. 2: viscous mu* (2 + |lambda|)
+    (the normal stress with the bulk term), thermal K* / c_v*."""
+    mu = math.sqrt(p.Pr / p.Ra)
+    K = 1.0 / (p.eps * p.D * math.sqrt(p.Ra * p.Pr))
+    cv = 1.0 / (p.gamma * p.eps * p.D)
+    return max(mu * (2.0 + abs(p.bulk_coef)), K / cv)
+
+
+@pytest.mark.parametrize("ndim,Pr,lam,stretch", [
+    (2, 1.0, -2.0 / 3.0, 0.0),   # viscous diffusivity the larger
+    (2, 0.3, -2.0 / 3.0, 0.0),   # thermal the larger
+    (2, 1.0, 0.0, 0.0),          # no bulk term: mu* 2
+    (3, 1.0, 2.0 / 3.0, 0.0),
+    (2, 1.0, -2.0 / 3.0, 1.5),   # tanh grid: the narrowest face of the row
+    (3, 0.5, -2.0 / 3.0, 1.5),
+])
+def test_dt_rule_diffusion_limit_closed_form(ora, ndim, Pr, lam, stretch):
+    """At rest, uniform T, density falling with height: at low Ra the
+    diffusion limit cfl rho_min h^2 / kappa decides, at the least dense
+    node (the top row) with the smallest spacing there."""
+    if ndim == 2:
+        p = Params(ndim=2, nx=40, nz=17, aspect=1.0, Ra=50.0, Pr=Pr, bulk_coef=lam,
+                   noise_amp=0.0, stretch=stretch, dt_rule=1)
+    else:
+        p = Params(ndim=3, nx=24, ny=20, nz=13, aspect=1.0, Ra=50.0, Pr=Pr, bulk_coef=lam,
+                   noise_amp=0.0, stretch=stretch, dt_rule=1)
+    z = _tanh_heights(stretch, p.nz) if stretch else np.arange(p.nz) / (p.nz - 1)
+    T = 0.6
+    rho = (1.3 - 0.8 * z).reshape((p.nz,) + (1,) * (len(p.shape) - 2))
+    zeros = [np.zeros(p.shape[1:]) for _ in range(ndim)]
+    X = _state(p, rho, zeros, T, z)
+    c = _sound(p, T)
+    faces = np.diff(z)
+    hz_top = faces[-1]
+    hs = [p.aspect / p.nx] + ([p.aspect / p.ny] if ndim == 3 else [])
+    h_top = min(hs + [hz_top])
+    acoustic = min(hs + [faces.min()]) / c
+    diffusive = (1.3 - 0.8) * h_top ** 2 / _kappa(p)
+    assert diffusive < acoustic
+    want = p.cfl * diffusive
+    got = ora.dt(p, X)
+    # on the tanh grid the top face is a difference of two heights near 1,
+    # each from a tanh (numpy's here, libm's in the oracle) that may differ
+    # by an ulp: about 1e-14 relative in the face, twice that in h^2
+    tol = 1e-12 if stretch else 1e-14
+    assert abs(got - want) <= tol * want, (got, want)
+    # the acoustic rule alone ignores it
+    q = Params(**{**p.__dict__, "dt_rule": 0})
+    assert abs(ora.dt(q, X) - p.cfl * acoustic) <= tol * p.cfl * acoustic
+
+
+def test_dt_rule_keeps_a_diffusion_dominated_box_stable(ora):
+    """Ra = 100 on a 32 x 17 box: with the acoustic step alone the diffusion
+    number of each operator is about 2, and the seeded +-1e-2 noise drives
+    grid-scale motion over a hundred times that of the diffusion-limited
+    run (the limiter and the nonlinearity keep it bounded, not small); with
+    the diffusion limit the number is cfl/2 = 1/4 and the sub-critical box
+    relaxes (kinetic energy falls after the initial adjustment)."""
+    kw = dict(ndim=2, nx=32, nz=17, aspect=1.0, Ra=100.0, noise_amp=1e-2, seed=4)
+    bad = Params(**kw, dt_rule=0)
+    good = Params(**kw, dt_rule=1)
+    X0 = ora.init(bad)
+    Xb, Xg = X0, X0
+    mb = mg = 0.0
+    for i in range(6):
+        Xb = ora.step(bad, Xb, 5)[0]
+        Xg = ora.step(good, Xg, 5)[0]
+        mb = max(mb, float(np.max(np.abs(Xb[1]))))
+        mg = max(mg, float(np.max(np.abs(Xg[1]))))
+        if i == 2:
+            k15 = ora.diag(good, Xg)["kinetic"]
+    assert np.all(np.isfinite(Xg))
+    assert mb > 100.0 * mg, (mb, mg)
+    assert ora.diag(good, Xg)["kinetic"] < 0.9 * k15
