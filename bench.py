@@ -1,17 +1,17 @@
 #!/usr/bin/env python3
 """Benchmark of the MacCormack-TVD step on one MI355X.
 
-Workload (default): the 2D 4096 x 1024 box, FP64, gamma 1.4, Pr 1, Ra 1e10,
-plates at T = 1 and 0.5, seeded +-1e-3 T noise, 1000 steps with the
-diagnostics (Nu, mass, ...) every 100 steps.  The state is synthetic
-(generated on the GPU by mtvd_init_state) and resident in HBM before the
-timed region.
+Workload (default): the largest single-GPU case, the 3D 1024 x 1024 x 256
+box (FP64, gamma 1.4, Pr 1, Ra 1e9, plates at T = 1 and 0.5, periodic in x
+and y, seeded +-1e-3 T noise).  The state is synthetic (generated on the GPU
+by mtvd_init_state) and resident in HBM before the timed region.
 
-Prints ONE JSON line: cell-updates/s over the timed steps (diagnostics
-included), the per-kernel roofline of the dominant sweep kernel (bytes of
-the per-sweep model: read and write every field once per node, measured
-with HIP events recorded on the library's stream), and the CPU oracle timed
-on a bounded sample of the same workload.
+Prints ONE JSON line: cell-updates/s (the median of several repetitions of
+K steps, each bracketed by device synchronisations), the roofline of the
+dominant sweep kernel (bytes of the per-sweep model: read and write every
+field once per node, over its average duration from HIP events recorded on
+the library's stream) against the HBM peak and against a measured device
+copy, and the CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -82,11 +82,22 @@ def copy_ref() -> int:
     return 2 * a.numel() * 8
 
 
-def cpu_baseline(kw: dict, budget_s: float):
-    """The CPU oracle, as it stands, on a bounded sample of the workload:
-    as many full steps from its initial state as fit in about budget_s."""
+def cpu_model() -> str:
+    """The host CPU's model name (lscpu's, from /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate_full(kw: dict, budget_s: float, threads: int):
+    """Full oracle steps from the initial state, as many as fit in about
+    budget_s: (cell-updates/s, steps, seconds)."""
     import oracle
-    p = oracle.Params(**kw)
+    p = oracle.Params(**kw, nthreads=threads)
     X = oracle.init(p)
     nodes = p.nx * (p.ny if p.ndim == 3 else 1) * p.nz
     t0 = time.perf_counter()
@@ -97,11 +108,90 @@ def cpu_baseline(kw: dict, budget_s: float):
     if extra:
         X, _, _ = oracle.step(p, X, extra)
     tot = one + (time.perf_counter() - t1)
-    steps = 1 + extra
-    return {"value": nodes * steps / tot, "unit": "cell-updates/s", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": f"{steps} full steps of the same workload from its initial state "
-                      f"({tot:.1f} s, OpenMP threads {oracle.threads()})"}
+    return nodes * (1 + extra) / tot, 1 + extra, tot
+
+
+def _oracle_rate_patches(kw: dict, budget_s: float, threads: int, side: int = 68):
+    """The oracle's box operators on sampled column patches of a 3D grid
+    (side x side columns, all rows, a two-column halo each way): the six
+    operators of a step applied to each patch, patches taken at seeded
+    positions until about budget_s have passed.  Rate = inner nodes of the
+    patches times operators / 6 over the time: (cell-updates/s, patches,
+    seconds)."""
+    import numpy as np
+    import oracle
+    p = oracle.Params(**kw, nthreads=threads)
+    rng = np.random.default_rng(12)
+    X0 = oracle.init_box(p, 0, 0, side, side)
+    # dt of the first patch: a grid of side x side columns with the same
+    # spacings as the whole one
+    pb = oracle.Params(**{**kw, "nx": side, "ny": side,
+                          "aspect": kw["aspect"] * side / kw["nx"]}, nthreads=threads)
+    assert kw["nx"] == kw["ny"]
+    tau = 0.5 * oracle.dt(pb, X0)
+    inner = (side - 4) * (side - 4) * p.nz
+    order = (2, 1, 0, 2, 1, 0)
+    done, tot = 0, 0.0
+    while True:
+        i0, j0 = int(rng.integers(0, p.nx)), int(rng.integers(0, p.ny))
+        B = oracle.init_box(p, i0, j0, side, side)
+        t0 = time.perf_counter()
+        for a in order:
+            B = oracle.sweep_box(p, a, tau, B)
+        tot += time.perf_counter() - t0
+        done += 1
+        if tot >= budget_s:
+            break
+    return inner * done / tot, done, tot
+
+
+def cpu_baseline(kw: dict, budget_s: float):
+    """The CPU oracle, as it stands (gcc -O2, no fast-math, OpenMP over
+    rows), on a bounded sample of the workload, single-threaded and on all
+    host cores.  2D: full steps from the initial state.  3D: the six box
+    operators of a step on sampled 68 x 68-column patches (all rows), since
+    a full step of the 1024 x 1024 x 256 grid takes minutes."""
+    import oracle
+    allc = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+    share = 0.25 if kw["ndim"] == 3 else 0.3
+    if kw["ndim"] == 3:
+        r1, n1, s1 = _oracle_rate_patches(kw, share * budget_s, 1)
+        rn, nn, sn = _oracle_rate_patches(kw, (1 - share) * budget_s, allc)
+        what = (f"sampled: the 6 box operators of one step on {nn} seeded 68x68-column "
+                f"patches of all {kw['nz']} rows ({nn * 64 * 64 * kw['nz']} inner nodes, "
+                f"{sn:.1f} s, {allc} threads); single thread {n1} patches in {s1:.1f} s")
+    else:
+        r1, n1, s1 = _oracle_rate_full(kw, share * budget_s, 1)
+        rn, nn, sn = _oracle_rate_full(kw, (1 - share) * budget_s, allc)
+        what = (f"{nn} full steps of the same workload from its initial state "
+                f"({sn:.1f} s, {allc} threads); single thread {n1} steps in {s1:.1f} s")
+    del oracle
+    return {"value": rn, "unit": "cell-updates/s", "cores": allc, "kind": "oracle",
+            "sample": what, "single_thread_value": r1, "cpu_model": cpu_model()}
+
+
+def copy_bandwidth(nbytes: int = 2 << 30, reps: int = 5) -> float:
+    """GB/s of a plain device-to-device copy of nbytes (read + write bytes
+    over the median time of reps copies, timed with events on torch's
+    stream)."""
+    import statistics
+
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / statistics.median(ts) / 1e9
 
 
 def bench_batch(args):
@@ -245,10 +335,12 @@ def bench_adjoint(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=0,
+                    help="steps per timed repetition (default: the workload's)")
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="2d_4096x1024_ra1e10")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--reps", type=int, default=5, help="timed repetitions (median reported)")
+    ap.add_argument("--workload", default="3d_1024x1024x256_ra1e9")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM counters)")
@@ -261,11 +353,15 @@ def main():
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
 
+    import statistics
+
     import torch
     import paper_2411_10372_amd as mtvd
     from paper_2411_10372_amd.workloads import WORKLOADS, params_dict
 
     wl = WORKLOADS[args.workload]
+    if not args.steps:
+        args.steps = wl.get("steps", 100)
     if "boxes" in wl:
         return bench_batch(args)
     if "adjoint_every" in wl:
@@ -273,10 +369,12 @@ def main():
     kw = params_dict(args.workload)
     p = mtvd.Params(**kw)
     diag_every = wl.get("diag_every", 0)
-    K, W = args.steps, args.warmup
+    K, W, R = args.steps, args.warmup, max(1, args.reps)
     nodes = p.nodes
+    sweeps = 6 if p.ndim == 3 else 4
 
     torch.cuda.set_device(0)
+    copy_gbs = copy_bandwidth()
     s = mtvd.Solver(p, device="cuda:0")
     if args.rows:
         s.set_tiling(*args.rows)
@@ -285,30 +383,38 @@ def main():
     s.sync()
     torch.cuda.synchronize()
 
-    # timed region: K steps, diagnostics every diag_every steps (they
-    # synchronise with the host, as a production run would)
-    log(f"timing {K} steps of {args.workload} ({nodes} nodes)")
-    t0 = time.perf_counter()
-    done = 0
-    diags = []
-    while done < K:
-        n = K - done
-        if diag_every:
-            n = min(n, diag_every - done % diag_every)
-        s.step(n)
-        done += n
-        if diag_every and done % diag_every == 0:
-            diags.append(s.diagnostics())
-    s.sync()
-    torch.cuda.synchronize()
-    t_all = time.perf_counter() - t0
+    # timed region: R repetitions of K steps, each bracketed by device
+    # synchronisations; diagnostics every diag_every steps where the
+    # workload asks for them (they synchronise with the host, as a
+    # production run would)
+    log(f"timing {R} x {K} steps of {args.workload} ({nodes} nodes)")
+    reps, done = [], 0
+    for _ in range(R):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        k = 0
+        while k < K:
+            n = K - k
+            if diag_every:
+                n = min(n, diag_every - done % diag_every)
+            s.step(n)
+            k += n
+            done += n
+            if diag_every and done % diag_every == 0:
+                s.diagnostics()
+        s.sync()
+        torch.cuda.synchronize()
+        reps.append(time.perf_counter() - t0)
+    t_med = statistics.median(reps)
 
-    # the same K steps without diagnostics
-    t0 = time.perf_counter()
-    s.step(K)
-    s.sync()
-    torch.cuda.synchronize()
-    t_nodiag = time.perf_counter() - t0
+    value_no_diag = None
+    if diag_every:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(K)
+        s.sync()
+        torch.cuda.synchronize()
+        value_no_diag = nodes * K / (time.perf_counter() - t0)
 
     # and again with HIP events around every sweep launch on the library's
     # stream (per-kernel durations for the roofline; the events themselves
@@ -328,8 +434,9 @@ def main():
     achieved = per_launch_bytes / avg_s / 1e9
     shash = source_hash(KERNEL_SOURCES[p.ndim])
     traffic = load_traffic(args.workload, AXES[dom], shash)
-
-    value = nodes * K / t_all
+    value = nodes * K / t_med
+    step_bytes_sweep = sweeps * 2 * p.nf * 8     # per cell-update, per-sweep model
+    step_bytes_floor = 2 * p.nf * 8              # per cell-update, one pass per step
     out = {
         "metric": METRIC,
         "value": value,
@@ -337,7 +444,7 @@ def main():
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
-        "ms_per_step": 1e3 * t_all / K,
+        "ms_per_step": 1e3 * t_med / K,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -348,15 +455,26 @@ def main():
                    "D": p.D, "cfl": p.cfl, "stretch": p.stretch, "diag_every": diag_every},
         "roofline": {"bound": "hbm", "kernel": AXES[dom], "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "bytes_per_launch": per_launch_bytes},
-        "value_no_diag": nodes * K / t_nodiag,
+                     "traffic": traffic, "bytes_per_launch": per_launch_bytes,
+                     "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
+        "repetitions_s": reps,
+        "step_roofline": {
+            "per_sweep_model_frac": value * step_bytes_sweep / 1e9 / HBM_PEAK_GBS,
+            "floor_model_frac": value * step_bytes_floor / 1e9 / HBM_PEAK_GBS,
+            "per_sweep_model_frac_of_copy": value * step_bytes_sweep / 1e9 / copy_gbs,
+            "bytes_per_cell_update": {"per_sweep": step_bytes_sweep, "floor": step_bytes_floor}},
         "kernels": kern,
         "final": {"step": dfin["step"], "time": dfin["time"], "mass": dfin["mass"],
                   "nu_mean": dfin["nu_mean"], "nu_bulk": dfin["nu_bulk"]},
         "source_hash": shash,
     }
+    if value_no_diag is not None:
+        out["value_no_diag"] = value_no_diag
     if args.copy_ref:
         out["copy_ref_bytes"] = copy_ref()
+    s.close()
+    del s
+    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(kw, args.cpu_seconds)
