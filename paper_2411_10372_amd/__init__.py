@@ -544,12 +544,15 @@ class Adjoint:
         return t
 
     def forward(self, theta=None, dt: float = 0.0):
-        """J and the dt used (dt = 0: the CFL dt of X_0)."""
+        """J and the dt used (dt = 0: the CFL dt of X_0).  Every call replaces
+        the checkpoints that :meth:`backward` reverses and advances
+        :attr:`generation`."""
         t = self._theta(theta)
         self._theta_keep = t
         J, d = ctypes.c_double(), ctypes.c_double()
         self._check(lib().mtvd_adj_forward(self.ctx, ctypes.c_void_p(t.data_ptr() if t is not None else 0),
                                            float(dt), ctypes.byref(J), ctypes.byref(d)))
+        self.generation = getattr(self, "generation", 0) + 1
         return J.value, d.value
 
     def backward(self, Jbar: float = 1.0, want_x0: bool = False):
@@ -586,24 +589,45 @@ def _nu_function():
 
     class TimeAveragedNu(torch.autograd.Function):
         """J(theta, Ra) as a differentiable torch op; the backward pass is the
-        library's hand-written adjoint (recomputation from checkpoints)."""
+        library's hand-written adjoint (recomputation from checkpoints).
+
+        dt is held fixed in the derivative.  With dt = 0 the first
+        application takes the CFL dt of its X_0 and the adjoint keeps it
+        (``frozen_dt``) for every later application, so that J is one smooth
+        function of theta whose gradient the backward pass returns.  The
+        adjoint's checkpoints belong to its latest forward pass: if another
+        forward ran on the same adjoint since this application's, the
+        backward pass first recomputes this one's from its saved theta."""
 
         @staticmethod
         def forward(ctx, theta, ra, adjoint, dt):
             if abs(float(ra) - adjoint.p.Ra) > 1e-12 * adjoint.p.Ra:
                 raise ValueError("Ra differs from the one the adjoint was created for")
-            J, _ = adjoint.forward(theta.detach(), dt)
+            dt = float(dt)
+            if dt <= 0.0:
+                dt = getattr(adjoint, "frozen_dt", 0.0)
+            th = theta.detach().clone()
+            J, dt_used = adjoint.forward(th, dt)
+            if dt <= 0.0:
+                adjoint.frozen_dt = dt_used
             ctx.adjoint = adjoint
+            ctx.generation = adjoint.generation
+            ctx.theta = th
+            ctx.dt = dt_used
+            ctx.theta_shape = theta.shape
             ctx.ra_device = ra.device if torch.is_tensor(ra) else None
             return torch.tensor(J, dtype=torch.float64, device=theta.device)
 
         @staticmethod
         def backward(ctx, gJ):
-            gt, _, gr = ctx.adjoint.backward(float(gJ))
+            a = ctx.adjoint
+            if a.generation != ctx.generation:
+                a.forward(ctx.theta, ctx.dt)
+            gt, _, gr = a.backward(float(gJ))
             gra = None
             if ctx.ra_device is not None:
                 gra = torch.tensor(gr, dtype=torch.float64, device=ctx.ra_device)
-            return gt.to(gJ.device), gra, None, None
+            return gt.reshape(ctx.theta_shape).to(gJ.device), gra, None, None
 
     return TimeAveragedNu
 
@@ -612,9 +636,12 @@ _TAN = None
 
 
 def time_averaged_nu(theta, ra, adjoint: Adjoint, dt: float = 0.0):
-    """Differentiable J(theta, Ra) (see :class:`Adjoint`).  ``theta`` is an
-    (nz, nx) float64 tensor on the GPU, ``ra`` a 0-d float64 tensor equal to
-    the adjoint's Ra; gradients flow to both."""
+    """Differentiable J(theta, Ra) (see :class:`Adjoint`).  ``theta`` is a
+    float64 tensor of nz*nx values on the GPU (any shape; its gradient has
+    the same shape), ``ra`` a 0-d float64 tensor equal to the adjoint's Ra;
+    gradients flow to both.  ``dt`` > 0 fixes the time step; dt = 0 takes
+    the CFL dt of the first application's initial state and keeps it for
+    every later one on the same adjoint (the derivative holds dt fixed)."""
     global _TAN
     if _TAN is None:
         _TAN = _nu_function()

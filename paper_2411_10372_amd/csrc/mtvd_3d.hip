@@ -19,8 +19,12 @@
 
 namespace mtvd {
 
-constexpr int kStrip3 = 60;
-constexpr int kNW = 8;
+constexpr int kNW = 8;                  // waves per block
+constexpr int kLW = 32;                 // lanes per plane row (x columns)
+constexpr int kPPW = 64 / kLW;          // planes per wave
+constexpr int kPB = kNW * kPPW;         // planes per block (2 halo each side)
+constexpr int kPer = kPB - 4;           // output planes per block
+constexpr int kStrip3 = kLW - 4;        // output columns per strip
 
 struct N3 { double r, m[3], E; };
 struct P3 { double u[3], T, p; };
@@ -84,18 +88,28 @@ __device__ __forceinline__ N3 shu(const N3& v) {
   return N3{shu(v.r), {shu(v.m[0]), shu(v.m[1]), shu(v.m[2])}, shu(v.E)};
 }
 
+// A lane's place in the block: column x of its plane row (two halo columns
+// each side) and plane p of the block (two halo planes each side); wave w
+// holds planes kPPW w .. kPPW w + kPPW-1, so a plane row is kLW consecutive
+// lanes and the lane shifts along x stay inside it for every lane whose
+// result is kept.
 struct Lane3 {
-  int col;
-  bool out;
+  int col;    // grid column
+  int x, p;   // column in the plane row, plane in the block
+  int role;   // 0: outer halo plane (X^n only), 1: inner halo plane (X^P), 2: output plane
+  bool out;   // column of an output lane (the plane decides the rest)
 };
 
-__device__ __forceinline__ Lane3 lane3(const Coef& c, int strip, int lane) {
+__device__ __forceinline__ Lane3 lane3(const Coef& c, int strip, int w, int lane) {
   Lane3 r;
+  r.x = lane % kLW;
+  r.p = w * kPPW + lane / kLW;
   int i0 = strip * kStrip3;
-  int i = i0 - 2 + lane;
+  int i = i0 - 2 + r.x;
   int m = i % c.nx;
   r.col = (m < 0) ? m + c.nx : m;
-  r.out = lane >= 2 && lane < 62 && (i0 + lane - 2) < c.nx;
+  r.out = r.x >= 2 && r.x < kLW - 2 && (i0 + r.x - 2) < c.nx;
+  r.role = (r.p == 0 || r.p == kPB - 1) ? 0 : ((r.p == 1 || r.p == kPB - 2) ? 1 : 2);
   return r;
 }
 
@@ -129,23 +143,54 @@ __device__ __forceinline__ void store3(const Coef& c, double* __restrict__ Y, lo
   Y[n + 4 * c.cnt] = v.E;
 }
 
-// Two scalars of every wave to LDS, barrier, and their central differences
-// across neighbouring waves.  Each exchange array has two buffers that
+// The same at node u + (this lane's node within a z plane), where u is the
+// same for the whole wave and the lane's part comes as a byte offset below
+// 4 GiB (the launcher checks 8 nx ny < 2^32): the field bases stay scalar
+// and a lane's address costs one 32-bit register.
+__device__ __forceinline__ const double& at_ob(const double* __restrict__ p, unsigned ob) {
+  return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(p) + ob);
+}
+__device__ __forceinline__ N3 load3o(const Coef& c, const double* __restrict__ X, long long u,
+                                     unsigned ob) {
+  const double* b = X + u;
+  N3 v;
+  v.r = at_ob(b, ob);
+  v.m[0] = at_ob(b + c.cnt, ob);
+  v.m[1] = at_ob(b + 2 * c.cnt, ob);
+  v.m[2] = at_ob(b + 3 * c.cnt, ob);
+  v.E = at_ob(b + 4 * c.cnt, ob);
+  return v;
+}
+__device__ __forceinline__ void store3o(const Coef& c, double* __restrict__ Y, long long u,
+                                        unsigned ob, const N3& v) {
+  char* b = reinterpret_cast<char*>(Y + u);
+  const long long fs = c.cnt * (long long)sizeof(double);
+  *reinterpret_cast<double*>(b + ob) = v.r;
+  *reinterpret_cast<double*>(b + fs + ob) = v.m[0];
+  *reinterpret_cast<double*>(b + 2 * fs + ob) = v.m[1];
+  *reinterpret_cast<double*>(b + 3 * fs + ob) = v.m[2];
+  *reinterpret_cast<double*>(b + 4 * fs + ob) = v.E;
+}
+
+// Two scalars of every lane to LDS, barrier, and their central differences
+// across neighbouring planes (the block's edge planes take a zero
+// difference; they are outer halo).  Each exchange array has two buffers that
 // alternate with the parity of the march row: two exchanges in a row on the
 // same array (at a chunk's first rows, at the top plate) then use different
 // buffers, and the barrier of the second one orders every read of the first
 // before the next write to its buffer, so a wave that runs ahead never
 // overwrites a value a slower wave has yet to read.
-__device__ __forceinline__ void exchange(double (&buf)[2][kNW][64], int w, int lane,
+__device__ __forceinline__ void exchange(double (&buf)[2][kPB * kLW], const Lane3& L,
                                          double a, double b, double ih2, double& da,
                                          double& db) {
-  buf[0][w][lane] = a;
-  buf[1][w][lane] = b;
+  const int i = L.p * kLW + L.x;
+  buf[0][i] = a;
+  buf[1][i] = b;
   __syncthreads();
-  const int wm = (w > 0) ? w - 1 : w;
-  const int wp = (w < kNW - 1) ? w + 1 : w;
-  da = (buf[0][wp][lane] - buf[0][wm][lane]) * ih2;
-  db = (buf[1][wp][lane] - buf[1][wm][lane]) * ih2;
+  const int im = (L.p > 0) ? i - kLW : i;
+  const int ip = (L.p < kPB - 1) ? i + kLW : i;
+  da = (buf[0][ip] - buf[0][im]) * ih2;
+  db = (buf[1][ip] - buf[1][im]) * ih2;
 }
 
 struct Acc3 {
@@ -230,12 +275,12 @@ __shared__ double zlds[kZL3];
 // in ihb2 and izw.
 template <int AX, int S, bool FUSE, bool PL, bool STR>
 __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, int fe, int m0,
-                                        int m1, int w, int lane, const Lane3& L, int bidx,
+                                        int m1, const Lane3& L, unsigned lob, long long lnode,
                                         bool bval, bool bwall, bool owave,
-                                        double (&xa)[2][2][kNW][64], double (&xb)[2][2][kNW][64],
+                                        double (&xa)[2][2][kPB * kLW], double (&xb)[2][2][kPB * kLW],
                                         const double* __restrict__ zr,
                                         const double* __restrict__ X, double* __restrict__ Y,
-                                        double tau, double lm, int bload, double zb,
+                                        double tau, double lm, double zb, int flo, int fhi,
                                         double ihb2, double izw) {
   constexpr int B = (AX == 2) ? 1 : 2;   // axis of the waves
   constexpr bool P = (AX == 2) && PL;    // plate rows possible in this chunk
@@ -244,11 +289,12 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
   const double ihm = (AX == 2) ? c.ihz : c.ihy;
   constexpr int c0 = S & 3, c1 = (S + 3) & 3, c2 = (S + 2) & 3, c3 = (S + 1) & 3, c4 = S & 3;
   constexpr int e0 = S & 1, e1 = (S + 1) & 1;
-  const int role = (w == 0 || w == kNW - 1) ? 0 : ((w == 1 || w == kNW - 2) ? 1 : 2);
-  // node of march row `row`
-  auto node = [&](int row) -> long long {
-    if (AX == 2) return ((long long)row * c.ny + bidx) * c.nx + L.col;
-    return ((long long)bidx * c.ny + wrap(row, c.ny)) * c.nx + L.col;
+  const int role = L.role;
+  // node of march row `row`: L_z the lane's column of z plane `row` (lane
+  // part lob, a byte offset); L_y plane bidx, row `row` (lane part lnode)
+  auto stnode = [&](int row, const N3& v) {
+    if (AX == 2) store3o(c, Y, (long long)row * c.plane, lob, v);
+    else store3(c, Y, (long long)wrap(row, c.ny) * c.nx + lnode, v);
   };
   // A (every step of the march, guarded by nothing): row f of X^n
   //    (prefetched two steps ago) and its primitives; prefetch row f+2 with
@@ -259,10 +305,9 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
   //    ring slots no stage reads, and their exchanged values are zeroed.
   {
     st.x[c0] = st.pf[e0];
-    const int fp = (AX == 2) ? min(max(f + 2, 0), M) : f + 2;
-    const long long np = (AX == 2) ? ((long long)fp * c.ny + bidx) * c.nx + L.col
-                                   : ((long long)bload * c.ny + wrap(fp, c.ny)) * c.nx + L.col;
-    st.pf[e0] = load3(c, X, np);
+    const int fp = min(max(f + 2, flo), fhi);
+    if (AX == 2) st.pf[e0] = load3o(c, X, (long long)fp * c.plane, lob);
+    else st.pf[e0] = load3(c, X, (long long)wrap(fp, c.ny) * c.nx + lnode);
     st.pn[c0] = prim3(c, st.x[c0], SZ ? zlds[min(max(f, 0), M)] : (AX == 2) ? zrow(f, M) : zb);
     st.s[c0] = fabs(st.pn[c0].u[AX]) + sound(c, st.pn[c0].T);
   }
@@ -283,12 +328,12 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
   }
   const bool rin_F = P ? (r >= 0 && r <= M - 1) : true;
   // B: predictor flux F_r (inner derivatives forward along the march); the
-  //    cross-wave derivatives of row r first (every wave of the block takes
-  //    part in the exchange: its condition is the same for all of them)
+  //    derivatives across the planes of row r first (every wave of the block
+  //    takes part in the exchange: its condition is the same for all of them)
   double bb = 0.0, bm = 0.0;   // d_B u_B and d_B u_AX of X^n at row r
   if (r >= m0 - 2 && rin_F) {
     const double ub = bval ? st.pn[c2].u[B] : 0.0, um = bval ? st.pn[c2].u[AX] : 0.0;
-    exchange(xa[S & 1], w, lane, ub, um, ihb2, bb, bm);
+    exchange(xa[S & 1], L, ub, um, ihb2, bb, bm);
   }
   if (r >= m0 - 2 && rin_F && role >= 1 && bval && !bwall) {
     P3 q0 = st.pn[c2];
@@ -314,7 +359,7 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
     q0.p = c.a * st.x[c2].r * q0.T;
     st.F[e0] = flux3<AX>(c, st.x[c2], q0, du, dT);
   }
-  // C: predictor X^P_r; exchange its velocities across waves
+  // C: predictor X^P_r; exchange its velocities across the planes
   const bool rin_P = P ? (r >= 0 && r <= M) : true;
   double pb = 0.0, pm = 0.0;   // d_B u_B and d_B u_AX of X^P at row r
   if (r >= m0 - 1 && rin_P) {
@@ -349,7 +394,7 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
     }
     double ub = (role >= 1 && bval) ? st.pp[c2].u[B] : 0.0;
     double um = (role >= 1 && bval) ? st.pp[c2].u[AX] : 0.0;
-    exchange(xb[S & 1], w, lane, ub, um, ihb2, pb, pm);
+    exchange(xb[S & 1], L, ub, um, ihb2, pb, pm);
   }
   // D: corrector flux F^P_r (inner derivatives backward along the march)
   const bool rin_FP = P ? (r >= 1 && r <= M) : true;
@@ -427,7 +472,7 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
         out.E = 0.5 * (xp.E + xc.E) + (Dc.E - Dm.E);
       }
       if (FUSE) acc_out(c, out, z_o, SZ ? fmax(st.ihf1, st.ihf2) : izw, st.acc, L.out);
-      if (L.out) store3(c, Y, node(o), out);
+      if (L.out) stnode(o, out);
     }
     st.Dp = Dc;
   }
@@ -445,7 +490,7 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
     }
     if (FUSE)
       acc_out(c, out, z_o, SZ ? (bwall ? izw : o == 0 ? st.ihf1 : st.ihf2) : izw, st.acc, L.out);
-    if (L.out) store3(c, Y, node(o), out);
+    if (L.out) stnode(o, out);
   }
   if (SZ) {
     st.ihf2 = st.ihf1;
@@ -461,8 +506,8 @@ __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const
                                                        double* __restrict__ Y, int kc,
                                                        int nstrips, int nbb, int row0,
                                                        int row_end) {
-  __shared__ double xa[2][2][kNW][64];
-  __shared__ double xb[2][2][kNW][64];
+  __shared__ double xa[2][2][kPB * kLW];
+  __shared__ double xb[2][2][kPB * kLW];
   constexpr int B = (AX == 2) ? 1 : 2;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
@@ -473,9 +518,9 @@ __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const
   bid /= nstrips;
   const int bb = bid % nbb;
   const int chunk = bid / nbb;   // of this launch's rows [row0, row_end)
-  const Lane3 L = lane3(c, strip, lane);
+  const Lane3 L = lane3(c, strip, w, lane);
   const int nb_len = (B == 1) ? c.ny : c.nz;
-  const int braw = bb * (kNW - 4) - 2 + w;   // index of this wave along B
+  const int braw = bb * kPer - 2 + L.p;   // index of this lane's plane along B
   int bidx;
   bool bval, bwall;
   if (B == 1) {
@@ -487,7 +532,7 @@ __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const
     bval = braw >= 0 && braw <= c.M;
     bwall = bval && (braw == 0 || braw == c.M);
   }
-  const bool owave = w >= 2 && w < kNW - 2 && braw >= 0 && braw < nb_len;
+  const bool owave = L.role == 2 && braw >= 0 && braw < nb_len;
   const int m0 = row0 + chunk * kc;
   const int m1 = min(m0 + kc, row_end);
   const double tau = 0.5 * dt;
@@ -498,10 +543,16 @@ __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const
   st.Dp = N3{0.0, {0.0, 0.0, 0.0}, 0.0};
   const int fs = (AX == 2) ? max(0, m0 - 2) : m0 - 2;
   const int fe = m1 + 2;
-  // the plane this wave loads from (L_y: clamped into the plates) and its
-  // height
+  // rows the stages read: m0-2 .. m1+1 (in the plates for L_z); the head
+  // loads clamped rows outside, which cache hits serve
+  const int flo = (AX == 2) ? max(0, m0 - 2) : m0 - 2;
+  const int fhi = (AX == 2) ? min(c.M, m1 + 1) : m1 + 1;
+  // the plane this lane loads from (L_y: clamped into the plates) and its
+  // height; the lane's part of its nodes' addresses
   const int bload = (AX == 1) ? min(max(bidx, 0), c.M) : bidx;
   const double zb = (AX == 1) ? zr[bload] : 0.0;
+  const unsigned lob = (AX == 2) ? (unsigned)(bidx * c.nx + L.col) * 8u : 0u;
+  const long long lnode = (AX == 1) ? (long long)bload * c.plane + L.col : 0;
   // the centred span across the waves (y for L_z; z for L_y, which on a
   // stretched grid is the wave's plane's own) and, for L_y's dt entry, the
   // plane's narrowest face
@@ -524,10 +575,10 @@ __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const
   // heads before them copy this defined, unused row
   st.pf[0] = st.pf[1] = N3{1.0, {0.0, 0.0, 0.0}, 1.0};
   for (int fb = (fs - 2) & ~3; fb <= fe; fb += 4) {
-    mf_iter<AX, 0, FUSE, PL, STR>(c, st, fb + 0, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, bload, zb, ihb2, izw);
-    mf_iter<AX, 1, FUSE, PL, STR>(c, st, fb + 1, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, bload, zb, ihb2, izw);
-    mf_iter<AX, 2, FUSE, PL, STR>(c, st, fb + 2, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, bload, zb, ihb2, izw);
-    mf_iter<AX, 3, FUSE, PL, STR>(c, st, fb + 3, fs, fe, m0, m1, w, lane, L, bidx, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, bload, zb, ihb2, izw);
+    mf_iter<AX, 0, FUSE, PL, STR>(c, st, fb + 0, fs, fe, m0, m1, L, lob, lnode, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, zb, flo, fhi, ihb2, izw);
+    mf_iter<AX, 1, FUSE, PL, STR>(c, st, fb + 1, fs, fe, m0, m1, L, lob, lnode, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, zb, flo, fhi, ihb2, izw);
+    mf_iter<AX, 2, FUSE, PL, STR>(c, st, fb + 2, fs, fe, m0, m1, L, lob, lnode, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, zb, flo, fhi, ihb2, izw);
+    mf_iter<AX, 3, FUSE, PL, STR>(c, st, fb + 3, fs, fe, m0, m1, L, lob, lnode, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, zb, flo, fhi, ihb2, izw);
   }
   if (FUSE) fold3(sh, slot, st.acc);
 }
@@ -551,29 +602,28 @@ struct LF {
 
 template <int S, bool FUSE, bool STR>
 __device__ __forceinline__ void lf_iter(const Coef& c, LF& st, int f, int fs, int fe, int k0,
-                                        int k1, int w, int lane, const Lane3& L, int j,
-                                        bool owave, double (&xa)[2][2][kNW][64],
-                                        double (&xb)[2][2][kNW][64],
+                                        int k1, const Lane3& L, unsigned lob,
+                                        bool owave, double (&xa)[2][2][kPB * kLW],
+                                        double (&xb)[2][2][kPB * kLW],
                                         const double* __restrict__ zr,
                                         const double* __restrict__ X, double* __restrict__ Y,
-                                        double lx) {
+                                        double lx, int flo, int fhi) {
   const int M = c.M;
   constexpr int c0 = S & 3, c1 = (S + 3) & 3, c2 = (S + 2) & 3, c3 = (S + 1) & 3;
-  const int role = (w == 0 || w == kNW - 1) ? 0 : ((w == 1 || w == kNW - 2) ? 1 : 2);
+  const int role = L.role;
   const double ihy2 = 0.5 * c.ihy;
-  auto node = [&](int k) -> long long { return ((long long)k * c.ny + j) * c.nx + L.col; };
 
   constexpr int e0 = S & 1;
   // every step, guarded by nothing (as in the march kernels of L_z, L_y)
   {
     st.x[c0] = st.pf[e0];
     if (STR) st.zz[c0] = st.pz[e0];
-    const int fp = min(max(f + 2, 0), M);
-    st.pf[e0] = load3(c, X, node(fp));
+    const int fp = min(max(f + 2, flo), fhi);
+    st.pf[e0] = load3o(c, X, (long long)fp * c.plane, lob);
     if (STR) st.pz[e0] = zr[fp];
     st.pn[c0] = prim3(c, st.x[c0], STR ? st.zz[c0] : zrow(f, M));
     st.s[c0] = fabs(st.pn[c0].u[0]) + sound(c, st.pn[c0].T);
-    exchange(xa[S & 1], w, lane, st.pn[c0].u[0], st.pn[c0].u[1], ihy2, st.yx[c0], st.yy[c0]);
+    exchange(xa[S & 1], L, st.pn[c0].u[0], st.pn[c0].u[1], ihy2, st.yx[c0], st.yy[c0]);
   }
   if (f < fs || f > fe) return;
   // stretched grid: centred span of row f-1 from the ring heights (rows past
@@ -611,7 +661,7 @@ __device__ __forceinline__ void lf_iter(const Coef& c, LF& st, int f, int fs, in
     }
     double a = (role >= 1) ? st.pp[c1].u[0] : 0.0;
     double b = (role >= 1) ? st.pp[c1].u[1] : 0.0;
-    exchange(xb[S & 1], w, lane, a, b, ihy2, st.pyx[c1], st.pyy[c1]);
+    exchange(xb[S & 1], L, a, b, ihy2, st.pyx[c1], st.pyy[c1]);
   }
   // corrector, average and TVD term on row f-2
   const int r = f - 2;
@@ -662,7 +712,7 @@ __device__ __forceinline__ void lf_iter(const Coef& c, LF& st, int f, int fs, in
       }
       acc_out(c, out, STR ? st.zz[c2] : zrow(r, M), izs, st.acc, L.out);
     }
-    if (L.out) store3(c, Y, node(r), out);
+    if (L.out) store3o(c, Y, (long long)r * c.plane, lob, out);
   }
   if (STR) st.icen1 = icen;
 }
@@ -673,8 +723,8 @@ __global__ __launch_bounds__(64 * kNW) void sweep_lf3d(Coef c, Shared* sh, const
                                                        const double* __restrict__ X,
                                                        double* __restrict__ Y, int kc,
                                                        int nstrips, int nbb) {
-  __shared__ double xa[2][2][kNW][64];
-  __shared__ double xb[2][2][kNW][64];
+  __shared__ double xa[2][2][kPB * kLW];
+  __shared__ double xb[2][2][kPB * kLW];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const double dt = step_dt<STR>(c, sh, slot);
@@ -684,10 +734,11 @@ __global__ __launch_bounds__(64 * kNW) void sweep_lf3d(Coef c, Shared* sh, const
   bid /= nstrips;
   const int bb = bid % nbb;
   const int chunk = bid / nbb;
-  const Lane3 L = lane3(c, strip, lane);
-  const int jraw = bb * (kNW - 4) - 2 + w;
+  const Lane3 L = lane3(c, strip, w, lane);
+  const int jraw = bb * kPer - 2 + L.p;
   const int j = wrap(jraw, c.ny);
-  const bool owave = w >= 2 && w < kNW - 2 && jraw >= 0 && jraw < c.ny;
+  const bool owave = L.role == 2 && jraw >= 0 && jraw < c.ny;
+  const unsigned lob = (unsigned)(j * c.nx + L.col) * 8u;   // lane's part of its addresses
   const int k0 = chunk * kc;
   const int k1 = min(k0 + kc, c.nz);
   const double lx = 0.5 * dt * c.ihx;
@@ -696,14 +747,17 @@ __global__ __launch_bounds__(64 * kNW) void sweep_lf3d(Coef c, Shared* sh, const
   st.acc.bad = false;
   const int fs = max(0, k0 - 2);
   const int fe = k1 + 1;
+  // rows the stages read (the head loads clamped rows outside, which cache
+  // hits serve)
+  const int flo = max(0, k0 - 2), fhi = min(c.M, k1 + 1);
   st.pf[0] = st.pf[1] = N3{1.0, {0.0, 0.0, 0.0}, 1.0};
   st.pz[0] = st.pz[1] = 0.0;
   st.icen1 = 0.0;
   for (int fb = (fs - 2) & ~3; fb <= fe; fb += 4) {
-    lf_iter<0, FUSE, STR>(c, st, fb + 0, fs, fe, k0, k1, w, lane, L, j, owave, xa, xb, zr, X, Y, lx);
-    lf_iter<1, FUSE, STR>(c, st, fb + 1, fs, fe, k0, k1, w, lane, L, j, owave, xa, xb, zr, X, Y, lx);
-    lf_iter<2, FUSE, STR>(c, st, fb + 2, fs, fe, k0, k1, w, lane, L, j, owave, xa, xb, zr, X, Y, lx);
-    lf_iter<3, FUSE, STR>(c, st, fb + 3, fs, fe, k0, k1, w, lane, L, j, owave, xa, xb, zr, X, Y, lx);
+    lf_iter<0, FUSE, STR>(c, st, fb + 0, fs, fe, k0, k1, L, lob, owave, xa, xb, zr, X, Y, lx, flo, fhi);
+    lf_iter<1, FUSE, STR>(c, st, fb + 1, fs, fe, k0, k1, L, lob, owave, xa, xb, zr, X, Y, lx, flo, fhi);
+    lf_iter<2, FUSE, STR>(c, st, fb + 2, fs, fe, k0, k1, L, lob, owave, xa, xb, zr, X, Y, lx, flo, fhi);
+    lf_iter<3, FUSE, STR>(c, st, fb + 3, fs, fe, k0, k1, L, lob, owave, xa, xb, zr, X, Y, lx, flo, fhi);
   }
   if (FUSE) fold3(sh, slot, st.acc);
 }
@@ -714,8 +768,10 @@ hipError_t launch_sweep_3d(int axis, const Coef& c, Shared* sh, const double* zr
                            int first, bool fuse, const double* X, double* Y, int kc,
                            hipStream_t s) {
   const int nstrips = (c.nx + kStrip3 - 1) / kStrip3;
-  const int per = kNW - 4;
+  const int per = kPer;
   const dim3 block(64 * kNW);
+  // the lane part of an address within a z plane is a 32-bit byte offset
+  if ((unsigned long long)c.plane * sizeof(double) >= (1ull << 32)) return hipErrorInvalidValue;
   const bool str = c.stretched != 0;   // the copies compiled for a stretched z grid
   if (axis == 0 || axis == 2) {
     // waves along y

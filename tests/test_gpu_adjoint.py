@@ -164,6 +164,57 @@ def test_autograd_wrapper():
         mtvd.time_averaged_nu(t, torch.tensor(2 * pg.Ra, dtype=torch.float64), a, dt)
 
 
+def test_autograd_two_applications_before_backward():
+    # J(th1) + J(th2) on one adjoint: the second forward replaces the
+    # checkpoints, so the first application's backward recomputes its own;
+    # each gradient equals the direct one, and a flat theta gets a flat
+    # gradient
+    torch = gpu_or_skip()
+    import paper_2411_10372_amd as mtvd
+    _say("autograd, two applications on one adjoint")
+    po, pg, th, X0, dt = _setup(SMALL, 0.05)
+    th2 = theta_field(po.nz, po.nx, seed=9, amp=0.05)
+    a = mtvd.Adjoint(pg, N_SMALL, EVERY_SMALL)
+    t1 = torch.tensor(th, dtype=torch.float64, device="cuda", requires_grad=True)
+    t2 = torch.tensor(th2.reshape(-1), dtype=torch.float64, device="cuda", requires_grad=True)
+    ra = torch.tensor(pg.Ra, dtype=torch.float64, requires_grad=True)
+    J = mtvd.time_averaged_nu(t1, ra, a, dt) + mtvd.time_averaged_nu(t2, ra, a, dt)
+    J.backward()
+    b = mtvd.Adjoint(pg, N_SMALL, EVERY_SMALL)
+    b.forward(th, dt)
+    g1, _, r1 = b.backward(1.0)
+    b.forward(th2, dt)
+    g2, _, r2 = b.backward(1.0)
+    assert t2.grad.shape == t2.shape
+    assert torch.equal(t1.grad, g1)
+    assert torch.equal(t2.grad, g2.reshape(-1))
+    assert float(ra.grad) == r1 + r2
+
+
+def test_autograd_default_dt_is_frozen_at_the_first_application():
+    # dt = 0: the first application takes the CFL dt of its X_0, later ones
+    # on the same adjoint reuse it, so J(theta) is one function of theta
+    torch = gpu_or_skip()
+    import paper_2411_10372_amd as mtvd
+    _say("autograd, default dt")
+    po, pg, th, X0, dt = _setup(SMALL, 0.05)
+    th2 = theta_field(po.nz, po.nx, seed=9, amp=0.05)
+    a = mtvd.Adjoint(pg, N_SMALL, EVERY_SMALL)
+    ra = torch.tensor(pg.Ra, dtype=torch.float64)
+    t1 = torch.tensor(th, dtype=torch.float64, device="cuda", requires_grad=True)
+    J1 = mtvd.time_averaged_nu(t1, ra, a)
+    assert abs(a.frozen_dt - dt) <= 4e-16 * dt
+    t2 = torch.tensor(th2, dtype=torch.float64, device="cuda", requires_grad=True)
+    J2 = mtvd.time_averaged_nu(t2, ra, a)
+    J2.backward()
+    b = mtvd.Adjoint(pg, N_SMALL, EVERY_SMALL)
+    Jb, _ = b.forward(th2, a.frozen_dt)
+    g, _, _ = b.backward(1.0)
+    assert float(J2.detach()) == Jb
+    assert torch.equal(t2.grad, g)
+    assert float(J1.detach()) == b.forward(th, a.frozen_dt)[0]
+
+
 def test_rejects_what_it_does_not_reverse():
     gpu_or_skip()
     import paper_2411_10372_amd as mtvd
@@ -241,10 +292,14 @@ def test_c4_central_differences_within_the_kink_bound():
     g, _, _ = a.backward(1.0)
     g = g.cpu().numpy()
     gn = float(np.sqrt(np.sum(g * g)))
-    errs = []
+    errs, rels = [], []
     for v in unit_directions(po.nz, po.nx, 16, seed=5):
         jp, _ = a.forward(th + H * v, dt)
         jm, _ = a.forward(th - H * v, dt)
-        errs.append(abs((jp - jm) / (2 * H) - float(np.sum(g * v))) / gn)
+        gv = float(np.sum(g * v))
+        d = abs((jp - jm) / (2 * H) - gv)
+        errs.append(d / gn)
+        rels.append(d / abs(gv))
     _say("C4 max |fd - adjoint| / |g|", max(errs))
+    _say("C4 per-direction |fd - adjoint| / |adjoint|", " ".join(f"{r:.2e}" for r in rels))
     assert max(errs) <= 1e-4, errs
