@@ -259,6 +259,30 @@ int mtvd_destroy(mtvd_ctx* c);
 const char* mtvd_strerror(int status);
 const char* mtvd_last_error(const mtvd_ctx* c);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * time steps of mtvd_set_state + mtvd_step without a context or a
+ * workspace.  buf_a holds the state (canonical layout, device memory);
+ * buf_b is the second buffer of the ping-pong; both caller-owned, distinct,
+ * 256-byte aligned, state-sized.  The dt of the state in buf_a is computed
+ * first (time 0), then nsteps >= 0 steps run on hip_stream (NULL = default
+ * stream) exactly as mtvd_step runs them, same kernels and launch shapes,
+ * so the result equals that path's bit for bit; *which (host) tells which
+ * buffer holds it (0 = a, 1 = b).  Asynchronous: no host synchronisation,
+ * no allocation of any kind.  The scratch the steps need (the shared dt
+ * maxima, time and flags, and the row heights) is a static device array of
+ * MTVD_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends and
+ * shared by every call on that GPU: it is cleared at the start of each
+ * call, and calls that overlap on one GPU (other streams, other threads)
+ * race.  Limits: uniform z grids (stretch = 0; MTVD_EINVAL otherwise) and
+ * nz <= MTVD_NOALLOC_MAX_NZ (MTVD_ESIZE otherwise); other parameter errors
+ * as mtvd_create.  Device flags (non-finite or non-positive values) are
+ * not reported by this call.  MTVD_EHIP on a launch failure. */
+#define MTVD_NOALLOC_MAX_NZ 8192
+#define MTVD_NOALLOC_SCRATCH_BYTES (1280 + 8 * MTVD_NOALLOC_MAX_NZ)
+int mtvd_step_noalloc(const mtvd_params* p, double* buf_a, double* buf_b, int32_t nsteps,
+                      void* hip_stream, int32_t* which);
+
 /* ---------------------------------------------------------------------------
  * Batches: many independent 2D boxes (each with its own grid, Ra, Pr, seed,
  * dt and time) advanced together.  Each directional operator of a step is

@@ -189,8 +189,10 @@ def lib() -> ctypes.CDLL:
                                         dp, dp]
         L.mtvd_bl_thickness_grid.argtypes = [dp, dp, ctypes.c_int32, ctypes.c_double,
                                              ctypes.c_double, dp, dp]
+        L.mtvd_step_noalloc.argtypes = [P, vp, vp, ctypes.c_int32, vp,
+                                        ctypes.POINTER(ctypes.c_int32)]
         for fn in ("mtvd_profiles", "mtvd_analysis_from_profiles", "mtvd_bl_thickness",
-                   "mtvd_bl_thickness_grid"):
+                   "mtvd_bl_thickness_grid", "mtvd_step_noalloc"):
             getattr(L, fn).restype = ctypes.c_int
         for fn in ("mtvd_adj_bytes", "mtvd_adj_create", "mtvd_adj_bind", "mtvd_adj_forward",
                    "mtvd_adj_backward", "mtvd_adj_coef_grads", "mtvd_adj_destroy"):
@@ -268,6 +270,28 @@ def state_bytes(p: Params):
     if rc != MTVD_OK:
         raise MtvdError(rc, lib().mtvd_strerror(rc).decode())
     return sb.value, wb.value
+
+
+def step_noalloc(p: Params, buf_a, buf_b, nsteps: int, stream=None) -> int:
+    """``mtvd_step_noalloc``: nsteps steps of the state in ``buf_a`` (a
+    float64 CUDA tensor of the state's size; ``buf_b`` the same, the second
+    buffer) with no allocation; returns which buffer (0 = a, 1 = b) holds
+    the result.  Asynchronous on ``stream`` (default: torch's current
+    stream)."""
+    import torch
+    for b in (buf_a, buf_b):
+        if not (torch.is_tensor(b) and b.is_cuda and b.dtype == torch.float64
+                and b.is_contiguous() and b.numel() * 8 >= state_bytes(p)[0]):
+            raise ValueError("buffers must be contiguous float64 CUDA tensors of the state's size")
+    st = stream if stream is not None else torch.cuda.current_stream(buf_a.device)
+    which = ctypes.c_int32()
+    pc = p._c()
+    rc = lib().mtvd_step_noalloc(ctypes.byref(pc), ctypes.c_void_p(buf_a.data_ptr()),
+                                 ctypes.c_void_p(buf_b.data_ptr()), int(nsteps),
+                                 ctypes.c_void_p(st.cuda_stream), ctypes.byref(which))
+    if rc != MTVD_OK:
+        raise MtvdError(rc, lib().mtvd_strerror(rc).decode())
+    return which.value
 
 
 class Solver:

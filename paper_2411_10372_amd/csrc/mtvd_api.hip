@@ -10,6 +10,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -385,7 +386,8 @@ std::vector<double> grid_metrics(const std::vector<double>& z) {
   return m;
 }
 
-int validate(const mtvd_params* p, std::string* why) {
+// The checks with their reason as a string literal (no allocation).
+int validate_c(const mtvd_params* p, const char** why) {
   if (!p) { *why = "null params"; return MTVD_EINVAL; }
   if (p->ndim != 2 && p->ndim != 3) { *why = "ndim must be 2 or 3"; return MTVD_EINVAL; }
   if (p->nx < 1 || p->nz < 5 || (p->ndim == 3 && p->ny < 1)) {
@@ -440,6 +442,13 @@ int validate(const mtvd_params* p, std::string* why) {
   return MTVD_OK;
 }
 
+int validate(const mtvd_params* p, std::string* why) {
+  const char* w = "";
+  int rc = validate_c(p, &w);
+  *why = w;
+  return rc;
+}
+
 Coef make_coef(const mtvd_params* p) {
   Coef c;
   memset(&c, 0, sizeof(c));
@@ -489,17 +498,17 @@ Coef make_coef(const mtvd_params* p) {
 Shared* shared_of(mtvd_ctx* c) { return (Shared*)(c->ws + c->L.shared); }
 double* zrow_of(mtvd_ctx* c) { return (double*)(c->ws + c->L.zrow); }
 
-int default_rows(const mtvd_ctx* c, int axis) {
+// slots: resident waves of the 2D sweep kernel of `axis` (wave_slots_2d)
+int default_rows_for(const Coef& cf, int slots, int axis) {
   long long kc;
-  if (c->c.ndim == 2) {
+  if (cf.ndim == 2) {
     // the fewest rows per wave that keep the whole launch in one round of
     // the device's resident waves: long marches (less halo re-reading per
     // row) and no partly filled last round
-    const long long cols = (long long)strips_2d(c->c.nx);
-    const int slots = axis == 2 ? c->slots_z : c->slots_x;
+    const long long cols = (long long)strips_2d(cf.nx);
     long long chunks = slots > 0 ? slots / cols : 1;
     if (chunks < 1) chunks = 1;
-    kc = (c->c.nz + chunks - 1) / chunks;
+    kc = (cf.nz + chunks - 1) / chunks;
     // small grids: at least 2 rows (more, shorter waves measured faster
     // down to 2 at 512x128, where every launch is latency-bound)
     if (kc < 2) kc = 2;
@@ -511,7 +520,7 @@ int default_rows(const mtvd_ctx* c, int axis) {
     // launches of their own).  Measured at 1024x1024x256 over 32-256 rows:
     // L_x fastest at 256, L_y at 128, L_z at 48; uneven splits (160, 192
     // rows) are slow.
-    const long long len = (axis == 1) ? c->c.ny : c->c.nz;
+    const long long len = (axis == 1) ? cf.ny : cf.nz;
     if (axis == 0) {
       kc = len < 256 ? len : 256;
     } else if (axis == 1) {
@@ -522,6 +531,10 @@ int default_rows(const mtvd_ctx* c, int axis) {
     if (kc < 4) kc = 4;
   }
   return (int)kc;
+}
+
+int default_rows(const mtvd_ctx* c, int axis) {
+  return default_rows_for(c->c, axis == 2 ? c->slots_z : c->slots_x, axis);
 }
 
 hipError_t take_event(mtvd_ctx* c, hipEvent_t* ev) {
@@ -1872,5 +1885,118 @@ int mtvd_adj_destroy(mtvd_adj* a) {
 }
 
 const char* mtvd_adj_last_error(const mtvd_adj* a) { return a ? a->err.c_str() : ""; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// The step without a context or a caller workspace (for callers that cannot
+// allocate).  Its scratch -- the scalars the kernels share (Shared) and the
+// row heights -- lives in this array, one copy per GPU, held until the
+// process ends; host code reaches it only through the device address that
+// hipGetSymbolAddress returns for the current device.
+
+namespace {
+
+constexpr size_t kNoallocShared = (sizeof(Shared) + kAlign - 1) / kAlign * kAlign;
+constexpr size_t kNoallocBytes = kNoallocShared + sizeof(double) * MTVD_NOALLOC_MAX_NZ;
+static_assert(kNoallocBytes == MTVD_NOALLOC_SCRATCH_BYTES, "scratch size in the header");
+
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch[kMaxDevices];   // device address of `scratch` per device
+
+// the current device's copy of `scratch`, looked up once per device
+hipError_t scratch_of_current(unsigned char** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch[dev] = (unsigned char*)ptr;
+  }
+  *out = g_scratch[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mtvd_step_noalloc(const mtvd_params* p, double* buf_a, double* buf_b, int32_t nsteps,
+                      void* hip_stream, int32_t* which) {
+  if (!p || !buf_a || !buf_b || !which) return MTVD_EINVAL;
+  if (nsteps < 0) return MTVD_EINVAL;
+  if (p->stretch != 0.0) {
+    fprintf(stderr, "mtvd_step_noalloc: uniform z grids only (stretch = 0)\n");
+    return MTVD_EINVAL;
+  }
+  if (p->nz > MTVD_NOALLOC_MAX_NZ) {
+    fprintf(stderr, "mtvd_step_noalloc: nz = %d exceeds the scratch limit of %d rows\n", p->nz,
+            MTVD_NOALLOC_MAX_NZ);
+    return MTVD_ESIZE;
+  }
+  const char* why = "";
+  int rc = validate_c(p, &why);
+  if (rc != MTVD_OK) {
+    fprintf(stderr, "mtvd_step_noalloc: %s\n", why);
+    return rc;
+  }
+  if (buf_a == buf_b) return MTVD_ESIZE;
+  if (((uintptr_t)buf_a | (uintptr_t)buf_b) % kAlign) return MTVD_ESIZE;
+  unsigned char* base = nullptr;
+  if (scratch_of_current(&base) != hipSuccess) return MTVD_EHIP;
+  Shared* sh = (Shared*)base;
+  double* zr = (double*)(base + kNoallocShared);
+  hipStream_t st = (hipStream_t)hip_stream;
+  const Coef c = make_coef(p);
+  // clear the scalars with a kernel (no memset node if the caller captures
+  // this into a graph), then the row heights, time 0, and the dt of the
+  // state in buf_a, as mtvd_set_state does
+  hipError_t e = launch_fill((double*)sh, (long long)(sizeof(Shared) / sizeof(double)), 0.0, st);
+  if (e != hipSuccess) return MTVD_EHIP;
+  zrow_kernel<<<(c.nz + 255) / 256, 256, 0, st>>>(c.nz, zr);
+  set_scalars_kernel<<<1, 64, 0, st>>>(sh, 0.0, 1);
+  clear_slot_kernel<<<1, 64, 0, st>>>(sh, 0);
+  long long blocks = (c.cnt + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  dt_kernel<<<(int)blocks, 256, 0, st>>>(c, sh, zr, 0, buf_a);
+  if (p->dt_mode == 1) freeze_dt_kernel<<<1, 64, 0, st>>>(c, sh, 0);
+  if (hipGetLastError() != hipSuccess) return MTVD_EHIP;
+  // the steps, as mtvd_step
+  static const int o2[2][4] = {{2, 0, 2, 0}, {2, 0, 0, 2}};
+  static const int o3[2][6] = {{2, 1, 0, 2, 1, 0}, {2, 1, 0, 0, 1, 2}};
+  const int ns = (c.ndim == 3) ? 6 : 4;
+  const int* order = (c.ndim == 3) ? o3[p->sweep_order] : o2[p->sweep_order];
+  const bool track = (p->dt_mode == 0);
+  int kcs[3] = {0, 0, 0};
+  for (int a = 0; a < 3; ++a)
+    kcs[a] = default_rows_for(c, c.ndim == 2 ? wave_slots_2d(a, false) : 0, a);
+  double* buf[2] = {buf_a, buf_b};
+  int cur = 0, slot = 0;
+  for (int s = 0; s < nsteps; ++s) {
+    for (int o = 0; o < ns; ++o) {
+      const int axis = order[o];
+      const int first = (o == 0) ? 1 : 0;
+      const bool fuse = track && o == ns - 1;
+      e = (c.ndim == 2)
+              ? launch_sweep_2d(axis, c, sh, zr, slot, first, fuse, buf[cur], buf[cur ^ 1],
+                                kcs[axis], st)
+              : launch_sweep_3d(axis, c, sh, zr, slot, first, fuse, buf[cur], buf[cur ^ 1],
+                                kcs[axis], st);
+      if (e != hipSuccess) return MTVD_EHIP;
+      cur ^= 1;
+    }
+    if (track) slot ^= 1;
+  }
+  *which = cur;
+  return MTVD_OK;
+}
 
 }  // extern "C"

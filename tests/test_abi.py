@@ -90,3 +90,24 @@ def test_adjoint_sizes_and_restrictions(L):
     q = mtvd.Params(limiter_form=1)._c()
     assert L.mtvd_adj_create(ctypes.byref(q), 10, 5, None, ctypes.byref(ctx)) == -1
     assert not ctx.value
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(stretch=1.0), -1),              # uniform z grids only
+    (dict(nz=8193, nx=16384), -2),        # beyond the static scratch
+    (dict(ndim=4), -1),
+    (dict(cfl=1.5), -3),
+])
+def test_noalloc_step_rejects_before_device_work(L, kw, code):
+    # the checks come before any device call, so no GPU is needed; the
+    # buffer pointers are never touched on these paths
+    import paper_2411_10372_amd as mtvd
+    p = mtvd.Params(**kw)._c()
+    which = ctypes.c_int32(-7)
+    dummy = ctypes.c_void_p(256)
+    rc = L.mtvd_step_noalloc(ctypes.byref(p), dummy, ctypes.c_void_p(512), 1, None,
+                             ctypes.byref(which))
+    assert rc == code
+    assert which.value == -7
+    assert L.mtvd_step_noalloc(ctypes.byref(p), dummy, dummy, -1, None,
+                               ctypes.byref(which)) == -1
