@@ -95,6 +95,18 @@ typedef struct mtvd_params {
                             take every z derivative on the node heights.
                             Single boxes, 2D and 3D (3D: nz <= 2048);
                             MTVD_EINVAL in batches and for the adjoint. */
+  int32_t dt_rule;       /* time-step rule (Sec. 3.1 gives none):
+                            0 (default): dt = cfl min over nodes and
+                            directions of h_a/(|u_a| + c), and mtvd_create
+                            rejects a box whose initial diffusion number
+                            exceeds 1/2 (MTVD_ESTABILITY);
+                            1: the minimum also runs over rho h^2 / kappa of
+                            every node, h its smallest spacing (on a
+                            stretched grid the narrower z face next to it),
+                            kappa = max(mu (2 + |lambda|), K/c_v), so that
+                            every operator L(dt/2) keeps its diffusion
+                            number at most cfl/2, and no box is rejected for
+                            it */
 } mtvd_params;
 
 /* Diagnostics of the current state (Sec. 2: mass, kinetic energy, total

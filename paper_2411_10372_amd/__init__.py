@@ -47,6 +47,7 @@ class _Params(ctypes.Structure):
         ("limiter_form", ctypes.c_int32), ("sweep_order", ctypes.c_int32),
         ("tvd_on", ctypes.c_int32), ("gravity_scale", ctypes.c_double),
         ("wall_order", ctypes.c_int32), ("stretch", ctypes.c_double),
+        ("dt_rule", ctypes.c_int32),
     ]
 
 
@@ -81,6 +82,7 @@ class Params:
     gravity_scale: float = 1.0
     wall_order: int = 2
     stretch: float = 0.0
+    dt_rule: int = 0
 
     def _c(self) -> _Params:
         return _Params(**{f.name: getattr(self, f.name) for f in fields(self)})

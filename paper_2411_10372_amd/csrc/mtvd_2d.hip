@@ -74,28 +74,33 @@ __device__ __forceinline__ void step_head(const Coef& c, Shared* sh, int slot, i
   }
 }
 
-__device__ __forceinline__ void fold_max(Shared* sh, int slot, double mx, double mz,
-                                         bool bad) {
+__device__ __forceinline__ void fold_max(const Coef& c, Shared* sh, int slot, double mx,
+                                         double mz, double md, bool bad) {
   mx = wave_max(mx);
   mz = wave_max(mz);
+  if (c.dt_rule) md = wave_min(md);
   unsigned long long anybad = __ballot(bad);
   if ((threadIdx.x & 63) == 0) {
     atomicMax(&sh->smax[slot ^ 1][max_part()][0], d2u(mx));
     atomicMax(&sh->smax[slot ^ 1][max_part()][2], d2u(mz));
+    if (c.dt_rule) fold_rho_h2(sh, slot ^ 1, max_part(), md);
     if (anybad) atomicOr(&sh->flags, 1u);
   }
 }
 
 // izs: 1 on the uniform grid; 1/h_z of the row on a stretched one (the z
 // slot then collects (|u_z| + c)/h_z, which dt divides into 1)
+// h2: the row's diff_h2 (dt_rule = 1; md collects the minimum of rho h^2)
 __device__ __forceinline__ void out_max(const Coef& c, const N2& o, double z, double izs,
-                                        double& mx, double& mz, bool& bad, bool lane_out) {
+                                        double h2, double& mx, double& mz, double& md,
+                                        bool& bad, bool lane_out) {
   P2 q = prim2(c, o, z);
   double cs = sound(c, q.T);
   double sx = fabs(q.ux) + cs, sz = (fabs(q.uz) + cs) * izs;
   if (lane_out) {
     mx = fmax(mx, sx);
     mz = fmax(mz, sz);
+    if (c.dt_rule) md = fmin(md, o.r * h2);
     if (!(o.r > 0.0) || !(q.T > 0.0) || !(sx < INFINITY) || !(sz < INFINITY)) bad = true;
   }
 }
@@ -126,7 +131,7 @@ struct Z2 {
   N2 xp[4];     // X^P
   P2 pp[4];     // primitives of X^P
   N2 FP[2];     // corrector flux (backward inner derivatives)
-  double mx, mz;
+  double mx, mz, md;
   bool bad;
   // stretched grid only: metrics derived from the ring heights and carried
   // one march step (a table read per row would wait behind the row loads)
@@ -283,8 +288,8 @@ __device__ __forceinline__ void z2_out(const Coef& c, Z2& st, bool emit, int o, 
       out.E = 0.5 * (xp.E + xc.E) + (Dc.E - Dm.E);
     }
     if (FUSE)
-      out_max(c, out, st.zz[Z::c3], STR ? fmax(st.ihf1, st.ihf2) : 1.0, st.mx, st.mz, st.bad,
-              L.out);
+      out_max(c, out, st.zz[Z::c3], STR ? fmax(st.ihf1, st.ihf2) : 1.0,
+              c.dt_rule ? diff_h2(c, o) : 0.0, st.mx, st.mz, st.md, st.bad, L.out);
     if (L.out) store2(c, Y, o, L.col, out);
   }
   st.Dp = Dc;
@@ -355,8 +360,8 @@ __device__ __forceinline__ void z2_iter(const Coef& c, Z2& st, int f, int fs, in
       out = N2{rho, 0.0, 0.0, rho * (c.cv * c.Tt + c.g * st.zz[Z::c3])};
     }
     if (FUSE)
-      out_max(c, out, st.zz[Z::c3], STR ? (o == 0 ? st.ihf1 : st.ihf2) : 1.0, st.mx, st.mz,
-              st.bad, L.out);
+      out_max(c, out, st.zz[Z::c3], STR ? (o == 0 ? st.ihf1 : st.ihf2) : 1.0,
+              c.dt_rule ? diff_h2(c, o) : 0.0, st.mx, st.mz, st.md, st.bad, L.out);
     if (L.out) store2(c, Y, o, L.col, out);
   }
   if (STR) {
@@ -380,6 +385,7 @@ __device__ __forceinline__ void z2_wave(const Coef& c, Shared* sh, const double*
   Z2 st;
   st.mx = 0.0;
   st.mz = 0.0;
+  st.md = INFINITY;
   st.bad = false;
   st.Dp = N2{0.0, 0.0, 0.0, 0.0};
   st.ihf1 = st.ihf2 = st.iw1 = 0.0;
@@ -402,7 +408,7 @@ __device__ __forceinline__ void z2_wave(const Coef& c, Shared* sh, const double*
     z2_iter<2, FUSE, STR>(c, st, fb + 2, fs, fe, k0, k1, L, zr, X, Y, tau, lz);
     z2_iter<3, FUSE, STR>(c, st, fb + 3, fs, fe, k0, k1, L, zr, X, Y, tau, lz);
   }
-  if (FUSE) fold_max(sh, slot, st.mx, st.mz, st.bad);
+  if (FUSE) fold_max(c, sh, slot, st.mx, st.mz, st.md, st.bad);
 }
 
 template <bool FUSE, bool STR>
@@ -432,7 +438,7 @@ struct X2 {
   P2 pn[4];      // p filled on use
   N2 xp[4];
   P2 pp[4];
-  double mx, mz;
+  double mx, mz, md;
   bool bad;
   double icen1;  // stretched grid: 1/(z_k+1 - z_k-1) of row f-2, carried
 };
@@ -541,7 +547,8 @@ __device__ __forceinline__ void x2_iter(const Coef& c, X2& st, int f, int fs, in
         const double hu = st.zz[Z::c1] - st.zz[Z::c2], hd = st.zz[Z::c2] - st.zz[Z::c3];
         izs = frcp(r == 0 ? hu : r == M ? hd : fmin(hu, hd));
       }
-      out_max(c, out, st.zz[Z::c2], izs, st.mx, st.mz, st.bad, L.out);
+      out_max(c, out, st.zz[Z::c2], izs, c.dt_rule ? diff_h2(c, r) : 0.0, st.mx, st.mz,
+              st.md, st.bad, L.out);
     }
     if (L.out) store2(c, Y, r, L.col, out);
   }
@@ -561,6 +568,7 @@ __device__ __forceinline__ void x2_wave(const Coef& c, Shared* sh, const double*
   X2 st;
   st.mx = 0.0;
   st.mz = 0.0;
+  st.md = INFINITY;
   st.bad = false;
   st.icen1 = 0.0;
   const int fs = max(0, k0 - 2);
@@ -577,7 +585,7 @@ __device__ __forceinline__ void x2_wave(const Coef& c, Shared* sh, const double*
     x2_iter<2, FUSE, STR>(c, st, fb + 2, fs, fe, k0, k1, L, zr, X, Y, lx);
     x2_iter<3, FUSE, STR>(c, st, fb + 3, fs, fe, k0, k1, L, zr, X, Y, lx);
   }
-  if (FUSE) fold_max(sh, slot, st.mx, st.mz, st.bad);
+  if (FUSE) fold_max(c, sh, slot, st.mx, st.mz, st.md, st.bad);
 }
 
 template <bool FUSE, bool STR>

@@ -195,13 +195,15 @@ __device__ __forceinline__ void exchange(double (&buf)[2][kPB * kLW], const Lane
 
 struct Acc3 {
   double s[3];
+  double md;   // min of rho h^2 (dt_rule = 1)
   bool bad;
 };
 
 // izs: 1 on the uniform grid; 1/h_z of the node on a stretched one (the z
 // entry then collects (|u_z| + c)/h_z, which dt divides into 1)
+// h2: the node's diff_h2 (dt_rule = 1)
 __device__ __forceinline__ void acc_out(const Coef& c, const N3& o, double z, double izs,
-                                        Acc3& a, bool on) {
+                                        double h2, Acc3& a, bool on) {
   P3 q = prim3(c, o, z);
   double cs = sound(c, q.T);
   double s0 = fabs(q.u[0]) + cs, s1 = fabs(q.u[1]) + cs, s2 = (fabs(q.u[2]) + cs) * izs;
@@ -209,19 +211,22 @@ __device__ __forceinline__ void acc_out(const Coef& c, const N3& o, double z, do
     a.s[0] = fmax(a.s[0], s0);
     a.s[1] = fmax(a.s[1], s1);
     a.s[2] = fmax(a.s[2], s2);
+    if (c.dt_rule) a.md = fmin(a.md, o.r * h2);
     if (!(o.r > 0.0) || !(q.T > 0.0) || !(s0 < INFINITY) || !(s1 < INFINITY) ||
         !(s2 < INFINITY))
       a.bad = true;
   }
 }
 
-__device__ __forceinline__ void fold3(Shared* sh, int slot, Acc3& a) {
+__device__ __forceinline__ void fold3(const Coef& c, Shared* sh, int slot, Acc3& a) {
   double m0 = wave_max(a.s[0]), m1 = wave_max(a.s[1]), m2 = wave_max(a.s[2]);
+  const double md = c.dt_rule ? wave_min(a.md) : 0.0;
   unsigned long long anybad = __ballot(a.bad);
   if ((threadIdx.x & 63) == 0) {
     atomicMax(&sh->smax[slot ^ 1][max_part()][0], d2u(m0));
     atomicMax(&sh->smax[slot ^ 1][max_part()][1], d2u(m1));
     atomicMax(&sh->smax[slot ^ 1][max_part()][2], d2u(m2));
+    if (c.dt_rule) fold_rho_h2(sh, slot ^ 1, max_part(), md);
     if (anybad) atomicOr(&sh->flags, 1u);
   }
 }
@@ -281,7 +286,7 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
                                         const double* __restrict__ zr,
                                         const double* __restrict__ X, double* __restrict__ Y,
                                         double tau, double lm, double zb, int flo, int fhi,
-                                        double ihb2, double izw) {
+                                        double ihb2, double izw, double h2b) {
   constexpr int B = (AX == 2) ? 1 : 2;   // axis of the waves
   constexpr bool P = (AX == 2) && PL;    // plate rows possible in this chunk
   constexpr bool SZ = STR && AX == 2;    // stretched march along z
@@ -471,7 +476,9 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
         for (int g = 0; g < 3; ++g) out.m[g] = 0.5 * (xp.m[g] + xc.m[g]) + (Dc.m[g] - Dm.m[g]);
         out.E = 0.5 * (xp.E + xc.E) + (Dc.E - Dm.E);
       }
-      if (FUSE) acc_out(c, out, z_o, SZ ? fmax(st.ihf1, st.ihf2) : izw, st.acc, L.out);
+      if (FUSE)
+        acc_out(c, out, z_o, SZ ? fmax(st.ihf1, st.ihf2) : izw,
+                c.dt_rule ? ((AX == 2) ? diff_h2(c, o) : h2b) : 0.0, st.acc, L.out);
       if (L.out) stnode(o, out);
     }
     st.Dp = Dc;
@@ -489,7 +496,8 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
       out = N3{rho, {0.0, 0.0, 0.0}, rho * (c.cv * c.Tt + c.g * z_o)};
     }
     if (FUSE)
-      acc_out(c, out, z_o, SZ ? (bwall ? izw : o == 0 ? st.ihf1 : st.ihf2) : izw, st.acc, L.out);
+      acc_out(c, out, z_o, SZ ? (bwall ? izw : o == 0 ? st.ihf1 : st.ihf2) : izw,
+              c.dt_rule ? ((AX == 2) ? diff_h2(c, o) : h2b) : 0.0, st.acc, L.out);
     if (L.out) stnode(o, out);
   }
   if (SZ) {
@@ -539,6 +547,7 @@ __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const
   const double lm = tau * ((AX == 2) ? c.ihz : c.ihy);
   MF st;
   st.acc.s[0] = st.acc.s[1] = st.acc.s[2] = 0.0;
+  st.acc.md = INFINITY;
   st.acc.bad = false;
   st.Dp = N3{0.0, {0.0, 0.0, 0.0}, 0.0};
   const int fs = (AX == 2) ? max(0, m0 - 2) : m0 - 2;
@@ -553,6 +562,8 @@ __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const
   const double zb = (AX == 1) ? zr[bload] : 0.0;
   const unsigned lob = (AX == 2) ? (unsigned)(bidx * c.nx + L.col) * 8u : 0u;
   const long long lnode = (AX == 1) ? (long long)bload * c.plane + L.col : 0;
+  // L_y: h^2 of the lane's plane for the diffusion part of dt (dt_rule = 1)
+  const double h2b = (AX == 1 && c.dt_rule) ? diff_h2(c, bload) : 0.0;
   // the centred span across the waves (y for L_z; z for L_y, which on a
   // stretched grid is the wave's plane's own) and, for L_y's dt entry, the
   // plane's narrowest face
@@ -575,12 +586,12 @@ __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const
   // heads before them copy this defined, unused row
   st.pf[0] = st.pf[1] = N3{1.0, {0.0, 0.0, 0.0}, 1.0};
   for (int fb = (fs - 2) & ~3; fb <= fe; fb += 4) {
-    mf_iter<AX, 0, FUSE, PL, STR>(c, st, fb + 0, fs, fe, m0, m1, L, lob, lnode, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, zb, flo, fhi, ihb2, izw);
-    mf_iter<AX, 1, FUSE, PL, STR>(c, st, fb + 1, fs, fe, m0, m1, L, lob, lnode, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, zb, flo, fhi, ihb2, izw);
-    mf_iter<AX, 2, FUSE, PL, STR>(c, st, fb + 2, fs, fe, m0, m1, L, lob, lnode, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, zb, flo, fhi, ihb2, izw);
-    mf_iter<AX, 3, FUSE, PL, STR>(c, st, fb + 3, fs, fe, m0, m1, L, lob, lnode, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, zb, flo, fhi, ihb2, izw);
+    mf_iter<AX, 0, FUSE, PL, STR>(c, st, fb + 0, fs, fe, m0, m1, L, lob, lnode, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, zb, flo, fhi, ihb2, izw, h2b);
+    mf_iter<AX, 1, FUSE, PL, STR>(c, st, fb + 1, fs, fe, m0, m1, L, lob, lnode, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, zb, flo, fhi, ihb2, izw, h2b);
+    mf_iter<AX, 2, FUSE, PL, STR>(c, st, fb + 2, fs, fe, m0, m1, L, lob, lnode, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, zb, flo, fhi, ihb2, izw, h2b);
+    mf_iter<AX, 3, FUSE, PL, STR>(c, st, fb + 3, fs, fe, m0, m1, L, lob, lnode, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, zb, flo, fhi, ihb2, izw, h2b);
   }
-  if (FUSE) fold3(sh, slot, st.acc);
+  if (FUSE) fold3(c, sh, slot, st.acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -710,7 +721,8 @@ __device__ __forceinline__ void lf_iter(const Coef& c, LF& st, int f, int fs, in
         const double hu = st.zz[c1] - st.zz[c2], hd = st.zz[c2] - st.zz[c3];
         izs = frcp(r == 0 ? hu : r == M ? hd : fmin(hu, hd));
       }
-      acc_out(c, out, STR ? st.zz[c2] : zrow(r, M), izs, st.acc, L.out);
+      acc_out(c, out, STR ? st.zz[c2] : zrow(r, M), izs, c.dt_rule ? diff_h2(c, r) : 0.0,
+              st.acc, L.out);
     }
     if (L.out) store3o(c, Y, (long long)r * c.plane, lob, out);
   }
@@ -744,6 +756,7 @@ __global__ __launch_bounds__(64 * kNW) void sweep_lf3d(Coef c, Shared* sh, const
   const double lx = 0.5 * dt * c.ihx;
   LF st;
   st.acc.s[0] = st.acc.s[1] = st.acc.s[2] = 0.0;
+  st.acc.md = INFINITY;
   st.acc.bad = false;
   const int fs = max(0, k0 - 2);
   const int fe = k1 + 1;
@@ -759,7 +772,7 @@ __global__ __launch_bounds__(64 * kNW) void sweep_lf3d(Coef c, Shared* sh, const
     lf_iter<2, FUSE, STR>(c, st, fb + 2, fs, fe, k0, k1, L, lob, owave, xa, xb, zr, X, Y, lx, flo, fhi);
     lf_iter<3, FUSE, STR>(c, st, fb + 3, fs, fe, k0, k1, L, lob, owave, xa, xb, zr, X, Y, lx, flo, fhi);
   }
-  if (FUSE) fold3(sh, slot, st.acc);
+  if (FUSE) fold3(c, sh, slot, st.acc);
 }
 
 // ---------------------------------------------------------------------------

@@ -126,6 +126,7 @@ __global__ void set_scalars_kernel(Shared* sh, double time, int clear_flags) {
 __global__ __launch_bounds__(256) void dt_kernel(Coef c, Shared* sh, const double* zr,
                                                  int slot, const double* __restrict__ X) {
   double m[3] = {0.0, 0.0, 0.0};
+  double md = INFINITY;      // min of rho h^2 (dt_rule = 1)
   bool bad = false;
   const int fz = c.nf - 2;   // rho u_z slot
   for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < c.cnt;
@@ -144,16 +145,19 @@ __global__ __launch_bounds__(256) void dt_kernel(Coef c, Shared* sh, const doubl
     m[0] = fmax(m[0], sx);
     m[1] = fmax(m[1], sy);
     m[2] = fmax(m[2], sz);
+    if (c.dt_rule) md = fmin(md, rho * diff_h2(c, k));
     if (!(rho > 0.0) || !(T > 0.0) || !(sx < INFINITY) || !(sy < INFINITY) ||
         !(sz < INFINITY))
       bad = true;
   }
   for (int a = 0; a < 3; ++a) m[a] = wave_max(m[a]);
+  if (c.dt_rule) md = wave_min(md);
   unsigned long long anybad = __ballot(bad);
   if ((threadIdx.x & 63) == 0) {
     atomicMax(&sh->smax[slot][max_part()][0], d2u(m[0]));
     if (c.ndim == 3) atomicMax(&sh->smax[slot][max_part()][1], d2u(m[1]));
     atomicMax(&sh->smax[slot][max_part()][2], d2u(m[2]));
+    if (c.dt_rule) fold_rho_h2(sh, slot, max_part(), md);
     if (anybad) atomicOr(&sh->flags, 1u);
   }
 }
@@ -412,12 +416,15 @@ int validate_c(const mtvd_params* p, const char** why) {
   if (p->sweep_order != 0 && p->sweep_order != 1) { *why = "sweep_order must be 0 or 1"; return MTVD_EINVAL; }
   if (p->tvd_on != 0 && p->tvd_on != 1) { *why = "tvd_on must be 0 or 1"; return MTVD_EINVAL; }
   if (p->wall_order != 1 && p->wall_order != 2) { *why = "wall_order must be 1 or 2"; return MTVD_EINVAL; }
+  if (p->dt_rule != 0 && p->dt_rule != 1) { *why = "dt_rule must be 0 or 1"; return MTVD_EINVAL; }
   if (!(p->stretch >= 0.0) || !(p->stretch <= 10.0)) { *why = "stretch must lie in [0, 10]"; return MTVD_EINVAL; }
   if (p->stretch > 0.0 && p->ndim == 3 && p->nz > 2048) {
     *why = "a stretched 3D grid has at most 2048 rows";   // the L_z kernels keep the heights in LDS
     return MTVD_EINVAL;
   }
   if (!(p->cfl > 0.0) || !(p->cfl <= 1.0)) { *why = "cfl must lie in (0, 1]"; return MTVD_ESTABILITY; }
+  // dt_rule = 1 keeps every diffusion number at most cfl/2 by itself
+  if (p->dt_rule == 1) return MTVD_OK;
   // diffusion number of the initial state (the acoustic limit sets dt):
   // max(mu(2+|lambda|), K/c_v) * tau / (rho_min h_min^2) <= 1/2
   double hx = p->aspect / p->nx, hz = 1.0 / (p->nz - 1);
@@ -490,6 +497,10 @@ Coef make_coef(const mtvd_params* p) {
   c.tvd_on = p->tvd_on;
   c.wall_order = p->wall_order;
   c.dt_mode = p->dt_mode;
+  c.dt_rule = p->dt_rule;
+  c.kappa = fmax(c.mu * (2.0 + fabs(c.lam)), c.K / c.cv);
+  c.hmh = (p->ndim == 3) ? fmin(c.hx, c.hy) : c.hx;
+  c.hm2 = fmin(c.hmh, c.hz) * fmin(c.hmh, c.hz);
   c.stretched = p->stretch > 0.0;
   c.zm = nullptr;   // set when the workspace is bound
   return c;
@@ -597,6 +608,24 @@ void host_slot_max(const Shared& hs, int slot, double S[3]) {
     for (int q = 0; q < kMaxParts; ++q) m = hs.smax[slot][q][a] > m ? hs.smax[slot][q][a] : m;
     memcpy(&S[a], &m, sizeof(double));
   }
+}
+
+// dt of the step a slot's maxima give, the same arithmetic as step_dt on
+// the device (entry 3: the complement of the minimum of rho h^2)
+double host_dt(const Coef& c, const Shared& hs, int slot) {
+  double S[3];
+  host_slot_max(hs, slot, S);
+  double m = fmin(c.hx / S[0], (c.stretched ? 1.0 : c.hz) / S[2]);
+  if (c.ndim == 3) m = fmin(m, c.hy / S[1]);
+  if (c.dt_rule) {
+    unsigned long long b = 0ull;
+    for (int q = 0; q < kMaxParts; ++q) b = hs.smax[slot][q][3] > b ? hs.smax[slot][q][3] : b;
+    b = ~b;
+    double rh2;
+    memcpy(&rh2, &b, sizeof(double));
+    m = fmin(m, rh2 / c.kappa);
+  }
+  return c.cfl * m;
 }
 
 int read_flags(mtvd_ctx* c, unsigned int* flags) {
@@ -807,12 +836,7 @@ int mtvd_diagnostics(mtvd_ctx* c, mtvd_diag* out) {
   if (c->p.dt_mode == 1) {
     out->dt = hs.dt_frozen;
   } else {
-    // the same arithmetic as step_dt on the device
-    double S[3];
-    host_slot_max(hs, c->slot, S);
-    double m = fmin(c->c.hx / S[0], (c->c.stretched ? 1.0 : c->c.hz) / S[2]);
-    if (c->c.ndim == 3) m = fmin(m, c->c.hy / S[1]);
-    out->dt = c->c.cfl * m;
+    out->dt = host_dt(c->c, hs, c->slot);
   }
   out->mass = host[0];
   out->kinetic = host[1];
@@ -1341,9 +1365,7 @@ int mtvd_batch_diagnostics(mtvd_batch* b, int32_t box, mtvd_diag* out) {
   if (b->p[box].dt_mode == 1) {
     out->dt = hs.dt_frozen;
   } else {
-    double S[3];
-    host_slot_max(hs, b->slot, S);
-    out->dt = c.cfl * fmin(c.hx / S[0], c.hz / S[2]);
+    out->dt = host_dt(c, hs, b->slot);
   }
   out->mass = host[0];
   out->kinetic = host[1];

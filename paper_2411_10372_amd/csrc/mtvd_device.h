@@ -30,6 +30,12 @@ struct Coef {
   double noise_amp;
   uint64_t seed;
   int limiter_form, tvd_on, wall_order, dt_mode;
+  // dt_rule = 1: dt also keeps every node's diffusion number at most cfl/2,
+  // dt <= cfl rho h^2 / kappa, kappa = max(mu (2 + |lambda|), K/c_v), h the
+  // node's smallest spacing (hm2 = h^2 on a uniform grid; hmh the smaller
+  // horizontal spacing)
+  int dt_rule;
+  double kappa, hm2, hmh;
   // tanh-stretched z grid: per-row metric table of kZM doubles per row
   // (see the kZM_* slots), device memory in the workspace; null when uniform
   int stretched;
@@ -121,6 +127,16 @@ __device__ __forceinline__ double slot_max(const Shared* sh, int slot, int a) {
   return u2d(m);
 }
 
+// Slot entry 3 (dt_rule = 1) holds the minimum over nodes of rho h^2 as
+// the bitwise complement of its bit pattern: complements of positive
+// doubles order in reverse, so the same atomic max that folds the other
+// entries folds this minimum (and a cleared entry, 0, lies below them all).
+__device__ __forceinline__ double slot_min_rho_h2(const Shared* sh, int slot) {
+  unsigned long long m = 0ull;
+  for (int q = 0; q < kMaxParts; ++q) m = max(m, sh->smax[slot][q][3]);
+  return u2d(~m);
+}
+
 // STR: a stretched z grid, whose z slot holds max (|u_z| + c)/h_z,k already
 template <bool STR = false>
 __device__ __forceinline__ double step_dt(const Coef& c, const Shared* sh, int slot) {
@@ -129,7 +145,22 @@ __device__ __forceinline__ double step_dt(const Coef& c, const Shared* sh, int s
   double mz = (STR ? 1.0 : c.hz) / slot_max(sh, slot, 2);
   m = fmin(m, mz);
   if (c.ndim == 3) m = fmin(m, c.hy / slot_max(sh, slot, 1));
+  // the minimum over nodes of rho h^2 / kappa is (min rho h^2) / kappa:
+  // division by the positive constant kappa is monotone
+  if (c.dt_rule) m = fmin(m, slot_min_rho_h2(sh, slot) / c.kappa);
   return c.cfl * m;
+}
+
+// h^2 of a node of row k for the diffusion part of dt: its smallest
+// spacing, on a stretched grid the narrower of its z faces (a plate node
+// has one)
+__device__ __forceinline__ double diff_h2(const Coef& c, int k) {
+  if (!c.stretched) return c.hm2;
+  const double hz = (k == 0)      ? c.zm[kZM_HF]
+                    : (k == c.M) ? c.zm[(c.M - 1) * kZM + kZM_HF]
+                                 : fmin(c.zm[(k - 1) * kZM + kZM_HF], c.zm[k * kZM + kZM_HF]);
+  const double h = fmin(c.hmh, hz);
+  return h * h;
 }
 
 // ---- 2D node values -------------------------------------------------------
@@ -253,11 +284,21 @@ __device__ __forceinline__ double dot2(const N2& a, const N2& b) {
   return ((a.r * b.r + a.mx * b.mx) + a.mz * b.mz) + a.E * b.E;
 }
 
-// wave-wide max (64 lanes)
+// wave-wide max and min (64 lanes)
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// fold the minimum of rho h^2 into slot entry 3 of part `part` (one lane)
+__device__ __forceinline__ void fold_rho_h2(Shared* sh, int slot, int part, double md) {
+  atomicMax(&sh->smax[slot][part][3], ~d2u(md));
 }
 
 }  // namespace mtvd
