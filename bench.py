@@ -37,7 +37,8 @@ def log(*a):
 # the files a sweep kernel's binary depends on (the build script holds its
 # compiler flags)
 KERNEL_SOURCES = {2: ("mtvd_2d.hip", "mtvd_device.h", "../build.py"),
-                  3: ("mtvd_3d.hip", "mtvd_device.h", "../build.py")}
+                  3: ("mtvd_3d.h", "mtvd_3d_x.hip", "mtvd_3d_y.hip", "mtvd_3d_z.hip",
+                      "mtvd_device.h", "../build.py")}
 
 
 def source_hash(files=None) -> str:
@@ -210,7 +211,15 @@ def bench_batch(args):
     b = mtvd.Batch(ps, device="cuda:0")
     b.init_state()
     t0 = time.perf_counter()
-    b.autotune(trial_steps=4)
+    if args.batch_rows:
+        # rows per wave given per box size (as a previous run's autotuner
+        # chose them): no trial launches, e.g. inside a profiler's window
+        rows = json.loads(args.batch_rows)
+        for i, p in enumerate(ps):
+            rx, rz = rows[f"{p.nx}x{p.nz}"]
+            b.set_tiling(i, rx, rz)
+    else:
+        b.autotune(trial_steps=4)
     t_tune = time.perf_counter() - t0
     b.step(W)
     torch.cuda.synchronize()
@@ -346,6 +355,9 @@ def main():
                     help="also run a plain 256 MiB device copy (reference for HBM counters)")
     ap.add_argument("--rows", type=int, nargs=2, default=None,
                     help="rows per wave for the x and z sweeps (default: library choice)")
+    ap.add_argument("--batch-rows", default=None,
+                    help='batch: rows per wave per box size as JSON, e.g. '
+                         '\'{"128x32": [4, 32], ...}\' (default: run the autotuner)')
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -251,11 +251,7 @@ int mtvd_sync(mtvd_ctx* c);
 
 /* Rows per wave along the march for the sweep kernels (0 = library
  * default).  It changes the launch shape only: results are identical bit
- * for bit for any value >= 1, except the 3D L_z operator, whose chunks that
- * cannot reach a plate run a separately compiled copy of the same
- * arithmetic (no plate code, no register spills) in which the compiler may
- * fuse a few multiply-adds differently: there results agree to rounding
- * (a few ulps). */
+ * for bit for any value >= 1. */
 int mtvd_set_tiling(mtvd_ctx* c, int32_t rows_x, int32_t rows_z);
 
 /* Per-launch timing of the sweep kernels with HIP events recorded on the

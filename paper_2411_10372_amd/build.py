@@ -27,13 +27,27 @@ FLAGS = [
 # march kernels 1.4% with iterative-minreg; the rest keep the default.
 SCHED = {
     "mtvd_2d.hip": "max-ilp",
-    "mtvd_3d.hip": "iterative-minreg",
+    "mtvd_3d_x.hip": "iterative-minreg",
+    "mtvd_3d_y.hip": "iterative-minreg",
+    "mtvd_3d_z.hip": "iterative-minreg",
+}
+
+# The 3D L_z operator runs its plate rows and the rows between in two
+# separately compiled copies of the same arithmetic; with multiply-adds
+# fused where the compiler likes, the copies rounded differently, so a
+# node's last bits depended on which copy its chunk ran (on the rows per
+# wave).  Without fusion every expression rounds as written in both copies.
+# (L_x and L_y have one copy each and keep their fused multiply-adds.)
+EXTRA = {
+    "mtvd_3d_z.hip": ["-ffp-contract=off"],
 }
 
 
 def flags_for(src: str) -> list:
-    st = SCHED.get(os.path.basename(src))
-    return FLAGS + (["-mllvm", f"-amdgpu-sched-strategy={st}"] if st else [])
+    name = os.path.basename(src)
+    st = SCHED.get(name)
+    return (FLAGS + (["-mllvm", f"-amdgpu-sched-strategy={st}"] if st else [])
+            + EXTRA.get(name, []))
 
 
 def sources():

@@ -1,5 +1,7 @@
-// mtvd_3d.hip -- fused predictor/corrector/TVD kernels of the directional
-// operators L_x, L_y, L_z in 3D (Sec. 3.1 of arXiv:2411.10372).
+// mtvd_3d.h -- fused predictor/corrector/TVD kernels of the directional
+// operators L_x, L_y, L_z in 3D (Sec. 3.1 of arXiv:2411.10372), as
+// templates; mtvd_3d_x.hip, mtvd_3d_y.hip and mtvd_3d_z.hip instantiate
+// and launch one operator each (the L_z file without fused multiply-adds).
 //
 // Launch shape: a block of kNW = 8 waves.  Lanes run along x (60 output
 // columns per wave plus two halo columns each side, exchanged with DPP wave
@@ -14,6 +16,8 @@
 //   L_x: flux across lanes, march z, waves along y
 // Every kernel reads and writes each field of each node once (5 fields x 8 B
 // in and out); halo re-reads hit in L2.
+#pragma once
+
 #include "mtvd_device.h"
 #include "mtvd_launch.h"
 
@@ -202,6 +206,8 @@ struct Acc3 {
 // izs: 1 on the uniform grid; 1/h_z of the node on a stretched one (the z
 // entry then collects (|u_z| + c)/h_z, which dt divides into 1)
 // h2: the node's diff_h2 (dt_rule = 1)
+// DIFF: also the minimum of rho h^2 (dt_rule = 1)
+template <bool DIFF>
 __device__ __forceinline__ void acc_out(const Coef& c, const N3& o, double z, double izs,
                                         double h2, Acc3& a, bool on) {
   P3 q = prim3(c, o, z);
@@ -211,22 +217,23 @@ __device__ __forceinline__ void acc_out(const Coef& c, const N3& o, double z, do
     a.s[0] = fmax(a.s[0], s0);
     a.s[1] = fmax(a.s[1], s1);
     a.s[2] = fmax(a.s[2], s2);
-    if (c.dt_rule) a.md = fmin(a.md, o.r * h2);
+    if (DIFF) a.md = fmin(a.md, o.r * h2);
     if (!(o.r > 0.0) || !(q.T > 0.0) || !(s0 < INFINITY) || !(s1 < INFINITY) ||
         !(s2 < INFINITY))
       a.bad = true;
   }
 }
 
-__device__ __forceinline__ void fold3(const Coef& c, Shared* sh, int slot, Acc3& a) {
+template <bool DIFF>
+__device__ __forceinline__ void fold3(Shared* sh, int slot, Acc3& a) {
   double m0 = wave_max(a.s[0]), m1 = wave_max(a.s[1]), m2 = wave_max(a.s[2]);
-  const double md = c.dt_rule ? wave_min(a.md) : 0.0;
+  const double md = DIFF ? wave_min(a.md) : 0.0;
   unsigned long long anybad = __ballot(a.bad);
   if ((threadIdx.x & 63) == 0) {
     atomicMax(&sh->smax[slot ^ 1][max_part()][0], d2u(m0));
     atomicMax(&sh->smax[slot ^ 1][max_part()][1], d2u(m1));
     atomicMax(&sh->smax[slot ^ 1][max_part()][2], d2u(m2));
-    if (c.dt_rule) fold_rho_h2(sh, slot ^ 1, max_part(), md);
+    if (DIFF) fold_rho_h2(sh, slot ^ 1, max_part(), md);
     if (anybad) atomicOr(&sh->flags, 1u);
   }
 }
@@ -271,6 +278,8 @@ struct MF {
 constexpr int kZL3 = 2048;
 __shared__ double zlds[kZL3];
 
+// FO: 0 no fold; 1 fold max(|u_a| + c) of the output into the next step's
+// slot; 2 also the minimum of rho h^2 (dt_rule = 1).
 // PL: the launch's rows may touch a plate (L_z).  The rows between (first
 // output row >= 4, last <= M-4: every stage then works on rows 2..M-4) run
 // a copy compiled without the plate and wall code, whose registers fit
@@ -278,7 +287,7 @@ __shared__ double zlds[kZL3];
 // STR: a stretched z grid.  L_z takes every z spacing from the heights in
 // LDS; L_y (waves along z) gets its wave's centred span and narrowest face
 // in ihb2 and izw.
-template <int AX, int S, bool FUSE, bool PL, bool STR>
+template <int AX, int S, int FO, bool PL, bool STR>
 __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, int fe, int m0,
                                         int m1, const Lane3& L, unsigned lob, long long lnode,
                                         bool bval, bool bwall, bool owave,
@@ -476,9 +485,9 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
         for (int g = 0; g < 3; ++g) out.m[g] = 0.5 * (xp.m[g] + xc.m[g]) + (Dc.m[g] - Dm.m[g]);
         out.E = 0.5 * (xp.E + xc.E) + (Dc.E - Dm.E);
       }
-      if (FUSE)
-        acc_out(c, out, z_o, SZ ? fmax(st.ihf1, st.ihf2) : izw,
-                c.dt_rule ? ((AX == 2) ? diff_h2(c, o) : h2b) : 0.0, st.acc, L.out);
+      if (FO)
+        acc_out<FO == 2>(c, out, z_o, SZ ? fmax(st.ihf1, st.ihf2) : izw,
+                         FO == 2 ? ((AX == 2) ? diff_h2(c, o) : h2b) : 0.0, st.acc, L.out);
       if (L.out) stnode(o, out);
     }
     st.Dp = Dc;
@@ -495,9 +504,9 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
       double rho = st.xp[c3].r;
       out = N3{rho, {0.0, 0.0, 0.0}, rho * (c.cv * c.Tt + c.g * z_o)};
     }
-    if (FUSE)
-      acc_out(c, out, z_o, SZ ? (bwall ? izw : o == 0 ? st.ihf1 : st.ihf2) : izw,
-              c.dt_rule ? ((AX == 2) ? diff_h2(c, o) : h2b) : 0.0, st.acc, L.out);
+    if (FO)
+      acc_out<FO == 2>(c, out, z_o, SZ ? (bwall ? izw : o == 0 ? st.ihf1 : st.ihf2) : izw,
+                       FO == 2 ? ((AX == 2) ? diff_h2(c, o) : h2b) : 0.0, st.acc, L.out);
     if (L.out) stnode(o, out);
   }
   if (SZ) {
@@ -507,7 +516,7 @@ __device__ __forceinline__ void mf_iter(const Coef& c, MF& st, int f, int fs, in
   }
 }
 
-template <int AX, bool FUSE, bool PL, bool STR>
+template <int AX, int FO, bool PL, bool STR>
 __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const double* zr,
                                                        int slot, int first,
                                                        const double* __restrict__ X,
@@ -563,7 +572,7 @@ __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const
   const unsigned lob = (AX == 2) ? (unsigned)(bidx * c.nx + L.col) * 8u : 0u;
   const long long lnode = (AX == 1) ? (long long)bload * c.plane + L.col : 0;
   // L_y: h^2 of the lane's plane for the diffusion part of dt (dt_rule = 1)
-  const double h2b = (AX == 1 && c.dt_rule) ? diff_h2(c, bload) : 0.0;
+  const double h2b = (AX == 1 && FO == 2) ? diff_h2(c, bload) : 0.0;
   // the centred span across the waves (y for L_z; z for L_y, which on a
   // stretched grid is the wave's plane's own) and, for L_y's dt entry, the
   // plane's narrowest face
@@ -586,12 +595,12 @@ __global__ __launch_bounds__(64 * kNW) void sweep_mf3d(Coef c, Shared* sh, const
   // heads before them copy this defined, unused row
   st.pf[0] = st.pf[1] = N3{1.0, {0.0, 0.0, 0.0}, 1.0};
   for (int fb = (fs - 2) & ~3; fb <= fe; fb += 4) {
-    mf_iter<AX, 0, FUSE, PL, STR>(c, st, fb + 0, fs, fe, m0, m1, L, lob, lnode, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, zb, flo, fhi, ihb2, izw, h2b);
-    mf_iter<AX, 1, FUSE, PL, STR>(c, st, fb + 1, fs, fe, m0, m1, L, lob, lnode, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, zb, flo, fhi, ihb2, izw, h2b);
-    mf_iter<AX, 2, FUSE, PL, STR>(c, st, fb + 2, fs, fe, m0, m1, L, lob, lnode, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, zb, flo, fhi, ihb2, izw, h2b);
-    mf_iter<AX, 3, FUSE, PL, STR>(c, st, fb + 3, fs, fe, m0, m1, L, lob, lnode, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, zb, flo, fhi, ihb2, izw, h2b);
+    mf_iter<AX, 0, FO, PL, STR>(c, st, fb + 0, fs, fe, m0, m1, L, lob, lnode, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, zb, flo, fhi, ihb2, izw, h2b);
+    mf_iter<AX, 1, FO, PL, STR>(c, st, fb + 1, fs, fe, m0, m1, L, lob, lnode, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, zb, flo, fhi, ihb2, izw, h2b);
+    mf_iter<AX, 2, FO, PL, STR>(c, st, fb + 2, fs, fe, m0, m1, L, lob, lnode, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, zb, flo, fhi, ihb2, izw, h2b);
+    mf_iter<AX, 3, FO, PL, STR>(c, st, fb + 3, fs, fe, m0, m1, L, lob, lnode, bval, bwall, owave, xa, xb, zr, X, Y, tau, lm, zb, flo, fhi, ihb2, izw, h2b);
   }
-  if (FUSE) fold3(c, sh, slot, st.acc);
+  if (FO) fold3<FO == 2>(sh, slot, st.acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -611,7 +620,7 @@ struct LF {
   double icen1;            // stretched grid: 1/(z_k+1 - z_k-1) of row f-2
 };
 
-template <int S, bool FUSE, bool STR>
+template <int S, int FO, bool STR>
 __device__ __forceinline__ void lf_iter(const Coef& c, LF& st, int f, int fs, int fe, int k0,
                                         int k1, const Lane3& L, unsigned lob,
                                         bool owave, double (&xa)[2][2][kPB * kLW],
@@ -715,21 +724,21 @@ __device__ __forceinline__ void lf_iter(const Coef& c, LF& st, int f, int fs, in
       for (int g = 0; g < 3; ++g) out.m[g] = 0.5 * (xp.m[g] + xc.m[g]) + (D.m[g] - Dm.m[g]);
       out.E = 0.5 * (xp.E + xc.E) + (D.E - Dm.E);
     }
-    if (FUSE) {
+    if (FO) {
       double izs = 1.0;
       if (STR) {   // 1/(narrowest face of row r); one face at a plate
         const double hu = st.zz[c1] - st.zz[c2], hd = st.zz[c2] - st.zz[c3];
         izs = frcp(r == 0 ? hu : r == M ? hd : fmin(hu, hd));
       }
-      acc_out(c, out, STR ? st.zz[c2] : zrow(r, M), izs, c.dt_rule ? diff_h2(c, r) : 0.0,
-              st.acc, L.out);
+      acc_out<FO == 2>(c, out, STR ? st.zz[c2] : zrow(r, M), izs,
+                       FO == 2 ? diff_h2(c, r) : 0.0, st.acc, L.out);
     }
     if (L.out) store3o(c, Y, (long long)r * c.plane, lob, out);
   }
   if (STR) st.icen1 = icen;
 }
 
-template <bool FUSE, bool STR>
+template <int FO, bool STR>
 __global__ __launch_bounds__(64 * kNW) void sweep_lf3d(Coef c, Shared* sh, const double* zr,
                                                        int slot, int first,
                                                        const double* __restrict__ X,
@@ -767,94 +776,26 @@ __global__ __launch_bounds__(64 * kNW) void sweep_lf3d(Coef c, Shared* sh, const
   st.pz[0] = st.pz[1] = 0.0;
   st.icen1 = 0.0;
   for (int fb = (fs - 2) & ~3; fb <= fe; fb += 4) {
-    lf_iter<0, FUSE, STR>(c, st, fb + 0, fs, fe, k0, k1, L, lob, owave, xa, xb, zr, X, Y, lx, flo, fhi);
-    lf_iter<1, FUSE, STR>(c, st, fb + 1, fs, fe, k0, k1, L, lob, owave, xa, xb, zr, X, Y, lx, flo, fhi);
-    lf_iter<2, FUSE, STR>(c, st, fb + 2, fs, fe, k0, k1, L, lob, owave, xa, xb, zr, X, Y, lx, flo, fhi);
-    lf_iter<3, FUSE, STR>(c, st, fb + 3, fs, fe, k0, k1, L, lob, owave, xa, xb, zr, X, Y, lx, flo, fhi);
+    lf_iter<0, FO, STR>(c, st, fb + 0, fs, fe, k0, k1, L, lob, owave, xa, xb, zr, X, Y, lx, flo, fhi);
+    lf_iter<1, FO, STR>(c, st, fb + 1, fs, fe, k0, k1, L, lob, owave, xa, xb, zr, X, Y, lx, flo, fhi);
+    lf_iter<2, FO, STR>(c, st, fb + 2, fs, fe, k0, k1, L, lob, owave, xa, xb, zr, X, Y, lx, flo, fhi);
+    lf_iter<3, FO, STR>(c, st, fb + 3, fs, fe, k0, k1, L, lob, owave, xa, xb, zr, X, Y, lx, flo, fhi);
   }
-  if (FUSE) fold3(c, sh, slot, st.acc);
+  if (FO) fold3<FO == 2>(sh, slot, st.acc);
 }
 
-// ---------------------------------------------------------------------------
+}  // namespace mtvd
 
-hipError_t launch_sweep_3d(int axis, const Coef& c, Shared* sh, const double* zr, int slot,
-                           int first, bool fuse, const double* X, double* Y, int kc,
-                           hipStream_t s) {
-  const int nstrips = (c.nx + kStrip3 - 1) / kStrip3;
-  const int per = kPer;
-  const dim3 block(64 * kNW);
-  // the lane part of an address within a z plane is a 32-bit byte offset
-  if ((unsigned long long)c.plane * sizeof(double) >= (1ull << 32)) return hipErrorInvalidValue;
-  const bool str = c.stretched != 0;   // the copies compiled for a stretched z grid
-  if (axis == 0 || axis == 2) {
-    // waves along y
-    const int nbb = (c.ny + per - 1) / per;
-    const int nch = (c.nz + kc - 1) / kc;
-    const long long nblk = (long long)nstrips * nbb * nch;
-    if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)nblk);
-    if (axis == 0) {
-#define MTVD_LF(F, T) sweep_lf3d<F, T><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nbb)
-      if (str) {
-        if (fuse) MTVD_LF(true, true); else MTVD_LF(false, true);
-      } else {
-        if (fuse) MTVD_LF(true, false); else MTVD_LF(false, false);
-      }
-#undef MTVD_LF
-    } else {
-      // The kPlate rows next to each plate run the copy with the plate and
-      // wall code (its registers spill) in launches of their own; the rows
-      // between (output rows >= 4 and <= M-4, so no stage reaches a plate)
-      // run the copy without it in chunks of kc.  The launches of one
-      // operator are independent (disjoint output rows); only the first one
-      // does the step's bookkeeping (time, dt, the next slot).
-      constexpr int kPlate = 8;
-      int fst = first;
-      auto run = [&](int r0, int r1, int k, bool pl) {
-        if (r1 <= r0) return;
-        const long long nck = (r1 - r0 + k - 1) / k;
-        const dim3 g((unsigned)((long long)nstrips * nbb * nck));
-#define MTVD_MF(F, P, T) sweep_mf3d<2, F, P, T><<<g, block, 0, s>>>(c, sh, zr, slot, fst, X, Y, k, nstrips, nbb, r0, r1)
-        if (str) {
-          if (pl) {
-            if (fuse) MTVD_MF(true, true, true); else MTVD_MF(false, true, true);
-          } else {
-            if (fuse) MTVD_MF(true, false, true); else MTVD_MF(false, false, true);
-          }
-        } else {
-          if (pl) {
-            if (fuse) MTVD_MF(true, true, false); else MTVD_MF(false, true, false);
-          } else {
-            if (fuse) MTVD_MF(true, false, false); else MTVD_MF(false, false, false);
-          }
-        }
-#undef MTVD_MF
-        fst = 0;
-      };
-      if (c.nz > 2 * kPlate) {
-        run(0, kPlate, kPlate, true);
-        run(kPlate, c.nz - kPlate, kc, false);
-        run(c.nz - kPlate, c.nz, kPlate, true);
-      } else {
-        run(0, c.nz, kc, true);
-      }
-    }
-  } else {
-    // march y, waves along z
-    const int nbb = (c.nz + per - 1) / per;
-    const int nch = (c.ny + kc - 1) / kc;
-    const long long nblk = (long long)nstrips * nbb * nch;
-    if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)nblk);
-#define MTVD_MY(F, T) sweep_mf3d<1, F, true, T><<<grid, block, 0, s>>>(c, sh, zr, slot, first, X, Y, kc, nstrips, nbb, 0, c.ny)
-    if (str) {
-      if (fuse) MTVD_MY(true, true); else MTVD_MY(false, true);
-    } else {
-      if (fuse) MTVD_MY(true, false); else MTVD_MY(false, false);
-    }
-#undef MTVD_MY
-  }
-  return hipGetLastError();
-}
+namespace mtvd {
+
+// one directional operator in 3D, per axis (mtvd_3d_x/y/z.hip); fo as FO
+hipError_t launch_sweep_3d_x(const Coef& c, Shared* sh, const double* zr, int slot, int first,
+                             int fo, const double* X, double* Y, int kc, hipStream_t s);
+hipError_t launch_sweep_3d_y(const Coef& c, Shared* sh, const double* zr, int slot, int first,
+                             int fo, const double* X, double* Y, int kc, hipStream_t s);
+hipError_t launch_sweep_3d_z(const Coef& c, Shared* sh, const double* zr, int slot, int first,
+                             int fo, const double* X, double* Y, int kc, hipStream_t s);
+
+inline int strips_3d(int nx) { return (nx + kStrip3 - 1) / kStrip3; }
 
 }  // namespace mtvd

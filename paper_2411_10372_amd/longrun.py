@@ -106,6 +106,8 @@ def main(argv=None) -> int:
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--noise", type=float, default=1e-3)
     ap.add_argument("--limiter-form", type=int, default=0)
+    ap.add_argument("--wall-order", type=int, default=2,
+                    help="z-derivatives in the plate fluxes: 2 one-sided second order, 1 first")
     ap.add_argument("--stretch", type=float, default=0.0,
                     help="tanh z-grid parameter s (0: uniform; 3D: nz <= 2048)")
     ap.add_argument("--t0", type=float, required=True, help="start of the averaging window")
@@ -118,14 +120,14 @@ def main(argv=None) -> int:
     p = Params(ndim=a.ndim, nx=a.nx, ny=(a.ny or a.nx) if a.ndim == 3 else 1, nz=a.nz,
                aspect=a.aspect, gamma=float(Fraction(a.gamma)), Pr=a.Pr, Ra=a.Ra, eps=a.eps,
                D=a.D, seed=a.seed, noise_amp=a.noise, limiter_form=a.limiter_form,
-               stretch=a.stretch)
+               stretch=a.stretch, wall_order=a.wall_order)
     out = time_averages(p, a.t0, a.t1, a.sample_steps, a.wall, a.rtol,
                         progress=lambda d: print(json.dumps(d), file=sys.stderr, flush=True))
     if not a.profiles:
         out.pop("profiles", None)
     out["params"] = {k: getattr(p, k) for k in ("ndim", "nx", "ny", "nz", "aspect", "gamma", "Pr",
                                                  "Ra", "eps", "D", "seed", "noise_amp",
-                                                 "limiter_form", "stretch")}
+                                                 "limiter_form", "stretch", "wall_order")}
     print(json.dumps(out), flush=True)
     return 0
 

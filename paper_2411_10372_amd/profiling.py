@@ -9,10 +9,18 @@ what the same counter reads for a plain device copy of known size (the
 last three ``__amd_rocclr_copyBuffer`` dispatches of the run: ``bench.py
 --copy-ref`` copies 256 MiB three times after everything it times).
 
+``sq``: per-kernel sequencer counters (SQ_*, GRBM_GUI_ACTIVE) of one or
+more ``rocprofv3 --pmc`` runs, summed over each kernel's dispatches, with
+the ratios that say where a wave's time goes: wave-cycles issuing VALU,
+scalar and LDS work, waiting for anything (memory, barriers, dependencies)
+and waiting to be issued.  SQ_WAVE_CYCLES, SQ_WAIT_ANY and
+SQ_WAIT_INST_ANY count quad-cycles, as do the SQ_ACTIVE_INST_* counters.
+
 Usage (paths are the rocprofv3 output directories):
     python -m paper_2411_10372_amd.profiling trace DIR OUT.md "COMMAND"
     python -m paper_2411_10372_amd.profiling pmc FETCH_DIR WRITE_DIR KERNEL \
         WORKLOAD SOURCE_HASH COPY_BYTES OUT.json "COMMANDS" [DISPATCHES_PER_LAUNCH]
+    python -m paper_2411_10372_amd.profiling sq OUT.md SOURCE_HASH "COMMANDS" DIR [DIR ...]
 """
 from __future__ import annotations
 
@@ -102,6 +110,52 @@ def pmc_summary(fetch_dir: str, write_dir: str, kernel: str, workload: str, shas
     return d
 
 
+def sq_summary(dirs, out_md: str, shash: str, commands: str) -> dict:
+    """Sum every counter over each kernel's dispatches (all runs) and write
+    the table of ratios per sweep kernel."""
+    tot: dict = {}
+    ndisp: dict = {}
+    for d in dirs:
+        for r in _counter(d):
+            k = _short(r["Kernel_Name"])
+            tot.setdefault(k, {}).setdefault(r["Counter_Name"], 0.0)
+            tot[k][r["Counter_Name"]] += float(r["Counter_Value"])
+            ndisp.setdefault(k, set()).add((d, r["Dispatch_Id"]))
+    lines = ["# Sequencer counters", "", f"Source hash: `{shash}`", "", "Commands:", "", "```",
+             commands, "```", "",
+             "Per kernel, summed over its dispatches; shares of the waves' lifetime "
+             "(SQ_WAVE_CYCLES):", "",
+             "| kernel | dispatches | waves | VALU insts / wave | SALU insts / wave | "
+             "issuing VALU | issuing SALU | issuing LDS | waiting (any) | waiting to issue |",
+             "|---|---|---|---|---|---|---|---|---|---|"]
+    out = {}
+    for k, c in sorted(tot.items()):
+        if "sweep" not in k and "adj" not in k:
+            continue
+        wc = c.get("SQ_WAVE_CYCLES")
+        w = c.get("SQ_WAVES")
+        if not wc or not w:
+            continue
+
+        def share(n):
+            v = c.get(n)
+            return f"{100.0 * v / wc:.1f} %" if v is not None else "-"
+
+        def per_wave(n):
+            v = c.get(n)
+            return f"{v / w:.0f}" if v is not None else "-"
+
+        lines.append(f"| `{k}` | {len(ndisp[k]) // max(1, len(dirs))} | {w:.0f} | "
+                     f"{per_wave('SQ_INSTS_VALU')} | {per_wave('SQ_INSTS_SALU')} | "
+                     f"{share('SQ_ACTIVE_INST_VALU')} | {share('SQ_ACTIVE_INST_SCA')} | "
+                     f"{share('SQ_ACTIVE_INST_LDS')} | {share('SQ_WAIT_ANY')} | "
+                     f"{share('SQ_WAIT_INST_ANY')} |")
+        out[k] = c
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return out
+
+
 if __name__ == "__main__":
     a = sys.argv[1:]
     if a and a[0] == "trace":
@@ -109,6 +163,8 @@ if __name__ == "__main__":
     elif a and a[0] == "pmc":
         print(json.dumps(pmc_summary(a[1], a[2], a[3], a[4], a[5], int(a[6]), a[7], a[8],
                                      int(a[9]) if len(a) > 9 else 1), indent=1))
+    elif a and a[0] == "sq":
+        print(json.dumps(sq_summary(a[4:], a[1], a[2], a[3]), indent=1))
     else:
         print(__doc__)
         sys.exit(2)

@@ -144,11 +144,10 @@ def test_3d_full_size_one_step_sampled(workload):
 @pytest.mark.parametrize("axis", [0, 1, 2])
 def test_3d_results_do_not_depend_on_the_tiling(axis):
     # rows per wave only change which wave computes a node: one operator
-    # with 4-row chunks and with 32-row chunks (every chunk touches a plate).
-    # L_x and L_y agree bit for bit.  L_z runs the chunks clear of the plates
-    # in a separately compiled copy whose fused multiply-adds can round
-    # differently, so there the two agree to rounding: 1e-15 of each field's
-    # scale (a few ulps, far below the 1e-13 parity bar)
+    # with 4-row chunks and with 32-row chunks (every chunk touches a plate)
+    # agree bit for bit.  L_z runs the chunks clear of the plates in a
+    # separately compiled copy of the same arithmetic, which rounds as
+    # written (no fused multiply-adds) like the plate copy
     po, pg = both(ndim=3, nx=70, ny=24, nz=33, Ra=1e6, seed=4)
     X0 = perturb(oracle.init(po), seed=77, amp=0.03)
     out = []
@@ -159,9 +158,4 @@ def test_3d_results_do_not_depend_on_the_tiling(axis):
         s.sweep(axis)
         out.append(s.get_state())
         s.close()
-    if axis != 2:
-        assert np.array_equal(out[0], out[1]), float(np.max(np.abs(out[0] - out[1])))
-    else:
-        e = parity_error(out[0], out[1], po)
-        _say("tiling3d L_z difference", e)
-        assert e <= 1e-15, e
+    assert np.array_equal(out[0], out[1]), float(np.max(np.abs(out[0] - out[1])))
