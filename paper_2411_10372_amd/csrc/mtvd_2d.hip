@@ -157,14 +157,17 @@ struct ZS {
 //    loads, because a guarded load has to be copied into the loop-carried
 //    ring registers at the guard's end and the copy waits for the load.
 //    Rows outside [first row, M] land in ring slots no stage reads.
+//    The row is clamped to [flo, fhi], the rows the chunk's stages read:
+//    the unrolled march prefetches past both ends of the chunk, and those
+//    loads repeat a row just loaded, which the caches serve.
 template <int S>
-__device__ __forceinline__ void z2_load(const Coef& c, Z2& st, int f, const Cols& L,
-                                        const double* __restrict__ zr,
+__device__ __forceinline__ void z2_load(const Coef& c, Z2& st, int f, int flo, int fhi,
+                                        const Cols& L, const double* __restrict__ zr,
                                         const double* __restrict__ X) {
   using Z = ZS<S>;
   st.x[Z::c0] = st.pf[Z::q0];
   st.zz[Z::c0] = st.pz[Z::q0];
-  const int fp = min(max(f + kPF, 0), c.M);
+  const int fp = min(max(f + kPF, flo), fhi);
   st.pf[Z::q0] = load2(c, X, fp, L.col);
   st.pz[Z::q0] = zr[fp];
   st.pn[Z::c0] = prim2(c, st.x[Z::c0], st.zz[Z::c0]);
@@ -303,7 +306,7 @@ __device__ __forceinline__ void z2_iter(const Coef& c, Z2& st, int f, int fs, in
                                         const double* __restrict__ X,
                                         double* __restrict__ Y, double tau, double lz) {
   using Z = ZS<S>;
-  z2_load<S>(c, st, f, L, zr, X);
+  z2_load<S>(c, st, f, fs, min(c.M, k1 + 1), L, zr, X);
   if (f < fs || f > fe) return;
   const int M = c.M;
   const int r = f - 2;
@@ -446,13 +449,13 @@ struct X2 {
 // The stages of one march step f of L_x (ring slots as for L_z).
 // the head of every step, as z2_load
 template <int S>
-__device__ __forceinline__ void x2_load(const Coef& c, X2& st, int f, const Cols& L,
-                                        const double* __restrict__ zr,
+__device__ __forceinline__ void x2_load(const Coef& c, X2& st, int f, int flo, int fhi,
+                                        const Cols& L, const double* __restrict__ zr,
                                         const double* __restrict__ X) {
   using Z = ZS<S>;
   st.x[Z::c0] = st.pf[Z::q0];
   st.zz[Z::c0] = st.pz[Z::q0];
-  const int fp = min(max(f + kPF, 0), c.M);
+  const int fp = min(max(f + kPF, flo), fhi);
   st.pf[Z::q0] = load2(c, X, fp, L.col);
   st.pz[Z::q0] = zr[fp];
   st.pn[Z::c0] = prim2(c, st.x[Z::c0], st.zz[Z::c0]);
@@ -523,7 +526,7 @@ __device__ __forceinline__ void x2_iter(const Coef& c, X2& st, int f, int fs, in
                                         const double* __restrict__ X,
                                         double* __restrict__ Y, double lx) {
   using Z = ZS<S>;
-  x2_load<S>(c, st, f, L, zr, X);
+  x2_load<S>(c, st, f, fs, min(c.M, k1 + 1), L, zr, X);
   if (f < fs || f > fe) return;
   const int M = c.M;
   const int r1 = f - 1;
