@@ -321,11 +321,16 @@ int mtvd_batch_get_state(mtvd_batch* b, int32_t box, double* host, size_t count)
 int mtvd_batch_set_state(mtvd_batch* b, int32_t box, const double* host, size_t count,
                          double time, int64_t step);
 int mtvd_batch_current(const mtvd_batch* b, int32_t* which);
-/* Rows per wave of one box's operators (0 = library default). */
+/* Rows per wave of one box's operators (0 = library default: for each
+ * operator the smallest bound k >= 4 with which the whole launch -- every
+ * box's column strips times its chunks of at most k rows -- fits the
+ * device's resident waves in one round, each box's rows split into equal
+ * chunks of at most k).  Results do not depend on it. */
 int mtvd_batch_set_tiling(mtvd_batch* b, int32_t box, int32_t rows_x, int32_t rows_z);
-/* Time trial steps of each distinct box size over the candidate rows per
- * wave {4, 8, 16, 32, 64} for L_z and then L_x, keep the fastest for every
- * box of that size, and restore the state, time and dt afterwards.
+/* Time trial steps of the whole batch for each distinct box size over the
+ * candidate rows per wave (the default's and 4, 8, 16, 32, 64) for L_z and
+ * then L_x, keep the fastest for every box of that size, and restore the
+ * state, time and dt afterwards.
  * `scratch` is caller-owned device memory of at least state_bytes +
  * 2048 * nbox bytes.  Synchronises. */
 int mtvd_batch_autotune(mtvd_batch* b, void* scratch, int32_t trial_steps);

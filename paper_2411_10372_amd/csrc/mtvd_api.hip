@@ -980,6 +980,7 @@ struct mtvd_batch {
   std::vector<long long> off;     // state offset of each box (doubles)
   std::vector<int> zoff;          // plate-table offset of each box
   std::vector<int> kcx, kcz;      // rows per wave (0 = default)
+  int kdef_x, kdef_z;             // the default's row bound per operator
   hipStream_t stream;
   hipStream_t cap;                // private stream for graph capture
   int device;
@@ -1012,13 +1013,25 @@ int berr(mtvd_batch* b, int code, const std::string& what) {
       return berr(b, MTVD_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-int batch_rows(const Coef& c, int kc) {
+// The default rows per wave of a batch operator: the smallest bound k >= 4
+// for which the launch -- every box's column strips times its chunks of at
+// most k rows -- fits the device's resident waves in one round (a second,
+// partly filled round would cost as much as a full one), every box's rows
+// split into equal chunks of at most k.  64 at most.
+int batch_default_k(const std::vector<Coef>& cs, int slots) {
+  if (slots <= 0) return 32;
+  for (int k = 4; k < 64; ++k) {
+    long long w = 0;
+    for (const auto& c : cs) w += (long long)strips_2d(c.nx) * ((c.nz + k - 1) / k);
+    if (w <= slots) return k;
+  }
+  return 64;
+}
+
+int batch_rows(const Coef& c, int kc, int kdef) {
   if (kc > 0) return kc;
-  // a single box of a batch fills part of the chip: a quarter of nz, 4..32
-  int r = c.nz / 4;
-  if (r < 4) r = 4;
-  if (r > 32) r = 32;
-  return r;
+  const int n = (c.nz + kdef - 1) / kdef;   // chunks of at most kdef rows
+  return (c.nz + n - 1) / n;
 }
 
 // item capacity: every box at the smallest tiling (4 rows per wave)
@@ -1084,8 +1097,8 @@ int upload_items(mtvd_batch* b) {
     d[i].c = b->c[i];
     d[i].off = b->off[i];
     d[i].zoff = b->zoff[i];
-    d[i].kc_x = batch_rows(b->c[i], b->kcx[i]);
-    d[i].kc_z = batch_rows(b->c[i], b->kcz[i]);
+    d[i].kc_x = batch_rows(b->c[i], b->kcx[i], b->kdef_x);
+    d[i].kc_z = batch_rows(b->c[i], b->kcz[i], b->kdef_z);
     d[i].nstrips = strips_2d(b->c[i].nx);
   }
   for (int i = 1; i < b->nbox; ++i)
@@ -1229,6 +1242,8 @@ int mtvd_batch_create(const mtvd_params* boxes, int32_t nbox, void* hip_stream,
   b->zoff = L.zoff;
   b->kcx.assign(nbox, 0);
   b->kcz.assign(nbox, 0);
+  b->kdef_x = batch_default_k(b->c, wave_slots_2d(0, false));
+  b->kdef_z = batch_default_k(b->c, wave_slots_2d(2, false));
   b->o_sh = L.o_sh;
   b->o_desc = L.o_desc;
   b->o_items = L.o_items;
@@ -1430,8 +1445,8 @@ int mtvd_batch_set_tiling(mtvd_batch* b, int32_t box, int32_t rows_x, int32_t ro
 int mtvd_batch_get_tiling(const mtvd_batch* b, int32_t box, int32_t* rows_x,
                           int32_t* rows_z) {
   if (!b || box < 0 || box >= b->nbox || !rows_x || !rows_z) return MTVD_EINVAL;
-  *rows_x = batch_rows(b->c[box], b->kcx[box]);
-  *rows_z = batch_rows(b->c[box], b->kcz[box]);
+  *rows_x = batch_rows(b->c[box], b->kcx[box], b->kdef_x);
+  *rows_z = batch_rows(b->c[box], b->kcz[box], b->kdef_z);
   return MTVD_OK;
 }
 
@@ -1490,8 +1505,10 @@ int mtvd_batch_autotune(mtvd_batch* b, void* scratch, int32_t trial_steps) {
     for (int axis = 0; axis < 2; ++axis) {   // 0: rows of L_z, 1: rows of L_x
       int bestk = 0;
       float bestt = 1e30f;
-      for (int k : cand) {
-        if (k > b->c[i].nz) continue;
+      const int kd = batch_rows(b->c[i], 0, axis == 0 ? b->kdef_z : b->kdef_x);
+      for (int ci = -1; ci < 5; ++ci) {
+        const int k = ci < 0 ? kd : cand[ci];
+        if (k > b->c[i].nz || (ci >= 0 && k == kd)) continue;
         for (int j : same) (axis == 0 ? b->kcz[j] : b->kcx[j]) = k;
         float t;
         int rc = trial(&t);
