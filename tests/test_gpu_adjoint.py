@@ -303,3 +303,9 @@ def test_c4_central_differences_within_the_kink_bound():
     _say("C4 max |fd - adjoint| / |g|", max(errs))
     _say("C4 per-direction |fd - adjoint| / |adjoint|", " ".join(f"{r:.2e}" for r in rels))
     assert max(errs) <= 1e-4, errs
+    # per direction, relative to the directional derivative itself: over
+    # these 16 seeded directions the kink crossings move the difference
+    # quotients by 3e-4 to 4.6e-2 of g.v (measured on MI355X); the bar is
+    # three times the largest, so a wrong sign or a dropped term in any
+    # direction fails while the kink spread does not
+    assert max(rels) <= 0.15, rels
