@@ -525,16 +525,13 @@ int default_rows_for(const Coef& cf, int slots, int axis) {
     if (kc < 2) kc = 2;
     if (kc > 64) kc = 64;
   } else {
-    // 3D, blocks of 8 waves (L_x and L_z march z, L_y marches y): L_x the
-    // whole marched extent up to 256 rows (no halo rows re-read), L_y half
-    // of it up to 128, L_z a quarter up to 48 (its plate rows run in
-    // launches of their own).  Measured at 1024x1024x256 over 32-256 rows:
-    // L_x fastest at 256, L_y at 128, L_z at 48; uneven splits (160, 192
-    // rows) are slow.
+    // 3D, blocks of 8 waves (L_x and L_z march z, L_y marches y): L_x and
+    // L_y half the marched extent up to 128 rows, L_z a quarter up to 48
+    // (its plate rows run in launches of their own).  Measured at
+    // 1024x1024x256: L_x fastest at 128 (5% ahead of the whole extent),
+    // L_y at 128, L_z at 48; uneven splits (160, 192 rows) are slow.
     const long long len = (axis == 1) ? cf.ny : cf.nz;
-    if (axis == 0) {
-      kc = len < 256 ? len : 256;
-    } else if (axis == 1) {
+    if (axis == 0 || axis == 1) {
       kc = len / 2 < 128 ? len / 2 : 128;
     } else {
       kc = len / 4 < 48 ? len / 4 : 48;
