@@ -34,11 +34,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# the files a sweep kernel's binary depends on (the build script holds its
-# compiler flags)
-KERNEL_SOURCES = {2: ("mtvd_2d.hip", "mtvd_device.h", "../build.py"),
+# the files a sweep kernel's binary and launch shape depend on (the build
+# script holds its compiler flags, the API source the default rows per wave)
+KERNEL_SOURCES = {2: ("mtvd_2d.hip", "mtvd_device.h", "mtvd_api.hip", "../build.py"),
                   3: ("mtvd_3d.h", "mtvd_3d_x.hip", "mtvd_3d_y.hip", "mtvd_3d_z.hip",
-                      "mtvd_device.h", "../build.py")}
+                      "mtvd_device.h", "mtvd_api.hip", "../build.py")}
 
 
 def source_hash(files=None) -> str:

@@ -526,13 +526,18 @@ int default_rows_for(const Coef& cf, int slots, int axis) {
     if (kc > 64) kc = 64;
   } else {
     // 3D, blocks of 8 waves (L_x and L_z march z, L_y marches y): L_x and
-    // L_y half the marched extent up to 128 rows, L_z a quarter up to 48
-    // (its plate rows run in launches of their own).  Measured at
-    // 1024x1024x256: L_x fastest at 128 (5% ahead of the whole extent),
-    // L_y at 128, L_z at 48; uneven splits (160, 192 rows) are slow.
+    // L_y half the marched extent up to 128 rows; L_z, whose 8 rows next to
+    // each plate run in launches of their own, the rows between in equal
+    // chunks of at most 80 (tall grids) or a quarter of nz (short ones).
+    // Measured at 1024x1024x256: L_x fastest at 128 (5% ahead of the
+    // whole extent), L_y at 128, L_z at 80 (3 x 80 rows; 2% ahead of
+    // 5 x 48, 4-7% ahead of 32 and 64); uneven splits are slow.
     const long long len = (axis == 1) ? cf.ny : cf.nz;
     if (axis == 0 || axis == 1) {
       kc = len / 2 < 128 ? len / 2 : 128;
+    } else if (len >= 128) {
+      const long long mid = len - 16, nch = (mid + 79) / 80;
+      kc = (mid + nch - 1) / nch;
     } else {
       kc = len / 4 < 48 ? len / 4 : 48;
     }
