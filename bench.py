@@ -331,7 +331,7 @@ def bench_adjoint(args):
                    "steps_per_gradient": N, "checkpoint_every": E, "dt": dt},
         "plain_forward_ms": 1e3 * t_plain, "adjoint_forward_ms": 1e3 * t_fwd,
         "adjoint_backward_ms": 1e3 * t_bwd, "backward_over_plain": t_bwd / t_plain,
-        "roofline": {"bound": "hbm", "kernel": "backward pass (all stage kernels)",
+        "roofline": {"bound": "hbm", "kernel": "backward pass (reverse and recompute kernels)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_gradient": bwd_bytes},

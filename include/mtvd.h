@@ -354,11 +354,11 @@ const char* mtvd_batch_last_error(const mtvd_batch* b);
  * The reverse of each directional operator is hand-written stage by stage;
  * at a kink of max/min/abs/phi it takes the branch the forward pass took.
  * Memory: checkpoints every `every` steps; for two intervals the operator
- * inputs (2 x 4 every states) and forward values (2 x 4 every x 13 doubles
- * per node: the backward pass recomputes the next interval, and its
- * operators' forward values, on a second stream of its own, default
- * priority, while it reverses the current one); about 41 doubles per node
- * of stage arrays (mtvd_adj_bytes gives the total).
+ * inputs (2 x 4 every states: the backward pass recomputes the next
+ * interval on a second stream of its own, default priority, while it
+ * reverses the current one); the forward values of two operators (2 x 13
+ * doubles per node); two cotangent states and the mu and K accumulators
+ * (mtvd_adj_bytes gives the total).
  * Restrictions: ndim = 2 and limiter_form = 0 (MTVD_EINVAL otherwise);
  * dt_mode is ignored (dt is always frozen).
  */

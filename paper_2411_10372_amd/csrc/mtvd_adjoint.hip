@@ -1,8 +1,10 @@
 // mtvd_adjoint.hip -- kernels of the reverse pass of a 2D time step with a
-// frozen dt: the four stages of each directional operator's reverse
-// (functions of mtvd_adjoint.h, one kernel per stage), the objective (the mean plate
-// Nusselt number, accumulated over steps), its cotangent, the initial state
-// from a temperature perturbation and the perturbation's cotangent.
+// frozen dt: each directional operator's forward values and its reverse
+// (the functions of mtvd_adjoint.h: one kernel for the forward values, one
+// for the three cotangent stages fused over tiles), the objective (the
+// mean plate Nusselt number, accumulated over steps), its cotangent, the
+// initial state from a temperature perturbation and the perturbation's
+// cotangent.
 //
 // Paper: Tiwari, Sharma & Verma, arXiv:2411.10372: Sec. 3.1 (the operator
 // reversed), Sec. 2 (initial state, mean_Nu).
@@ -17,14 +19,13 @@ using adj::Arr;
 
 namespace {
 
-enum Stage { kFwAll, kRvTc, kRvPred, kRvPrim };
-
 constexpr int kBlk = 256;
 
-// AX: the operator's axis as a compile-time constant, so that every axis
-// test of the stage functions folds away
-template <int ST, int AX>
-__global__ __launch_bounds__(kBlk) void adj_stage(AC c, Arr A, const Shared* sh) {
+// The operator's forward values (fw_all), one thread per node.  AX: the
+// operator's axis as a compile-time constant, so that every axis test of
+// the stage functions folds away.
+template <int AX>
+__global__ __launch_bounds__(kBlk) void adj_fw_kernel(AC c, Arr A, const Shared* sh) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= c.cnt) return;
   c.axis = AX;
@@ -32,12 +33,52 @@ __global__ __launch_bounds__(kBlk) void adj_stage(AC c, Arr A, const Shared* sh)
   c.tau = 0.5 * sh->dt_frozen;
   c.lm = c.tau * c.iha;
   const int i = (int)(t % c.nx), k = (int)(t / c.nx);
-  switch (ST) {
-    case kFwAll: adj::fw_all(c, A, i, k); break;
-    case kRvTc: adj::rv_tc(c, A, i, k); break;
-    case kRvPred: adj::rv_pred(c, A, i, k); break;
-    default: adj::rv_prim(c, A, i, k); break;
+  adj::fw_all(c, A, i, k);
+}
+
+// The reverse of one operator in one kernel: the three cotangent stages
+// over a tile of kTA x kTB output nodes per block, their intermediate
+// values in shared memory (the tiled pass of mtvd_adjoint.h; thread t
+// computes node t of each stage's region).  tiles_b = tiles across the
+// axis; block q < ntiles takes tile (q / tiles_b, q % tiles_b) (along,
+// across).  With AXF >= 0 the blocks from ntiles on fill, for the operator
+// to be reversed next (axis AXF, state F.X), its forward values F.P, F.S,
+// F.XP, F.PP: independent work that keeps the CUs busy while the tiles
+// wait on memory, and leaves those values in the caches for the next
+// launch.  40 KiB of shared memory and at most 168 VGPRs (three waves per
+// SIMD) let three blocks share a CU: 768 blocks at once, more than the
+// ~520 tiles (+ 128 forward-value blocks) of a 512 x 128 grid, which then
+// run in a single round.
+template <int AX, int AXF>
+__global__ __launch_bounds__(adj::kNT, 3) void adj_rev_fused(AC c, Arr A, const Shared* sh,
+                                                              int tiles_b, int ntiles,
+                                                              double nu_a, Arr F) {
+  __shared__ double L[adj::kTileDoubles];
+  c.tau = 0.5 * sh->dt_frozen;
+  if (AXF >= 0 && (int)blockIdx.x >= ntiles) {
+    AC cf = c;
+    cf.axis = AXF;
+    cf.iha = AXF == 0 ? c.ihx : c.ihz;
+    cf.lm = cf.tau * cf.iha;
+    const long long stride = (long long)(gridDim.x - ntiles) * adj::kNT;
+    for (long long n = (long long)(blockIdx.x - ntiles) * adj::kNT + threadIdx.x; n < c.cnt;
+         n += stride)
+      adj::fw_all(cf, F, (int)(n % c.nx), (int)(n / c.nx));
+    return;
   }
+  c.axis = AX;
+  c.iha = AX == 0 ? c.ihx : c.ihz;
+  c.lm = c.tau * c.iha;
+  const int a0 = (int)(blockIdx.x / tiles_b) * adj::kTA, b0 = (int)(blockIdx.x % tiles_b) * adj::kTB;
+  const int t = threadIdx.x;
+  adj::tile_tc(c, A, L, a0, b0, t);
+  __syncthreads();
+  adj::PredOut o;
+  const bool put = t < adj::kNP && adj::tile_pred(c, A, L, a0, b0, t, o);
+  __syncthreads();
+  if (put) adj::tile_pred_put(L, t, o);
+  __syncthreads();
+  if (t < adj::kNO) adj::tile_prim(c, A, L, a0, b0, t, nu_a);
 }
 
 // out[0] += s_mu * sum(MU) + s_K * sum(KB); one block, fixed order
@@ -188,26 +229,39 @@ hipError_t launch_adj_fw(int axis, const AC& c0, const Arr& A, const Shared* sh,
   c.iha = axis == 0 ? c.ihx : c.ihz;
   const unsigned g = blocks_for(c.cnt, kBlk);
   if (axis == 0)
-    adj_stage<kFwAll, 0><<<g, kBlk, 0, s>>>(c, A, sh);
+    adj_fw_kernel<0><<<g, kBlk, 0, s>>>(c, A, sh);
   else
-    adj_stage<kFwAll, 2><<<g, kBlk, 0, s>>>(c, A, sh);
+    adj_fw_kernel<2><<<g, kBlk, 0, s>>>(c, A, sh);
   return hipGetLastError();
 }
 
-hipError_t launch_adj_rev(int axis, const AC& c0, const Arr& A, const Shared* sh,
-                          hipStream_t s) {
+hipError_t launch_adj_rev(int axis, const AC& c0, const Arr& A, const Shared* sh, double nu_w,
+                          double eps, int next_axis, const Arr& F, hipStream_t s) {
+  const double nu_a = nu_w == 0.0 ? 0.0 : nu_w * (-0.5 / eps);
   AC c = c0;
   c.axis = axis;
   c.iha = axis == 0 ? c.ihx : c.ihz;
-  const unsigned g = blocks_for(c.cnt, kBlk);
+  const int na = axis == 0 ? c.nx : c.nz, nb = axis == 0 ? c.nz : c.nx;
+  const int ta = (na + adj::kTA - 1) / adj::kTA, tb = (nb + adj::kTB - 1) / adj::kTB;
+  const int nt = ta * tb;
+  // forward-value blocks: up to 128, a node per thread and round
+  const long long fwb = (c.cnt + adj::kNT - 1) / adj::kNT;
+  const int nf = next_axis < 0 ? 0 : (int)(fwb < 128 ? fwb : 128);
+  const unsigned g = (unsigned)(nt + nf);
   if (axis == 0) {
-    adj_stage<kRvTc, 0><<<g, kBlk, 0, s>>>(c, A, sh);
-    adj_stage<kRvPred, 0><<<g, kBlk, 0, s>>>(c, A, sh);
-    adj_stage<kRvPrim, 0><<<g, kBlk, 0, s>>>(c, A, sh);
+    if (next_axis == 2)
+      adj_rev_fused<0, 2><<<g, adj::kNT, 0, s>>>(c, A, sh, tb, nt, nu_a, F);
+    else if (next_axis == 0)
+      adj_rev_fused<0, 0><<<g, adj::kNT, 0, s>>>(c, A, sh, tb, nt, nu_a, F);
+    else
+      adj_rev_fused<0, -1><<<g, adj::kNT, 0, s>>>(c, A, sh, tb, nt, nu_a, F);
   } else {
-    adj_stage<kRvTc, 2><<<g, kBlk, 0, s>>>(c, A, sh);
-    adj_stage<kRvPred, 2><<<g, kBlk, 0, s>>>(c, A, sh);
-    adj_stage<kRvPrim, 2><<<g, kBlk, 0, s>>>(c, A, sh);
+    if (next_axis == 0)
+      adj_rev_fused<2, 0><<<g, adj::kNT, 0, s>>>(c, A, sh, tb, nt, nu_a, F);
+    else if (next_axis == 2)
+      adj_rev_fused<2, 2><<<g, adj::kNT, 0, s>>>(c, A, sh, tb, nt, nu_a, F);
+    else
+      adj_rev_fused<2, -1><<<g, adj::kNT, 0, s>>>(c, A, sh, tb, nt, nu_a, F);
   }
   return hipGetLastError();
 }

@@ -1590,10 +1590,12 @@ int aerr(mtvd_adj* a, int code, const std::string& what) {
 
 constexpr size_t kFwDoubles = 13;   // P (4), S (1), XP (4), PP (4) per node
 
-// the forward-value arrays of operator q of an interval in buffer b
-void fw_slice(const mtvd_adj* a, int b, int q, adj::Arr* A) {
+// the forward-value arrays in ring slot b (operator q of an interval uses
+// slot q & 1: each reverse launch reads its own slot and fills the other
+// for the operator reversed after it)
+void fw_slice(const mtvd_adj* a, int b, adj::Arr* A) {
   const size_t one = (size_t)a->c.cnt;
-  double* base = a->fw[b] + kFwDoubles * one * (size_t)q;
+  double* base = a->fw[b];
   A->P = base;
   A->XP = base + 4 * one;
   A->PP = base + 8 * one;
@@ -1618,18 +1620,13 @@ size_t adj_layout(mtvd_adj* a, unsigned char* base) {
   for (int q = 0; q < 2; ++q) a->segs[q] = (double*)take(S * 4 * (size_t)a->every);
   for (int q = 0; q < 2; ++q) a->tmp[q] = (double*)take(S);
   for (int q = 0; q < 2; ++q) a->cot[q] = (double*)take(S);
-  // forward values (P, S, XP, PP: 13 doubles per node) of every operator of
-  // an interval, computed on the side stream after its recompute
-  for (int q = 0; q < 2; ++q)
-    a->fw[q] = (double*)take(kFwDoubles * one * 4 * (size_t)a->every);
+  // forward values (P, S, XP, PP: 13 doubles per node) of two operators:
+  // the one being reversed and the next
+  for (int q = 0; q < 2; ++q) a->fw[q] = (double*)take(kFwDoubles * one);
   adj::Arr& A = a->A;
   A.P = A.XP = A.PP = A.S = nullptr;   // set per operator (fw_slice)
-  A.XPb = (double*)take(S);
-  A.PPb = (double*)take(S);
-  A.PB = (double*)take(S);
-  A.DPb = (double*)take(5 * one);
-  A.DB = (double*)take(5 * one);
-  A.SB = (double*)take(one);
+  // the cotangent stages keep their intermediate values on chip
+  A.XPb = A.PPb = A.PB = A.DPb = A.DB = A.SB = nullptr;
   A.MU = (double*)take(one);
   A.KB = (double*)take(one);
   A.zr = a->zr;
@@ -1821,6 +1818,9 @@ int mtvd_adj_backward(mtvd_adj* a, double Jbar, double* grad_x0, double* grad_th
   // into segs[b] on the side stream while the main stream reverses the
   // segment after it from segs[b ^ 1]; events order each buffer's
   // recompute before its reverse and its reverse before its next recompute.
+  // The forward values an operator's reverse reads are filled by the
+  // reverse launch before it (launch_adj_rev's next operator), the
+  // segment's last operator's by a launch of their own.
   auto seg_len = [&](int seg) {
     const int s0 = seg * a->every;
     return (a->nsteps - s0 < a->every) ? a->nsteps - s0 : a->every;
@@ -1834,12 +1834,6 @@ int mtvd_adj_backward(mtvd_adj* a, double Jbar, double* grad_x0, double* grad_th
         const double* in = q == 0 ? base : a->segs[b] + S * (size_t)(q - 1);
         hipError_t e = launch_sweep_2d(o[s], a->c, a->sh, a->zr, 0, 0, false, in,
                                        a->segs[b] + S * (size_t)q, a->kc, a->side);
-        if (e != hipSuccess) return e;
-        // the operator's forward values, which need no cotangent
-        adj::Arr A = a->A;
-        A.X = in;
-        fw_slice(a, b, q, &A);
-        e = launch_adj_fw(o[s], a->ac, A, a->sh, a->side);
         if (e != hipSuccess) return e;
       }
     return hipEventRecord(a->rec_done[b], a->side);
@@ -1861,6 +1855,12 @@ int mtvd_adj_backward(mtvd_adj* a, double Jbar, double* grad_x0, double* grad_th
     const int m = seg_len(seg);
     double* base = a->ckpt + S * seg;
     auto state = [&](int q) -> double* { return q == 0 ? base : a->segs[b] + S * (size_t)(q - 1); };
+    {
+      adj::Arr A = a->A;
+      A.X = state(4 * m - 1);
+      fw_slice(a, (4 * m - 1) & 1, &A);
+      AHIP(a, launch_adj_fw(o[3], a->ac, A, a->sh, a->stream));
+    }
     for (int j = m - 1; j >= 0; --j) {
       const int n = s0 + j + 1;   // the step maps X_{n-1} to X_n
       if (n == a->nsteps) {
@@ -1868,16 +1868,26 @@ int mtvd_adj_backward(mtvd_adj* a, double Jbar, double* grad_x0, double* grad_th
         AHIP(a, launch_nu_vjp(a->ac, a->c, a->zr, state(4 * m), w, a->cot[cur], a->stream));
       }
       for (int s = 3; s >= 0; --s) {
+        const int q = 4 * j + s;
         adj::Arr A = a->A;
-        A.X = state(4 * j + s);
-        fw_slice(a, b, 4 * j + s, &A);
+        A.X = state(q);
+        fw_slice(a, q & 1, &A);
         A.Yb = a->cot[cur];
         A.Xb = a->cot[cur ^ 1];
-        AHIP(a, launch_adj_rev(o[s], a->ac, A, a->sh, a->stream));
+        // the step's first operator reads the state X_{n-1}: its reverse
+        // also adds the objective's cotangent at X_{n-1} (none at X_0)
+        const double nu_w = (s == 0 && n - 1 >= 1) ? w : 0.0;
+        // and fills the forward values of operator q - 1 of the segment
+        adj::Arr F = a->A;
+        int next_axis = -1;
+        if (q >= 1) {
+          F.X = state(q - 1);
+          fw_slice(a, (q - 1) & 1, &F);
+          next_axis = o[(q - 1) & 3];
+        }
+        AHIP(a, launch_adj_rev(o[s], a->ac, A, a->sh, nu_w, a->c.eps, next_axis, F, a->stream));
         cur ^= 1;
       }
-      if (n - 1 >= 1)
-        AHIP(a, launch_nu_vjp(a->ac, a->c, a->zr, state(4 * j), w, a->cot[cur], a->stream));
     }
     AHIP(a, hipEventRecord(a->rev_done[b], a->stream));
   }

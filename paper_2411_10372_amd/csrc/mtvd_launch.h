@@ -31,11 +31,16 @@ hipError_t launch_sweep_3d(int axis, const Coef& c, Shared* sh, const double* zr
 
 // reverse of one 2D operator L_axis(dt_frozen/2) at A.X, in two parts:
 // launch_adj_fw fills the forward values A.P, A.S, A.XP, A.PP of A.X (it
-// needs no cotangent, so it can run ahead); launch_adj_rev then takes
-// A.Xb = J^T A.Yb, and A.MU and A.KB accumulate the mu and K cotangents
+// needs no cotangent); launch_adj_rev then takes A.Xb = J^T A.Yb + nu_w
+// dNu_mean/dX (A.X) (nu_w = 0: no objective term; eps: the Nusselt
+// number's eps), and A.MU and A.KB accumulate the mu and K cotangents.
+// With next_axis >= 0 the same launch also fills the forward values of the
+// operator reversed next (axis next_axis, state F.X) into F.P, F.S, F.XP,
+// F.PP, which must not alias A's.
 hipError_t launch_adj_fw(int axis, const adj::AC& c, const adj::Arr& A, const Shared* sh,
                          hipStream_t s);
 hipError_t launch_adj_rev(int axis, const adj::AC& c, const adj::Arr& A, const Shared* sh,
+                          double nu_w, double eps, int next_axis, const adj::Arr& F,
                           hipStream_t s);
 hipError_t launch_fill(double* a, long long n, double v, hipStream_t s);
 hipError_t launch_ra_reduce(long long cnt, const double* MU, const double* KB, double s_mu,
