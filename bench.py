@@ -35,10 +35,10 @@ def log(*a):
 
 
 # the files a sweep kernel's binary and launch shape depend on (the build
-# script holds its compiler flags, the API source the default rows per wave)
-KERNEL_SOURCES = {2: ("mtvd_2d.hip", "mtvd_device.h", "mtvd_api.hip", "../build.py"),
+# script holds its compiler flags, mtvd_rows.h the default rows per wave)
+KERNEL_SOURCES = {2: ("mtvd_2d.hip", "mtvd_device.h", "mtvd_rows.h", "../build.py"),
                   3: ("mtvd_3d.h", "mtvd_3d_x.hip", "mtvd_3d_y.hip", "mtvd_3d_z.hip",
-                      "mtvd_device.h", "mtvd_api.hip", "../build.py")}
+                      "mtvd_device.h", "mtvd_rows.h", "../build.py")}
 
 
 def source_hash(files=None) -> str:
