@@ -22,8 +22,12 @@ Parity status of each function (what pins it is in ``tests/test_oracle_*``):
   sweep x/y/z, step -- pinned (linear acoustics/viscous/thermal amplification
                        in closed form, conservation, symmetries, hydrostatic
                        convergence, second-order self-convergence)
-  TVD limiter form  -- parity unpinned beyond its properties (conservative,
-                       zero on linear data, no new extrema at a contact)
+  TVD term          -- pinned for both limiter forms (closed forms at an
+                       isolated spike, phi = 0, and inside the limiter's ramp,
+                       0 < phi < 1, with the face Co from the larger |u|+c;
+                       zero on linear data; conservative; no new extrema at
+                       a contact for the Davis form).  Which form the paper
+                       means is a reading (A4), not a pin.
   diag              -- pinned (conduction Nu = 1, closed-form sums)
   init_theta        -- pinned (equals init without noise at theta = 0; T of
                        interior nodes recovered as T0 + theta)

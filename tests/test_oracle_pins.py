@@ -547,6 +547,50 @@ def test_tvd_term_at_an_isolated_spike(ora):
     assert np.all((Y1 - Y0)[:3] == 0)
 
 
+@pytest.mark.parametrize("lf", [0, 1])
+def test_tvd_term_inside_the_limiter_ramp(ora, lf):
+    """Energy jumps (a, b, a) s on three consecutive faces, nothing else
+    varying: at the middle face r+ = r- = a/b, at the outer two one ratio is
+    0 and the other b/a.  Printed form (limiter argument r+ + r-): the middle
+    face has phi = 4a/b = 0.4 (the ramp of phi), G = C/2 (1 - 0.4); the
+    outer faces phi = 1, G = 0.  Davis form G(r+) + G(r-): the middle face
+    2 x C/2 (1 - 2a/b), each outer face C/2 (from its zero ratio).  C of a
+    face = Co(1 - Co), Co = (tau/dx) max(c) over its two nodes (at rest)."""
+    p = Params(nx=32, nz=3, gravity_scale=0.0, diffusion_scale=0.0, noise_amp=0.0,
+               limiter_form=lf)
+    X = uniform_state(p, 1.0, np.array([0.0, 0.0]), 0.75)
+    s, a, b = 0.2, 0.1, 1.0
+    X[3, 1, 16:] += a * s
+    X[3, 1, 17:] += b * s
+    X[3, 1, 18:] += a * s
+    X[3, 1, 26:] -= (2 * a + b) * s          # back down far away (periodic x)
+    tau = 0.5 * ora.dt(p, X)
+    Y1 = ora.sweep(p, 0, tau, X)
+    Y0 = ora.sweep(Params(**{**p.__dict__, "tvd_on": 0}), 0, tau, X)
+    d = (Y1 - Y0)[3, 1]
+    cv = cv_of(p)
+    ca = (p.gamma - 1) / (p.gamma * p.eps * p.D)
+    c = np.sqrt(p.gamma * ca * (X[3, 1] / X[0, 1]) / cv)
+    lam = tau / (p.aspect / p.nx)
+
+    def C(k):                                  # face k + 1/2
+        Co = lam * max(c[k], c[k + 1])
+        assert Co <= 0.5
+        return Co * (1 - Co)
+
+    if lf == 0:
+        D15, D16, D17 = 0.0, 0.5 * C(16) * (1 - 4 * a / b) * b * s, 0.0
+    else:
+        D15 = 0.5 * C(15) * a * s
+        D16 = 2 * 0.5 * C(16) * (1 - 2 * a / b) * b * s
+        D17 = 0.5 * C(17) * a * s
+    want = {15: D15, 16: D16 - D15, 17: D17 - D16, 18: -D17}
+    for j, v in want.items():
+        assert abs(d[j] - v) < 1e-14, (j, d[j], v)
+    assert np.all(d[3:15] == 0) and np.all(d[19:24] == 0)
+    assert np.all((Y1 - Y0)[:3] == 0)
+
+
 def test_tvd_term_vanishes_on_linear_data(ora):
     """Linear data: every ratio is 1, r+ + r- = 2, phi = 1, G = 0."""
     p = Params(nx=12, nz=5, gravity_scale=0.0, Ra=1e4, noise_amp=0.0)
