@@ -99,6 +99,27 @@ def test_gradient_matches_oracle_complex_step(grid):
         assert abs((jp - jm) / (2 * H) - ad) <= 1e-6 * gn
 
 
+@pytest.mark.parametrize("knob", [dict(sweep_order=1), dict(wall_order=1), dict(tvd_on=0)])
+def test_gradient_with_reading_knobs_matches_oracle_complex_step(knob):
+    """The reading knobs the adjoint accepts: the symmetric split order
+    (whose reverse pairs operators of the same axis), first-order plate
+    derivatives, the step without its TVD term."""
+    gpu_or_skip()
+    import paper_2411_10372_amd as mtvd
+    _say("gradient with", knob)
+    po, pg, th, X0, dt = _setup({**SMALL, **knob}, 0.05)
+    a = mtvd.Adjoint(pg, N_SMALL, EVERY_SMALL)
+    a.forward(th, dt)
+    g, _, _ = a.backward(1.0)
+    g = g.cpu().numpy()
+    gn = float(np.sqrt(np.sum(g * g)))
+    for v in unit_directions(po.nz, po.nx, 2, seed=6):
+        _, d = oracle.time_avg_nu_cs(po, X0, oracle.theta_direction(po, X0, v), N_SMALL, dt)
+        ad = float(np.sum(g * v))
+        _say("complex step", d, "adjoint", ad, "err/|g|", abs(d - ad) / gn)
+        assert abs(d - ad) <= _cs_bar(gn), (d, ad, gn)
+
+
 def _coef_bar(po, dmu, dK):
     # d/dRa = dJ/dmu* dmu*/dRa + dJ/dK* dK*/dRa can cancel; its error is
     # bounded by the same relative error on the scale of the two parts
