@@ -1499,6 +1499,11 @@ const char* mtvd_batch_last_error(const mtvd_batch* b) { return b ? b->err.c_str
 // time with the forward kernels, keeping every operator's input, and runs
 // the operators' reverses from the last step to the first.
 
+// events in each of the forward pass's two rings (more than the batches in
+// flight, so that a wait always finds the record it means)
+constexpr int kNuEvents = 8;
+static_assert(kNuEvents > 4, "the forward pass keeps up to 4 batches in flight");
+
 struct mtvd_adj {
   mtvd_params p;
   Coef c;                 // dt_mode = 1
@@ -1509,7 +1514,7 @@ struct mtvd_adj {
   hipEvent_t rec_done[2], rev_done[2];
   // forward pass: a batch of steps done on the stream / its objective terms
   // added on the side stream (rings of kNuEvents)
-  hipEvent_t fwd_done[8], nu_done[8];
+  hipEvent_t fwd_done[kNuEvents], nu_done[kNuEvents];
   unsigned char* ws;
   double *zr, *acc, *ckpt, *segs[2], *fw[2], *tmp[2], *cot[2];
   Shared* sh;
@@ -1675,13 +1680,13 @@ int mtvd_adj_create(const mtvd_params* p, int32_t nsteps, int32_t every, void* h
   a->stream = (hipStream_t)hip_stream;
   a->side = nullptr;
   for (int q = 0; q < 2; ++q) a->rec_done[q] = a->rev_done[q] = nullptr;
-  for (int q = 0; q < 8; ++q) a->fwd_done[q] = a->nu_done[q] = nullptr;
+  for (int q = 0; q < kNuEvents; ++q) a->fwd_done[q] = a->nu_done[q] = nullptr;
   // default priority, as the caller's stream; events without timing
   bool ok = hipStreamCreateWithFlags(&a->side, hipStreamNonBlocking) == hipSuccess;
   for (int q = 0; q < 2 && ok; ++q)
     ok = hipEventCreateWithFlags(&a->rec_done[q], hipEventDisableTiming) == hipSuccess &&
          hipEventCreateWithFlags(&a->rev_done[q], hipEventDisableTiming) == hipSuccess;
-  for (int q = 0; q < 8 && ok; ++q)
+  for (int q = 0; q < kNuEvents && ok; ++q)
     ok = hipEventCreateWithFlags(&a->fwd_done[q], hipEventDisableTiming) == hipSuccess &&
          hipEventCreateWithFlags(&a->nu_done[q], hipEventDisableTiming) == hipSuccess;
   if (!ok) {
@@ -1744,28 +1749,28 @@ int mtvd_adj_forward(mtvd_adj* a, const double* theta, double dt, double* J, dou
   // than the ring's traffic to memory.
   const int R = 4 * a->every;
   const int K = R / 2 < 25 ? (R / 2 < 1 ? 1 : R / 2) : 25;
-  const int D = R / K < 4 ? R / K : 4;               // batches in flight; < 8 events
+  const int D = R / K < 4 ? R / K : 4;               // batches in flight, < kNuEvents
   auto state_out = [&](int n) -> double* {           // X_{n+1}
     const int nn = n + 1;
     if (nn % a->every == 0 && nn / a->every < a->nseg) return a->ckpt + S * (nn / a->every);
     return a->segs[0] + S * (size_t)(n % R);
   };
-  AHIP(a, hipEventRecord(a->fwd_done[7], a->stream));
-  AHIP(a, hipStreamWaitEvent(a->side, a->fwd_done[7], 0));   // after the fill above
+  AHIP(a, hipEventRecord(a->fwd_done[kNuEvents - 1], a->stream));
+  AHIP(a, hipStreamWaitEvent(a->side, a->fwd_done[kNuEvents - 1], 0));   // after the fill above
   const double* in = a->ckpt;
   for (int m = 0, n0 = 0; n0 < a->nsteps; ++m, n0 += K) {
     const int n1 = n0 + K < a->nsteps ? n0 + K : a->nsteps;
-    if (m >= D) AHIP(a, hipStreamWaitEvent(a->stream, a->nu_done[(m - D) % 8], 0));
+    if (m >= D) AHIP(a, hipStreamWaitEvent(a->stream, a->nu_done[(m - D) % kNuEvents], 0));
     for (int n = n0; n < n1; ++n) {
       double* out = state_out(n);
       AHIP(a, adj_fwd_step(a, in, out));
       in = out;
     }
-    AHIP(a, hipEventRecord(a->fwd_done[m % 8], a->stream));
-    AHIP(a, hipStreamWaitEvent(a->side, a->fwd_done[m % 8], 0));
+    AHIP(a, hipEventRecord(a->fwd_done[m % kNuEvents], a->stream));
+    AHIP(a, hipStreamWaitEvent(a->side, a->fwd_done[m % kNuEvents], 0));
     for (int n = n0; n < n1; ++n)
       AHIP(a, launch_nu_obj(a->c, a->zr, state_out(n), w, a->acc, a->side));
-    AHIP(a, hipEventRecord(a->nu_done[m % 8], a->side));
+    AHIP(a, hipEventRecord(a->nu_done[m % kNuEvents], a->side));
   }
   AHIP(a, hipEventRecord(a->nu_done[0], a->side));
   AHIP(a, hipStreamWaitEvent(a->stream, a->nu_done[0], 0));
@@ -1910,7 +1915,7 @@ int mtvd_adj_destroy(mtvd_adj* a) {
     if (a->rec_done[q]) (void)hipEventDestroy(a->rec_done[q]);
     if (a->rev_done[q]) (void)hipEventDestroy(a->rev_done[q]);
   }
-  for (int q = 0; q < 8; ++q) {
+  for (int q = 0; q < kNuEvents; ++q) {
     if (a->fwd_done[q]) (void)hipEventDestroy(a->fwd_done[q]);
     if (a->nu_done[q]) (void)hipEventDestroy(a->nu_done[q]);
   }
