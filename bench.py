@@ -286,6 +286,8 @@ def bench_adjoint(args):
     wl = WORKLOADS[args.workload]
     p = mtvd.Params(**params_dict(args.workload))
     N, E = wl["steps"], wl["adjoint_every"]
+    if args.adjoint_steps:          # a shorter gradient (counter runs)
+        N = args.adjoint_steps
     reps = max(1, min(args.steps, 10))
     torch.cuda.set_device(0)
     rng = np.random.default_rng(wl["theta_seed"])
@@ -355,6 +357,9 @@ def main():
                     help="also run a plain 256 MiB device copy (reference for HBM counters)")
     ap.add_argument("--rows", type=int, nargs=2, default=None,
                     help="rows per wave for the x and z sweeps (default: library choice)")
+    ap.add_argument("--adjoint-steps", type=int, default=0,
+                    help="adjoint workload: steps per gradient instead of the workload's "
+                         "(for profiling runs; the reported value is then of that shorter run)")
     ap.add_argument("--batch-rows", default=None,
                     help='batch: rows per wave per box size as JSON, e.g. '
                          '\'{"128x32": [4, 32], ...}\' (default: run the autotuner)')
