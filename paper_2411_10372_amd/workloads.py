@@ -24,6 +24,12 @@ WORKLOADS = {
     # the same on the tanh-stretched z grid, s = 1.2
     "3d_1024x1024x256_ra1e9_tanh1.2": dict(COMMON, ndim=3, nx=1024, ny=1024, nz=256, Ra=1e9,
                                            seed=2, steps=200, stretch=1.2),
+    # one GPU's share of the 1024 x 1024 x 256 box on eight: an x slab of 128
+    # columns plus the 2 halo columns on each side that its sweeps read, run
+    # as a periodic box of that shape (its cells are wider in x than the full
+    # box's; a step's cost does not depend on the cell sizes)
+    "3d_slab132x1024x256_ra1e9": dict(COMMON, ndim=3, nx=132, ny=1024, nz=256, Ra=1e9,
+                                      seed=2, steps=200),
     # 2D 512 x 128, Ra 1e7, 500 steps, dt frozen: the adjoint case
     "2d_512x128_ra1e7": dict(COMMON, ndim=2, nx=512, ny=1, nz=128, Ra=1e7, seed=4, steps=500,
                              dt_mode=1),
