@@ -14,6 +14,11 @@ WORKLOADS = {
     # 2D 4096 x 1024, Ra 1e10, 1000 steps, diagnostics every 100: the benchmark case
     "2d_4096x1024_ra1e10": dict(COMMON, ndim=2, nx=4096, ny=1, nz=1024, Ra=1e10, seed=1,
                                 steps=1000, diag_every=100),
+    # one GPU's share of it on eight: a 512-column slab plus the 6 halo
+    # columns on each side that one exchange per step needs (z, x, z, x read
+    # 1 + 2 + 1 + 2), run as a periodic box of that shape
+    "2d_slab524x1024_ra1e10": dict(COMMON, ndim=2, nx=524, ny=1, nz=1024, Ra=1e10, seed=1,
+                                   steps=1000, diag_every=100),
     # the same on the tanh-stretched z grid, s = 1.2 (the plate cells are
     # 2s/sinh(2s) = 0.44 of the uniform spacing)
     "2d_4096x1024_ra1e10_tanh1.2": dict(COMMON, ndim=2, nx=4096, ny=1, nz=1024, Ra=1e10,
